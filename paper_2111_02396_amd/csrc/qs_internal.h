@@ -1,0 +1,74 @@
+// Internal interface between the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qs {
+
+constexpr int kMaxGateQubits = 5;
+constexpr int kMaxChannelQubits = 2;
+constexpr int kMaxQubits = 34;
+
+// Threads per workgroup of the streaming kernels (four wave64 wavefronts).
+constexpr int kBlock = 256;
+
+// Reduction partial buffers hold at most this many workgroups' results.
+constexpr int kMaxReduceBlocks = 2048;
+// Widest per-workgroup reduction record: the 4x4 complex two-qubit
+// reduced density matrix (32 doubles) plus two scalars.
+constexpr int kMaxReduceWidth = 34;
+
+// Sampling blocks hold 2^kSampleBlockBits amplitudes.
+constexpr int kSampleBlockBits = 10;
+
+// A fused gate as the kernels see it: targets ascending, matrix rows and
+// columns in that ascending-target bit order, complex64.
+struct GateDesc {
+    int k;
+    int t[kMaxGateQubits];
+    float2 m[32 * 32];  // leading (2^k)^2 entries used, row-major
+};
+
+struct ReadoutDesc {
+    int enabled;
+    double e0[kMaxQubits];  // P(read 1 | 0)
+    double e1[kMaxQubits];  // P(read 0 | 1)
+};
+
+// All launchers enqueue on `st` and return the launch status.
+
+hipError_t launch_set_basis(float2 *amp, int n, uint64_t index, hipStream_t st);
+
+hipError_t launch_scale(float2 *amp, int n, float s, hipStream_t st);
+
+// Algorithm 1 for one fused gate.  mat_dev: device copy of g.m, required
+// when g.k == 5 (too large for kernel arguments), ignored otherwise.
+hipError_t launch_apply_gate(float2 *amp, int n, const GateDesc &g, const float2 *mat_dev,
+                             hipStream_t st);
+
+// FP64 reductions with a fixed tree.  Each writes `width` doubles to out_dev.
+// norm: width 1 (sum |psi|^2).
+hipError_t launch_norm(const float2 *amp, int n, double *partials, double *out_dev,
+                       hipStream_t st);
+
+// Reduced density matrix R = sum_groups v v^dag over k <= 2 ascending
+// targets: width 2*4^k doubles, R[j][l] at (2*(j*D+l), +1).
+hipError_t launch_rdm(const float2 *amp, int n, int k, const int *t_sorted, double *partials,
+                      double *out_dev, hipStream_t st);
+
+// Conventional-method trial: out = M in (k <= 2), with sum |out|^2 and
+// sum |in|^2 in one pass: width 2.
+hipError_t launch_apply_copy_norm(const float2 *in, float2 *out, int n, const GateDesc &g,
+                                  double *partials, double *out_dev, hipStream_t st);
+
+int reduce_blocks_for(int n, int k);
+
+// Sampling: block sums, a single-workgroup scan, then one thread per sample.
+// sums / incl: device doubles [2^(n - B)] with B = min(n, kSampleBlockBits).
+hipError_t launch_sample(const float2 *amp, int n, double *sums, double *incl,
+                         uint64_t seed, uint32_t traj, uint32_t circ, int n_samples,
+                         const ReadoutDesc &ro, uint64_t *out_dev, double *norm_dev,
+                         hipStream_t st);
+
+}  // namespace qs

@@ -1,0 +1,487 @@
+// gfx950 kernels for the state-vector hot path.
+//
+//  * gate application (Section 3.1, Algorithm 1): one 2^k-amplitude index
+//    group per work-item; consecutive work-items own consecutive groups, so
+//    with the target bits removed the loads of a wavefront are contiguous;
+//    the fused matrix travels in the kernel arguments (k <= 4, read through
+//    scalar loads) or in device memory (k = 5);
+//  * FP64 reductions (norm, two-qubit reduced density matrix, the
+//    conventional method's trial norm) with a fixed grid and a fixed
+//    butterfly/tree order, so results are bit-identical run to run;
+//  * measurement sampling: FP64 block sums, one-workgroup scan, one
+//    work-item per sample with Philox draws.
+#include <hip/hip_runtime.h>
+
+#include "qs_internal.h"
+#include "qs_philox.h"
+
+namespace qs {
+namespace {
+
+template <int K>
+struct GateArgs {
+    float2 m[(1 << K) * (1 << K)];
+    int t[K];
+};
+
+struct TargetArgs {
+    int t[kMaxGateQubits];
+};
+
+// Insert a zero bit at each ascending target position.
+template <int K, typename Idx>
+__device__ __forceinline__ Idx spread_index(Idx g, const int *t) {
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+        const int q = t[b];
+        const Idx low = g & ((Idx(1) << q) - Idx(1));
+        g = ((g >> q) << (q + 1)) | low;
+    }
+    return g;
+}
+
+template <int K, typename Idx>
+__device__ __forceinline__ Idx local_offset(int j, const int *t) {
+    Idx off = 0;
+#pragma unroll
+    for (int b = 0; b < K; ++b)
+        if ((j >> b) & 1) off |= Idx(1) << t[b];
+    return off;
+}
+
+__device__ __forceinline__ float2 cmac(float2 acc, float2 a, float2 b) {
+    acc.x = fmaf(a.x, b.x, acc.x);
+    acc.x = fmaf(-a.y, b.y, acc.x);
+    acc.y = fmaf(a.x, b.y, acc.y);
+    acc.y = fmaf(a.y, b.x, acc.y);
+    return acc;
+}
+
+// ---------------------------------------------------------------- gates
+
+template <int K, typename Idx>
+__global__ __launch_bounds__(kBlock) void apply_gate_args(float2 *__restrict__ amp, Idx groups,
+                                                          GateArgs<K> a) {
+    constexpr int D = 1 << K;
+    const Idx stride = Idx(gridDim.x) * Idx(kBlock);
+    for (Idx g = Idx(blockIdx.x) * Idx(kBlock) + Idx(threadIdx.x); g < groups; g += stride) {
+        const Idx base = spread_index<K, Idx>(g, a.t);
+        float2 v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = amp[base + local_offset<K, Idx>(j, a.t)];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc = cmac(acc, a.m[j * D + l], v[l]);
+            amp[base + local_offset<K, Idx>(j, a.t)] = acc;
+        }
+    }
+}
+
+// k = 5: the 32x32 matrix (8 KiB) is staged once per workgroup in LDS and
+// read with wave-uniform addresses (broadcast).
+template <typename Idx>
+__global__ __launch_bounds__(kBlock) void apply_gate5_lds(float2 *__restrict__ amp, Idx groups,
+                                                          const float2 *__restrict__ mat,
+                                                          TargetArgs ta) {
+    constexpr int K = 5, D = 32;
+    __shared__ float2 sm[D * D];
+    for (int i = threadIdx.x; i < D * D; i += kBlock) sm[i] = mat[i];
+    __syncthreads();
+    const Idx stride = Idx(gridDim.x) * Idx(kBlock);
+    for (Idx g = Idx(blockIdx.x) * Idx(kBlock) + Idx(threadIdx.x); g < groups; g += stride) {
+        const Idx base = spread_index<K, Idx>(g, ta.t);
+        float2 v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = amp[base + local_offset<K, Idx>(j, ta.t)];
+#pragma unroll 4
+        for (int j = 0; j < D; ++j) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc = cmac(acc, sm[j * D + l], v[l]);
+            amp[base + local_offset<K, Idx>(j, ta.t)] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- utility
+
+template <typename Idx>
+__global__ __launch_bounds__(kBlock) void set_basis(float2 *__restrict__ amp, Idx dim, Idx index) {
+    const Idx stride = Idx(gridDim.x) * Idx(kBlock);
+    for (Idx i = Idx(blockIdx.x) * Idx(kBlock) + Idx(threadIdx.x); i < dim; i += stride)
+        amp[i] = make_float2(i == index ? 1.f : 0.f, 0.f);
+}
+
+template <typename Idx>
+__global__ __launch_bounds__(kBlock) void scale_state(float2 *__restrict__ amp, Idx dim, float s) {
+    const Idx stride = Idx(gridDim.x) * Idx(kBlock);
+    for (Idx i = Idx(blockIdx.x) * Idx(kBlock) + Idx(threadIdx.x); i < dim; i += stride) {
+        float2 v = amp[i];
+        amp[i] = make_float2(v.x * s, v.y * s);
+    }
+}
+
+// ---------------------------------------------------------------- reductions
+
+// Fixed-order workgroup sum of W per-thread values; thread 0 writes them.
+template <int W>
+__device__ __forceinline__ void block_sum_write(double (&vals)[W], double *__restrict__ dst) {
+    __shared__ double red[kBlock / 64][W];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        double x = vals[w];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+        vals[w] = x;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) red[wave][w] = vals[w];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            double s = red[0][w];
+#pragma unroll
+            for (int i = 1; i < kBlock / 64; ++i) s += red[i][w];
+            dst[w] = s;
+        }
+    }
+}
+
+template <typename Idx>
+__global__ __launch_bounds__(kBlock) void norm_partials(const float2 *__restrict__ amp, Idx dim,
+                                                        double *__restrict__ partials) {
+    double acc[1] = {0.0};
+    const Idx stride = Idx(gridDim.x) * Idx(kBlock);
+    for (Idx i = Idx(blockIdx.x) * Idx(kBlock) + Idx(threadIdx.x); i < dim; i += stride) {
+        const float2 v = amp[i];
+        const double re = v.x, im = v.y;
+        acc[0] = fma(re, re, fma(im, im, acc[0]));
+    }
+    block_sum_write<1>(acc, partials + blockIdx.x);
+}
+
+template <int K, typename Idx>
+__global__ __launch_bounds__(kBlock) void rdm_partials(const float2 *__restrict__ amp, Idx groups,
+                                                       TargetArgs ta,
+                                                       double *__restrict__ partials) {
+    constexpr int D = 1 << K;
+    constexpr int W = 2 * D * D;
+    double acc[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] = 0.0;
+    const Idx stride = Idx(gridDim.x) * Idx(kBlock);
+    for (Idx g = Idx(blockIdx.x) * Idx(kBlock) + Idx(threadIdx.x); g < groups; g += stride) {
+        const Idx base = spread_index<K, Idx>(g, ta.t);
+        double vr[D], vi[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            const float2 v = amp[base + local_offset<K, Idx>(j, ta.t)];
+            vr[j] = v.x;
+            vi[j] = v.y;
+        }
+        // R[j][l] += v_j conj(v_l)
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+                acc[2 * (j * D + l)] = fma(vr[j], vr[l], fma(vi[j], vi[l], acc[2 * (j * D + l)]));
+                acc[2 * (j * D + l) + 1] =
+                    fma(vi[j], vr[l], fma(-vr[j], vi[l], acc[2 * (j * D + l) + 1]));
+            }
+    }
+    block_sum_write<W>(acc, partials + size_t(blockIdx.x) * W);
+}
+
+template <int K, typename Idx>
+__global__ __launch_bounds__(kBlock) void apply_copy_norm(const float2 *__restrict__ in,
+                                                          float2 *__restrict__ out, Idx groups,
+                                                          GateArgs<K> a,
+                                                          double *__restrict__ partials) {
+    constexpr int D = 1 << K;
+    double acc[2] = {0.0, 0.0};
+    const Idx stride = Idx(gridDim.x) * Idx(kBlock);
+    for (Idx g = Idx(blockIdx.x) * Idx(kBlock) + Idx(threadIdx.x); g < groups; g += stride) {
+        const Idx base = spread_index<K, Idx>(g, a.t);
+        float2 v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            v[j] = in[base + local_offset<K, Idx>(j, a.t)];
+            acc[1] = fma(double(v[j].x), double(v[j].x), fma(double(v[j].y), double(v[j].y), acc[1]));
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            float2 w = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int l = 0; l < D; ++l) w = cmac(w, a.m[j * D + l], v[l]);
+            out[base + local_offset<K, Idx>(j, a.t)] = w;
+            acc[0] = fma(double(w.x), double(w.x), fma(double(w.y), double(w.y), acc[0]));
+        }
+    }
+    block_sum_write<2>(acc, partials + size_t(blockIdx.x) * 2);
+}
+
+// Sum `count` records of `width` doubles in a fixed order (one workgroup).
+__global__ __launch_bounds__(kBlock) void reduce_records(const double *__restrict__ partials,
+                                                         int count, int width,
+                                                         double *__restrict__ out) {
+    __shared__ double red[kBlock];
+    for (int w = 0; w < width; ++w) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < count; i += kBlock) s += partials[size_t(i) * width + w];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = kBlock / 2; h >= 1; h >>= 1) {
+            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[w] = red[0];
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- sampling
+
+// One workgroup per sampling block of 2^B amplitudes.
+template <typename Idx>
+__global__ __launch_bounds__(kBlock) void sample_block_sums(const float2 *__restrict__ amp, int B,
+                                                            double *__restrict__ sums) {
+    const Idx first = Idx(blockIdx.x) << B;
+    const int len = 1 << B;
+    double acc[1] = {0.0};
+    for (int i = threadIdx.x; i < len; i += kBlock) {
+        const float2 v = amp[first + Idx(i)];
+        acc[0] = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), acc[0]));
+    }
+    block_sum_write<1>(acc, sums + blockIdx.x);
+}
+
+// Inclusive prefix over nb block sums: each thread scans a contiguous chunk
+// sequentially; chunk bases come from one sequential pass over the chunk
+// totals.  Writes the total to *norm.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void sample_scan(const double *__restrict__ sums,
+                                                            int64_t nb, double *__restrict__ incl,
+                                                            double *__restrict__ norm) {
+    __shared__ double part[kScanThreads];
+    const int64_t chunk = (nb + kScanThreads - 1) / kScanThreads;
+    const int64_t lo = int64_t(threadIdx.x) * chunk;
+    const int64_t hi = lo + chunk < nb ? lo + chunk : nb;
+    double s = 0.0;
+    for (int64_t b = lo; b < hi; ++b) s += sums[b];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double run = 0.0;
+        for (int i = 0; i < kScanThreads; ++i) {
+            const double v = part[i];
+            part[i] = run;
+            run += v;
+        }
+        *norm = run;
+    }
+    __syncthreads();
+    double run = part[threadIdx.x];
+    for (int64_t b = lo; b < hi; ++b) {
+        run += sums[b];
+        incl[b] = run;
+    }
+}
+
+template <typename Idx>
+__global__ __launch_bounds__(kBlock) void sample_draw(const float2 *__restrict__ amp, int n, int B,
+                                                      const double *__restrict__ incl, int64_t nb,
+                                                      const double *__restrict__ norm,
+                                                      uint64_t seed, uint32_t traj, uint32_t circ,
+                                                      int n_samples, ReadoutDesc ro,
+                                                      uint64_t *__restrict__ out) {
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s >= n_samples) return;
+    const double N = *norm;
+    const double target = philox_uniform(seed, uint32_t(s), traj, circ, kStreamMeasure) * N;
+    // smallest block b with target < incl[b]
+    int64_t lo = 0, hi = nb;
+    while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (target < incl[mid]) hi = mid; else lo = mid + 1;
+    }
+    uint64_t x;
+    if (lo >= nb) {
+        x = (uint64_t(1) << n) - 1;
+    } else {
+        double acc = lo > 0 ? incl[lo - 1] : 0.0;
+        const Idx first = Idx(lo) << B;
+        const int len = 1 << B;
+        int pick = len - 1;
+        for (int i = 0; i < len; ++i) {
+            const float2 v = amp[first + Idx(i)];
+            acc += fma(double(v.x), double(v.x), double(v.y) * double(v.y));
+            if (target < acc) { pick = i; break; }
+        }
+        x = uint64_t(first) + uint64_t(pick);
+    }
+    if (ro.enabled) {
+        for (int q = 0; q < n; ++q) {
+            const int bit = int((x >> q) & 1u);
+            const double u = philox_uniform(seed, uint32_t(uint64_t(s) * uint64_t(n) + uint64_t(q)),
+                                            traj, circ, kStreamReadout);
+            if (u < (bit ? ro.e1[q] : ro.e0[q])) x ^= uint64_t(1) << q;
+        }
+    }
+    out[s] = x;
+}
+
+// ---------------------------------------------------------------- helpers
+
+inline unsigned grid_for(uint64_t work_items, unsigned cap = 1u << 20) {
+    uint64_t b = (work_items + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return unsigned(b);
+}
+
+template <int K>
+GateArgs<K> make_args(const GateDesc &g) {
+    GateArgs<K> a;
+    constexpr int D = 1 << K;
+    for (int i = 0; i < D * D; ++i) a.m[i] = g.m[i];
+    for (int b = 0; b < K; ++b) a.t[b] = g.t[b];
+    return a;
+}
+
+template <typename Idx>
+hipError_t apply_gate_idx(float2 *amp, int n, const GateDesc &g, const float2 *mat_dev,
+                          hipStream_t st) {
+    const Idx groups = Idx(1) << (n - g.k);
+    const unsigned grid = grid_for(uint64_t(groups));
+    switch (g.k) {
+        case 1: apply_gate_args<1, Idx><<<grid, kBlock, 0, st>>>(amp, groups, make_args<1>(g)); break;
+        case 2: apply_gate_args<2, Idx><<<grid, kBlock, 0, st>>>(amp, groups, make_args<2>(g)); break;
+        case 3: apply_gate_args<3, Idx><<<grid, kBlock, 0, st>>>(amp, groups, make_args<3>(g)); break;
+        case 4: apply_gate_args<4, Idx><<<grid, kBlock, 0, st>>>(amp, groups, make_args<4>(g)); break;
+        case 5: {
+            TargetArgs ta;
+            for (int b = 0; b < 5; ++b) ta.t[b] = g.t[b];
+            apply_gate5_lds<Idx><<<grid, kBlock, 0, st>>>(amp, groups, mat_dev, ta);
+            break;
+        }
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int reduce_blocks_for(int n, int k) {
+    // at least 4 groups per work-item; a fixed count per (n, k)
+    const uint64_t groups = uint64_t(1) << (n - k);
+    uint64_t b = groups / (4u * kBlock);
+    if (b < 1) b = 1;
+    if (b > kMaxReduceBlocks) b = kMaxReduceBlocks;
+    return int(b);
+}
+
+hipError_t launch_set_basis(float2 *amp, int n, uint64_t index, hipStream_t st) {
+    const uint64_t dim = uint64_t(1) << n;
+    const unsigned grid = grid_for(dim);
+    if (n <= 31)
+        set_basis<uint32_t><<<grid, kBlock, 0, st>>>(amp, uint32_t(dim), uint32_t(index));
+    else
+        set_basis<uint64_t><<<grid, kBlock, 0, st>>>(amp, dim, index);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(float2 *amp, int n, float s, hipStream_t st) {
+    const uint64_t dim = uint64_t(1) << n;
+    const unsigned grid = grid_for(dim);
+    if (n <= 31)
+        scale_state<uint32_t><<<grid, kBlock, 0, st>>>(amp, uint32_t(dim), s);
+    else
+        scale_state<uint64_t><<<grid, kBlock, 0, st>>>(amp, dim, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_gate(float2 *amp, int n, const GateDesc &g, const float2 *mat_dev,
+                             hipStream_t st) {
+    if (n <= 31) return apply_gate_idx<uint32_t>(amp, n, g, mat_dev, st);
+    return apply_gate_idx<uint64_t>(amp, n, g, mat_dev, st);
+}
+
+hipError_t launch_norm(const float2 *amp, int n, double *partials, double *out_dev,
+                       hipStream_t st) {
+    const int nb = reduce_blocks_for(n, 0);
+    const uint64_t dim = uint64_t(1) << n;
+    if (n <= 31)
+        norm_partials<uint32_t><<<nb, kBlock, 0, st>>>(amp, uint32_t(dim), partials);
+    else
+        norm_partials<uint64_t><<<nb, kBlock, 0, st>>>(amp, dim, partials);
+    reduce_records<<<1, kBlock, 0, st>>>(partials, nb, 1, out_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_rdm(const float2 *amp, int n, int k, const int *t_sorted, double *partials,
+                      double *out_dev, hipStream_t st) {
+    const int nb = reduce_blocks_for(n, k);
+    TargetArgs ta;
+    for (int b = 0; b < kMaxGateQubits; ++b) ta.t[b] = b < k ? t_sorted[b] : 0;
+    const uint64_t groups = uint64_t(1) << (n - k);
+    const int width = 2 << (2 * k);
+    if (k == 1) {
+        if (n <= 31) rdm_partials<1, uint32_t><<<nb, kBlock, 0, st>>>(amp, uint32_t(groups), ta, partials);
+        else rdm_partials<1, uint64_t><<<nb, kBlock, 0, st>>>(amp, groups, ta, partials);
+    } else if (k == 2) {
+        if (n <= 31) rdm_partials<2, uint32_t><<<nb, kBlock, 0, st>>>(amp, uint32_t(groups), ta, partials);
+        else rdm_partials<2, uint64_t><<<nb, kBlock, 0, st>>>(amp, groups, ta, partials);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    reduce_records<<<1, kBlock, 0, st>>>(partials, nb, width, out_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_copy_norm(const float2 *in, float2 *out, int n, const GateDesc &g,
+                                  double *partials, double *out_dev, hipStream_t st) {
+    const int nb = reduce_blocks_for(n, g.k);
+    const uint64_t groups = uint64_t(1) << (n - g.k);
+    if (g.k == 1) {
+        if (n <= 31) apply_copy_norm<1, uint32_t><<<nb, kBlock, 0, st>>>(in, out, uint32_t(groups), make_args<1>(g), partials);
+        else apply_copy_norm<1, uint64_t><<<nb, kBlock, 0, st>>>(in, out, groups, make_args<1>(g), partials);
+    } else if (g.k == 2) {
+        if (n <= 31) apply_copy_norm<2, uint32_t><<<nb, kBlock, 0, st>>>(in, out, uint32_t(groups), make_args<2>(g), partials);
+        else apply_copy_norm<2, uint64_t><<<nb, kBlock, 0, st>>>(in, out, groups, make_args<2>(g), partials);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    reduce_records<<<1, kBlock, 0, st>>>(partials, nb, 2, out_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(const float2 *amp, int n, double *sums, double *incl, uint64_t seed,
+                         uint32_t traj, uint32_t circ, int n_samples, const ReadoutDesc &ro,
+                         uint64_t *out_dev, double *norm_dev, hipStream_t st) {
+    const int B = n < kSampleBlockBits ? n : kSampleBlockBits;
+    const int64_t nb = int64_t(1) << (n - B);
+    if (n <= 31)
+        sample_block_sums<uint32_t><<<unsigned(nb), kBlock, 0, st>>>(amp, B, sums);
+    else
+        sample_block_sums<uint64_t><<<unsigned(nb), kBlock, 0, st>>>(amp, B, sums);
+    sample_scan<<<1, kScanThreads, 0, st>>>(sums, nb, incl, norm_dev);
+    if (n_samples > 0) {
+        const unsigned grid = unsigned((n_samples + kBlock - 1) / kBlock);
+        if (n <= 31)
+            sample_draw<uint32_t><<<grid, kBlock, 0, st>>>(amp, n, B, incl, nb, norm_dev, seed, traj,
+                                                           circ, n_samples, ro, out_dev);
+        else
+            sample_draw<uint64_t><<<grid, kBlock, 0, st>>>(amp, n, B, incl, nb, norm_dev, seed, traj,
+                                                           circ, n_samples, ro, out_dev);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qs

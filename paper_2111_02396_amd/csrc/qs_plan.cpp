@@ -1,0 +1,262 @@
+// Host-side planning: Kraus bounds, greedy gate fusion, fused matrices.
+#include "qs_plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+namespace qs {
+
+namespace {
+
+// Eigenvalues of a real symmetric m x m matrix by cyclic Jacobi rotations.
+void jacobi_symmetric(int m, std::vector<double> &a, std::vector<double> &eig) {
+    auto at = [&](int r, int c) -> double & { return a[size_t(r) * m + c]; };
+    double scale = 0.0;
+    for (double v : a) scale = std::max(scale, std::fabs(v));
+    const double tiny = scale * 1e-300 + std::numeric_limits<double>::min();
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < m; ++p)
+            for (int q = p + 1; q < m; ++q) off += at(p, q) * at(p, q);
+        if (off <= (scale * scale) * 1e-34 || off == 0.0) break;
+        for (int p = 0; p < m; ++p) {
+            for (int q = p + 1; q < m; ++q) {
+                const double apq = at(p, q);
+                if (std::fabs(apq) <= tiny) continue;
+                const double theta = (at(q, q) - at(p, p)) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) /
+                                 (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0);
+                const double s = t * c;
+                for (int r = 0; r < m; ++r) {  // columns p, q
+                    const double arp = at(r, p), arq = at(r, q);
+                    at(r, p) = c * arp - s * arq;
+                    at(r, q) = s * arp + c * arq;
+                }
+                for (int r = 0; r < m; ++r) {  // rows p, q
+                    const double apr = at(p, r), aqr = at(q, r);
+                    at(p, r) = c * apr - s * aqr;
+                    at(q, r) = s * apr + c * aqr;
+                }
+            }
+        }
+    }
+    eig.resize(m);
+    for (int i = 0; i < m; ++i) eig[i] = at(i, i);
+}
+
+}  // namespace
+
+double hermitian_min_eigenvalue(int d, const cd *A) {
+    const int m = 2 * d;
+    std::vector<double> a(size_t(m) * m);
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            const cd v = A[r * d + c];
+            a[size_t(r) * m + c] = v.real();
+            a[size_t(r) * m + c + d] = -v.imag();
+            a[size_t(r + d) * m + c] = v.imag();
+            a[size_t(r + d) * m + c + d] = v.real();
+        }
+    // symmetrise against rounding in the caller's Hermitian input
+    for (int r = 0; r < m; ++r)
+        for (int c = r + 1; c < m; ++c) {
+            const double s = 0.5 * (a[size_t(r) * m + c] + a[size_t(c) * m + r]);
+            a[size_t(r) * m + c] = a[size_t(c) * m + r] = s;
+        }
+    std::vector<double> eig;
+    jacobi_symmetric(m, a, eig);
+    return *std::min_element(eig.begin(), eig.end());
+}
+
+void gram(int d, const cd *K, cd *G) {
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            cd s = 0.0;
+            for (int m = 0; m < d; ++m) s += std::conj(K[m * d + a]) * K[m * d + b];
+            G[a * d + b] = s;
+        }
+}
+
+bool is_identity_multiple(int d, const cd *M, double tol, cd *scalar_out) {
+    const cd c = M[0];
+    for (int r = 0; r < d; ++r)
+        for (int col = 0; col < d; ++col) {
+            const cd expect = r == col ? c : cd(0.0);
+            if (std::abs(M[r * d + col] - expect) > tol) return false;
+        }
+    if (scalar_out) *scalar_out = c;
+    return true;
+}
+
+void kraus_bounds(int k, int n_kraus, const cd *kraus, double *pbar, bool *mixture) {
+    const int d = 1 << k;
+    std::vector<cd> G(size_t(d) * d);
+    bool mix = true;
+    for (int i = 0; i < n_kraus; ++i) {
+        gram(d, kraus + size_t(i) * d * d, G.data());
+        const double lam = hermitian_min_eigenvalue(d, G.data());
+        pbar[i] = lam > 0.0 ? lam : 0.0;
+        double tr = 0.0;
+        for (int j = 0; j < d; ++j) tr += G[j * d + j].real();
+        const double c = tr / d;
+        for (int r = 0; r < d && mix; ++r)
+            for (int col = 0; col < d; ++col) {
+                const cd expect = r == col ? cd(c) : cd(0.0);
+                if (std::abs(G[r * d + col] - expect) > 1e-12) {
+                    mix = false;
+                    break;
+                }
+            }
+    }
+    *mixture = mix;
+}
+
+std::vector<Block> fuse_greedy(int n_qubits, const std::vector<PlanOp> &ops, int max_fuse,
+                               std::vector<int> *op_block) {
+    const int n_ops = int(ops.size());
+    std::vector<std::vector<int>> on_qubit(n_qubits);
+    for (int o = 0; o < n_ops; ++o)
+        for (int j = 0; j < ops[o].k; ++j) on_qubit[ops[o].q[j]].push_back(o);
+    std::vector<size_t> head(n_qubits, 0);
+    std::vector<char> taken(n_ops, 0);
+    if (op_block) op_block->assign(n_ops, -1);
+
+    auto first_open = [&](int q) -> int {
+        auto &lst = on_qubit[q];
+        size_t &h = head[q];
+        while (h < lst.size() && taken[lst[h]]) ++h;
+        return h < lst.size() ? lst[h] : -1;
+    };
+    auto ready = [&](int o) -> bool {
+        for (int j = 0; j < ops[o].k; ++j)
+            if (first_open(ops[o].q[j]) != o) return false;
+        return true;
+    };
+
+    std::vector<Block> blocks;
+    for (int seed = 0; seed < n_ops; ++seed) {
+        if (taken[seed]) continue;
+        Block b;
+        bool in_set[64] = {false};
+        int qs[64];
+        int nq = 0;
+        auto add = [&](int o) {
+            taken[o] = 1;
+            b.ops.push_back(o);
+            for (int j = 0; j < ops[o].k; ++j) {
+                const int q = ops[o].q[j];
+                if (!in_set[q]) {
+                    in_set[q] = true;
+                    qs[nq++] = q;
+                }
+            }
+        };
+        add(seed);
+        const int limit = std::max(max_fuse, ops[seed].k);
+        for (;;) {
+            int best = -1;
+            int best_growth = 0;
+            for (int i = 0; i < nq; ++i) {
+                const int c = first_open(qs[i]);
+                if (c < 0 || !ready(c)) continue;
+                int growth = 0;
+                for (int j = 0; j < ops[c].k; ++j) growth += in_set[ops[c].q[j]] ? 0 : 1;
+                if (nq + growth > limit) continue;
+                const bool better = best < 0 || (growth == 0 && best_growth > 0) ||
+                                    ((growth == 0) == (best_growth == 0) && c < best);
+                if (better) {
+                    best = c;
+                    best_growth = growth;
+                }
+            }
+            if (best < 0) break;
+            add(best);
+        }
+        std::sort(b.ops.begin(), b.ops.end());
+        std::sort(qs, qs + nq);
+        b.k = nq;
+        for (int i = 0; i < nq; ++i) b.q[i] = qs[i];
+        if (op_block)
+            for (int o : b.ops) (*op_block)[o] = int(blocks.size());
+        blocks.push_back(std::move(b));
+    }
+    return blocks;
+}
+
+int union_qubits(const std::vector<int> &members, const std::vector<PlanOp> &ops, int *q_out) {
+    int nq = 0;
+    for (int o : members)
+        for (int j = 0; j < ops[o].k; ++j) {
+            const int q = ops[o].q[j];
+            bool seen = false;
+            for (int i = 0; i < nq; ++i) seen |= q_out[i] == q;
+            if (!seen) q_out[nq++] = q;
+        }
+    std::sort(q_out, q_out + nq);
+    return nq;
+}
+
+void fused_matrix(int k, const int *q, const std::vector<int> &members,
+                  const std::vector<PlanOp> &ops, const std::vector<const cd *> &mats, cd *out) {
+    const int D = 1 << k;
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) out[r * D + c] = r == c ? cd(1.0) : cd(0.0);
+    cd v[32], w[32];
+    for (int o : members) {
+        const cd *U = mats[o];
+        if (!U) continue;
+        const PlanOp &op = ops[o];
+        const int ko = op.k, d = 1 << ko;
+        int lp[5], lps[5];
+        for (int j = 0; j < ko; ++j) {
+            lp[j] = int(std::find(q, q + k, op.q[j]) - q);
+            lps[j] = lp[j];
+        }
+        std::sort(lps, lps + ko);
+        int off[32];
+        for (int j = 0; j < d; ++j) {
+            int x = 0;
+            for (int b = 0; b < ko; ++b)
+                if ((j >> b) & 1) x |= 1 << lp[b];
+            off[j] = x;
+        }
+        const int groups = D >> ko;
+        for (int g = 0; g < groups; ++g) {
+            int base = g;
+            for (int b = 0; b < ko; ++b) {
+                const int p = lps[b];
+                base = ((base >> p) << (p + 1)) | (base & ((1 << p) - 1));
+            }
+            for (int c = 0; c < D; ++c) {
+                for (int j = 0; j < d; ++j) v[j] = out[(base + off[j]) * D + c];
+                for (int j = 0; j < d; ++j) {
+                    cd s = 0.0;
+                    for (int l = 0; l < d; ++l) s += U[j * d + l] * v[l];
+                    w[j] = s;
+                }
+                for (int j = 0; j < d; ++j) out[(base + off[j]) * D + c] = w[j];
+            }
+        }
+    }
+}
+
+void to_ascending_order(int k, const int *t, const cd *in, cd *out, int *t_sorted) {
+    const int D = 1 << k;
+    int order[5];
+    for (int j = 0; j < k; ++j) order[j] = j;
+    std::sort(order, order + k, [&](int a, int b) { return t[a] < t[b]; });
+    for (int s = 0; s < k; ++s) t_sorted[s] = t[order[s]];
+    // original bit order[s] -> sorted bit s
+    auto map = [&](int x) {
+        int y = 0;
+        for (int s = 0; s < k; ++s)
+            if ((x >> order[s]) & 1) y |= 1 << s;
+        return y;
+    };
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) out[map(r) * D + map(c)] = in[r * D + c];
+}
+
+}  // namespace qs

@@ -1,0 +1,64 @@
+// Host-side planning: Kraus bounds, greedy gate fusion, fused matrices.
+// Plain C++17 (no device code), so the planner can be exercised on a CPU.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <vector>
+
+namespace qs {
+
+using cd = std::complex<double>;
+
+// An operation as the planner sees it: matrix bit j <-> q[j].
+struct PlanOp {
+    int k = 0;
+    int q[5] = {0, 0, 0, 0, 0};
+};
+
+// A fused block: ascending qubits, time-ordered member operations.
+struct Block {
+    int k = 0;
+    int q[5] = {0, 0, 0, 0, 0};
+    std::vector<int> ops;
+};
+
+// Smallest eigenvalue of a d x d Hermitian matrix (row-major), via the real
+// symmetric 2d x 2d embedding [[Re, -Im], [Im, Re]] and cyclic Jacobi sweeps.
+double hermitian_min_eigenvalue(int d, const cd *A);
+
+// G = K^dag K for a d x d matrix.
+void gram(int d, const cd *K, cd *G);
+
+// Kraus bounds (Section 3.5): pbar_i = max(lambda_min(K_i^dag K_i), 0);
+// mixture = every K_i^dag K_i is c_i I within 1e-12 (entrywise).
+void kraus_bounds(int k, int n_kraus, const cd *kraus, double *pbar, bool *mixture);
+
+// Greedy fusion (Section 3.2).  Operations are taken in time order; the
+// earliest unassigned operation seeds a block; the block then repeatedly
+// absorbs the earliest operation that (a) is the first unassigned operation
+// on each of its qubits and (b) touches the block's qubits, preferring those
+// that add no new qubit, while the union stays within max_fuse qubits.
+// Operations wider than max_fuse form a block of their own.  Condition (a)
+// makes "apply the blocks in creation order" equal to "apply the operations
+// in time order".
+std::vector<Block> fuse_greedy(int n_qubits, const std::vector<PlanOp> &ops, int max_fuse,
+                               std::vector<int> *op_block = nullptr);
+
+// Fused matrix of a subset of operations (time-ordered indices) acting on
+// the ascending qubit set q[0..k-1]: the product of the embedded operator
+// matrices, latest on the left.  mats[o] = matrix of op o (its own target
+// order), or nullptr for an identity placeholder.  out: (2^k)^2 row-major.
+void fused_matrix(int k, const int *q, const std::vector<int> &members,
+                  const std::vector<PlanOp> &ops, const std::vector<const cd *> &mats, cd *out);
+
+// Ascending union of the qubits of `members`; returns its size.
+int union_qubits(const std::vector<int> &members, const std::vector<PlanOp> &ops, int *q_out);
+
+// Permute a d x d matrix written for target order t[0..k-1] into ascending
+// target order.
+void to_ascending_order(int k, const int *t, const cd *in, cd *out, int *t_sorted);
+
+bool is_identity_multiple(int d, const cd *M, double tol, cd *scalar_out);
+
+}  // namespace qs

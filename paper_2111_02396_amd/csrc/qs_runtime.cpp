@@ -1,0 +1,1175 @@
+// Host runtime behind include/qs.h: state handles, deferred operations,
+// Kraus-branch selection, sampling and the trajectory driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <string>
+#include <vector>
+
+#include "qs.h"
+#include "qs_internal.h"
+#include "qs_philox.h"
+#include "qs_plan.h"
+
+using qs::cd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qs_status fail(qs_status st, const std::string &msg) {
+    g_last_error = msg;
+    return st;
+}
+
+constexpr int kRingSlots = 64;
+constexpr int kDefaultFuse = 4;
+constexpr double kRenormLogThreshold = -46.0;  // ~1e-20 on the norm squared
+
+struct PendingOp {
+    int k;
+    int t[5];
+    std::vector<cd> m;
+};
+
+}  // namespace
+
+struct qs_state_s {
+    int n = 0;
+    float2 *amp = nullptr;      // where the amplitudes are now
+    float2 *home = nullptr;     // where they live between calls
+    bool owns_home = false;
+    hipStream_t st = nullptr;
+    float2 *scratch = nullptr;  // second state for the conventional method
+    double *red_partials = nullptr;
+    double *red_out = nullptr;
+    double *red_host = nullptr;  // pinned
+    double *samp_sums = nullptr;
+    double *samp_incl = nullptr;
+    double *samp_norm = nullptr;
+    uint64_t *samp_out = nullptr;
+    size_t samp_cap = 0;
+    float2 *ring_dev = nullptr;   // k = 5 matrices
+    float2 *ring_host = nullptr;  // pinned staging
+    hipEvent_t ring_ev[kRingSlots] = {};
+    bool ring_live[kRingSlots] = {};
+    int ring_pos = 0;
+    std::vector<PendingOp> pending;
+    bool poisoned = false;
+};
+
+namespace {
+
+qs_status device_fail(qs_state s, hipError_t e, const char *what) {
+    if (s) s->poisoned = true;
+    return fail(QS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define QS_HIP(s, expr)                                          \
+    do {                                                         \
+        hipError_t e_ = (expr);                                  \
+        if (e_ != hipSuccess) return device_fail((s), e_, #expr); \
+    } while (0)
+
+#define QS_CHECK(expr)                   \
+    do {                                 \
+        qs_status st_ = (expr);          \
+        if (st_ != QS_OK) return st_;    \
+    } while (0)
+
+qs_status check_handle(qs_state s) {
+    if (!s) return fail(QS_ERR_INVALID_ARGUMENT, "null state handle");
+    if (s->poisoned) return fail(QS_ERR_DEVICE, "state handle poisoned by an earlier device error");
+    return QS_OK;
+}
+
+bool finite_matrix(const double *m, size_t n_doubles) {
+    for (size_t i = 0; i < n_doubles; ++i)
+        if (!std::isfinite(m[i])) return false;
+    return true;
+}
+
+qs_status check_targets(int n, int k, const int *t, int kmax) {
+    if (k < 1 || k > kmax) return fail(QS_ERR_INVALID_ARGUMENT, "k out of range");
+    if (k > n) return fail(QS_ERR_INVALID_ARGUMENT, "more targets than qubits");
+    if (!t) return fail(QS_ERR_INVALID_ARGUMENT, "null targets");
+    for (int i = 0; i < k; ++i) {
+        if (t[i] < 0 || t[i] >= n) return fail(QS_ERR_INVALID_ARGUMENT, "target out of range");
+        for (int j = 0; j < i; ++j)
+            if (t[i] == t[j]) return fail(QS_ERR_INVALID_ARGUMENT, "duplicate target");
+    }
+    return QS_OK;
+}
+
+// GateDesc (ascending targets, complex64) from a complex128 matrix in the
+// caller's target order.
+void make_desc(int k, const int *t, const cd *m, qs::GateDesc &g) {
+    const int D = 1 << k;
+    std::vector<cd> sorted(size_t(D) * D);
+    int ts[5];
+    qs::to_ascending_order(k, t, m, sorted.data(), ts);
+    g.k = k;
+    for (int b = 0; b < 5; ++b) g.t[b] = b < k ? ts[b] : 0;
+    for (int i = 0; i < D * D; ++i)
+        g.m[i] = make_float2(float(sorted[i].real()), float(sorted[i].imag()));
+}
+
+qs_status ensure_ring(qs_state s) {
+    if (s->ring_dev) return QS_OK;
+    QS_HIP(s, hipMalloc(&s->ring_dev, sizeof(float2) * 1024 * kRingSlots));
+    QS_HIP(s, hipHostMalloc(&s->ring_host, sizeof(float2) * 1024 * kRingSlots, hipHostMallocDefault));
+    for (int i = 0; i < kRingSlots; ++i) {
+        QS_HIP(s, hipEventCreateWithFlags(&s->ring_ev[i], hipEventDisableTiming));
+        s->ring_live[i] = false;
+    }
+    return QS_OK;
+}
+
+qs_status enqueue_desc(qs_state s, const qs::GateDesc &g) {
+    const float2 *mat_dev = nullptr;
+    if (g.k == 5) {
+        QS_CHECK(ensure_ring(s));
+        const int slot = s->ring_pos;
+        s->ring_pos = (s->ring_pos + 1) % kRingSlots;
+        if (s->ring_live[slot]) QS_HIP(s, hipEventSynchronize(s->ring_ev[slot]));
+        std::memcpy(s->ring_host + size_t(slot) * 1024, g.m, sizeof(float2) * 1024);
+        QS_HIP(s, hipMemcpyAsync(s->ring_dev + size_t(slot) * 1024, s->ring_host + size_t(slot) * 1024,
+                                 sizeof(float2) * 1024, hipMemcpyHostToDevice, s->st));
+        QS_HIP(s, hipEventRecord(s->ring_ev[slot], s->st));
+        s->ring_live[slot] = true;
+        mat_dev = s->ring_dev + size_t(slot) * 1024;
+    }
+    QS_HIP(s, qs::launch_apply_gate(s->amp, s->n, g, mat_dev, s->st));
+    return QS_OK;
+}
+
+qs_status enqueue_matrix(qs_state s, int k, const int *t, const cd *m) {
+    qs::GateDesc g;
+    make_desc(k, t, m, g);
+    return enqueue_desc(s, g);
+}
+
+qs_status flush_pending(qs_state s, int max_fuse = kDefaultFuse) {
+    if (s->pending.empty()) return QS_OK;
+    std::vector<qs::PlanOp> ops(s->pending.size());
+    std::vector<const cd *> mats(s->pending.size());
+    for (size_t i = 0; i < s->pending.size(); ++i) {
+        ops[i].k = s->pending[i].k;
+        for (int j = 0; j < 5; ++j) ops[i].q[j] = s->pending[i].t[j];
+        mats[i] = s->pending[i].m.data();
+    }
+    const auto blocks = qs::fuse_greedy(s->n, ops, max_fuse);
+    std::vector<cd> M(1024);
+    for (const auto &b : blocks) {
+        qs::fused_matrix(b.k, b.q, b.ops, ops, mats, M.data());
+        cd c;
+        if (qs::is_identity_multiple(1 << b.k, M.data(), 1e-15, &c) && std::abs(c - cd(1.0)) < 1e-15)
+            continue;
+        QS_CHECK(enqueue_matrix(s, b.k, b.q, M.data()));  // b.q ascending already
+    }
+    s->pending.clear();
+    return QS_OK;
+}
+
+qs_status ensure_reduce(qs_state s) {
+    if (s->red_partials) return QS_OK;
+    QS_HIP(s, hipMalloc(&s->red_partials, sizeof(double) * qs::kMaxReduceBlocks * qs::kMaxReduceWidth));
+    QS_HIP(s, hipMalloc(&s->red_out, sizeof(double) * qs::kMaxReduceWidth));
+    QS_HIP(s, hipHostMalloc(&s->red_host, sizeof(double) * qs::kMaxReduceWidth, hipHostMallocDefault));
+    return QS_OK;
+}
+
+qs_status ensure_sampling(qs_state s, size_t n_out) {
+    if (!s->samp_sums) {
+        const int B = std::min(s->n, qs::kSampleBlockBits);
+        const size_t nb = size_t(1) << (s->n - B);
+        QS_HIP(s, hipMalloc(&s->samp_sums, sizeof(double) * nb));
+        QS_HIP(s, hipMalloc(&s->samp_incl, sizeof(double) * nb));
+        QS_HIP(s, hipMalloc(&s->samp_norm, sizeof(double) * 2));
+    }
+    if (n_out > s->samp_cap) {
+        if (s->samp_out) QS_HIP(s, hipFree(s->samp_out));
+        s->samp_out = nullptr;
+        s->samp_cap = 0;
+        QS_HIP(s, hipMalloc(&s->samp_out, sizeof(uint64_t) * n_out));
+        s->samp_cap = n_out;
+    }
+    return QS_OK;
+}
+
+qs_status ensure_scratch(qs_state s) {
+    if (s->scratch) return QS_OK;
+    const size_t bytes = sizeof(float2) << s->n;
+    size_t free_b = 0, total_b = 0;
+    QS_HIP(s, hipMemGetInfo(&free_b, &total_b));
+    if (free_b < bytes) return fail(QS_ERR_OUT_OF_MEMORY, "no room for the conventional method's second state");
+    hipError_t e = hipMalloc(&s->scratch, bytes);
+    if (e != hipSuccess) {
+        s->scratch = nullptr;
+        (void)hipGetLastError();
+        return fail(QS_ERR_OUT_OF_MEMORY, "allocating the second state failed");
+    }
+    return QS_OK;
+}
+
+// Sum of |psi|^2 over the current buffer; synchronises.
+qs_status device_norm(qs_state s, double *out) {
+    QS_CHECK(ensure_reduce(s));
+    QS_HIP(s, qs::launch_norm(s->amp, s->n, s->red_partials, s->red_out, s->st));
+    QS_HIP(s, hipMemcpyAsync(s->red_host, s->red_out, sizeof(double), hipMemcpyDeviceToHost, s->st));
+    QS_HIP(s, hipStreamSynchronize(s->st));
+    *out = s->red_host[0];
+    return QS_OK;
+}
+
+// R = sum_groups v v^dag over ascending targets ts (k <= 2); synchronises.
+// R[j][l] = (red_host[2(jD+l)], red_host[2(jD+l)+1]).
+qs_status device_rdm(qs_state s, int k, const int *ts) {
+    QS_CHECK(ensure_reduce(s));
+    QS_HIP(s, qs::launch_rdm(s->amp, s->n, k, ts, s->red_partials, s->red_out, s->st));
+    const int width = 2 << (2 * k);
+    QS_HIP(s, hipMemcpyAsync(s->red_host, s->red_out, sizeof(double) * width, hipMemcpyDeviceToHost, s->st));
+    QS_HIP(s, hipStreamSynchronize(s->st));
+    return QS_OK;
+}
+
+// Host record of one channel.
+struct ChannelInfo {
+    int op = -1;
+    int k = 0;
+    int t[5] = {};
+    int ts[5] = {};     // ascending
+    int nk = 0;
+    const cd *kraus = nullptr;           // nk consecutive D x D (caller order)
+    std::vector<double> pbar;
+    bool mixture = false;
+    std::vector<char> identity;          // K_i proportional to I
+    std::vector<cd> unit;                // mixture: K_i / sqrt(pbar_i)
+    std::vector<cd> excess_sorted;       // K_i^dag K_i - pbar_i I, ascending-target order
+    int default_pick = 0;
+    std::vector<double> log_pbar;        // log of pbar_i (norm^2 shrink bound)
+};
+
+void build_channel(int k, const int *t, int nk, const cd *kraus, ChannelInfo &c) {
+    const int D = 1 << k;
+    c.k = k;
+    for (int b = 0; b < k; ++b) c.t[b] = t[b];
+    c.nk = nk;
+    c.kraus = kraus;
+    c.pbar.assign(nk, 0.0);
+    bool mix = false;
+    qs::kraus_bounds(k, nk, kraus, c.pbar.data(), &mix);
+    c.mixture = mix;
+    c.identity.assign(nk, 0);
+    c.unit.assign(size_t(nk) * D * D, cd(0.0));
+    c.excess_sorted.assign(size_t(nk) * D * D, cd(0.0));
+    c.log_pbar.assign(nk, 0.0);
+    std::vector<cd> G(size_t(D) * D);
+    for (int i = 0; i < nk; ++i) {
+        const cd *K = kraus + size_t(i) * D * D;
+        c.identity[i] = qs::is_identity_multiple(D, K, 1e-14, nullptr) ? 1 : 0;
+        if (mix && c.pbar[i] > 0.0) {
+            const double f = 1.0 / std::sqrt(c.pbar[i]);
+            for (int e = 0; e < D * D; ++e) c.unit[size_t(i) * D * D + e] = K[e] * f;
+        }
+        qs::gram(D, K, G.data());
+        for (int j = 0; j < D; ++j) G[j * D + j] -= c.pbar[i];
+        qs::to_ascending_order(k, t, G.data(), c.excess_sorted.data() + size_t(i) * D * D, c.ts);
+        c.log_pbar[i] = c.mixture ? 0.0 : (c.pbar[i] > 0.0 ? std::log(c.pbar[i]) : -1e300);
+    }
+    int best = 0;
+    for (int i = 1; i < nk; ++i)
+        if (c.pbar[i] > c.pbar[best]) best = i;
+    c.default_pick = best;
+}
+
+// Matrix to apply for pick i picked from the bounds: nullptr = identity
+// (a scalar multiple of I is dropped: normalisation is lazy).
+const cd *fast_pick_matrix(const ChannelInfo &c, int i) {
+    const int D = 1 << c.k;
+    if (c.identity[i]) return nullptr;
+    if (c.mixture) return c.unit.data() + size_t(i) * D * D;
+    return c.kraus + size_t(i) * D * D;
+}
+
+// Algorithm 2, steps 1-11: returns the pick, or -1 with *residual set.
+int select_fast(const ChannelInfo &c, double r, double *residual) {
+    for (int i = 0; i < c.nk; ++i) {
+        if (r < c.pbar[i]) return i;
+        r -= c.pbar[i];
+    }
+    if (c.mixture) {
+        for (int i = c.nk - 1; i >= 0; --i)
+            if (c.pbar[i] > 0.0) return i;
+    }
+    *residual = r;
+    return -1;
+}
+
+// Algorithm 2, steps 13-20, from the FP64 reduced density matrix R (ascending
+// target order, R[j][l] = sum v_j conj(v_l)).  Returns the pick and p_i.
+int select_slow(const ChannelInfo &c, const double *R, double r, double *p_out, double *N_out) {
+    const int D = 1 << c.k;
+    double N = 0.0;
+    for (int j = 0; j < D; ++j) N += R[2 * (j * D + j)];
+    *N_out = N;
+    int last_pos = -1, pick = -1;
+    double e_pick = 0.0;
+    std::vector<double> e(c.nk, 0.0);
+    for (int i = 0; i < c.nk; ++i) {
+        const cd *M = c.excess_sorted.data() + size_t(i) * D * D;
+        double tr = 0.0;  // Re sum_jl M[j][l] R[l][j]
+        for (int j = 0; j < D; ++j)
+            for (int l = 0; l < D; ++l) {
+                const cd m = M[j * D + l];
+                const double rr = R[2 * (l * D + j)], ri = R[2 * (l * D + j) + 1];
+                tr += m.real() * rr - m.imag() * ri;
+            }
+        e[i] = tr / N;
+        if (e[i] > 0.0) last_pos = i;
+        if (r < e[i]) {
+            pick = i;
+            e_pick = e[i];
+            break;
+        }
+        r -= e[i];
+    }
+    if (pick < 0) {
+        pick = last_pos >= 0 ? last_pos : c.nk - 1;
+        e_pick = e[pick];
+    }
+    *p_out = c.pbar[pick] + e_pick;
+    return pick;
+}
+
+uint32_t channel_draw_index(uint32_t ordinal) { return ordinal; }
+
+// Conventional method for one channel (Section 3.5): trial i writes K_i psi
+// to the second state with its norm; r < p_i keeps it.  On return the
+// accepted state is current (buffers swapped).
+qs_status naive_channel(qs_state s, const ChannelInfo &c, double r, int *pick_out,
+                        double *accepted_norm_out) {
+    QS_CHECK(ensure_scratch(s));
+    QS_CHECK(ensure_reduce(s));
+    const int D = 1 << c.k;
+    int last_pos = -1;
+    int pick = -1;
+    double N = 0.0;
+    for (int i = 0; i < c.nk; ++i) {
+        qs::GateDesc g;
+        make_desc(c.k, c.t, c.kraus + size_t(i) * D * D, g);
+        QS_HIP(s, qs::launch_apply_copy_norm(s->amp, s->scratch, s->n, g, s->red_partials, s->red_out, s->st));
+        QS_HIP(s, hipMemcpyAsync(s->red_host, s->red_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        QS_HIP(s, hipStreamSynchronize(s->st));
+        N = s->red_host[1];
+        if (!(N > 0.0) || !std::isfinite(N)) return fail(QS_ERR_ZERO_NORM, "state has zero norm");
+        const double p = s->red_host[0] / N;
+        if (p > 0.0) last_pos = i;
+        if (r < p) {
+            pick = i;
+            *accepted_norm_out = s->red_host[0];
+            break;
+        }
+        r -= p;
+    }
+    if (pick < 0) {
+        if (last_pos < 0) return fail(QS_ERR_ZERO_NORM, "every Kraus operator annihilates the state");
+        pick = last_pos;
+        qs::GateDesc g;
+        make_desc(c.k, c.t, c.kraus + size_t(pick) * D * D, g);
+        QS_HIP(s, qs::launch_apply_copy_norm(s->amp, s->scratch, s->n, g, s->red_partials, s->red_out, s->st));
+        QS_HIP(s, hipMemcpyAsync(s->red_host, s->red_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+        QS_HIP(s, hipStreamSynchronize(s->st));
+        *accepted_norm_out = s->red_host[0];
+    }
+    std::swap(s->amp, s->scratch);
+    *pick_out = pick;
+    return QS_OK;
+}
+
+qs_status restore_home(qs_state s) {
+    if (s->amp == s->home) return QS_OK;
+    QS_HIP(s, hipMemcpyAsync(s->home, s->amp, sizeof(float2) << s->n, hipMemcpyDeviceToDevice, s->st));
+    s->scratch = s->amp;
+    s->amp = s->home;
+    return QS_OK;
+}
+
+qs_status renormalize_now(qs_state s) {
+    double N = 0.0;
+    QS_CHECK(device_norm(s, &N));
+    if (!(N > 0.0) || !std::isfinite(N)) return fail(QS_ERR_ZERO_NORM, "state has zero norm");
+    QS_HIP(s, qs::launch_scale(s->amp, s->n, float(1.0 / std::sqrt(N)), s->st));
+    return QS_OK;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+
+extern "C" {
+
+const char *qs_last_error_message(void) { return g_last_error.c_str(); }
+
+const char *qs_version(void) { return "qs-mi355x 0.1"; }
+
+qs_status qs_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    if (!ctr || !key || !out) return fail(QS_ERR_INVALID_ARGUMENT, "null argument");
+    const qs::PhiloxWords w = qs::philox4x32_10(ctr[0], ctr[1], ctr[2], ctr[3], key[0], key[1]);
+    for (int i = 0; i < 4; ++i) out[i] = w.w[i];
+    return QS_OK;
+}
+
+qs_status qs_kraus_bounds(int k, int n_kraus, const double *kraus, double *pbar_out,
+                          int *mixture_out) {
+    if (k < 1 || k > qs::kMaxGateQubits || n_kraus < 1 || n_kraus > 64 || !kraus || !pbar_out ||
+        !mixture_out)
+        return fail(QS_ERR_INVALID_ARGUMENT, "bad arguments");
+    const int D = 1 << k;
+    if (!finite_matrix(kraus, size_t(n_kraus) * D * D * 2))
+        return fail(QS_ERR_INVALID_ARGUMENT, "non-finite Kraus entries");
+    bool mix = false;
+    qs::kraus_bounds(k, n_kraus, reinterpret_cast<const cd *>(kraus), pbar_out, &mix);
+    *mixture_out = mix ? 1 : 0;
+    return QS_OK;
+}
+
+qs_status qs_create_state(int n_qubits, void *device_buf, size_t buf_bytes, void *hip_stream,
+                          qs_state *out) {
+    if (!out) return fail(QS_ERR_INVALID_ARGUMENT, "null output handle");
+    *out = nullptr;
+    if (n_qubits < 1 || n_qubits > qs::kMaxQubits) return fail(QS_ERR_INVALID_ARGUMENT, "n out of range");
+    const size_t bytes = sizeof(float2) << n_qubits;
+    if (device_buf && buf_bytes < bytes) return fail(QS_ERR_INVALID_ARGUMENT, "buffer smaller than 8*2^n bytes");
+    auto *s = new qs_state_s();
+    s->n = n_qubits;
+    s->st = static_cast<hipStream_t>(hip_stream);
+    if (device_buf) {
+        s->home = static_cast<float2 *>(device_buf);
+    } else {
+        size_t free_b = 0, total_b = 0;
+        hipError_t e = hipMemGetInfo(&free_b, &total_b);
+        if (e != hipSuccess) {
+            delete s;
+            return fail(QS_ERR_DEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+        }
+        if (free_b < bytes) {
+            delete s;
+            return fail(QS_ERR_OUT_OF_MEMORY, "free device memory below 8*2^n bytes");
+        }
+        e = hipMalloc(&s->home, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete s;
+            return fail(QS_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
+        }
+        s->owns_home = true;
+    }
+    s->amp = s->home;
+    hipError_t e = qs::launch_set_basis(s->amp, s->n, 0, s->st);
+    if (e != hipSuccess) {
+        if (s->owns_home) (void)hipFree(s->home);
+        delete s;
+        return fail(QS_ERR_DEVICE, std::string("init: ") + hipGetErrorString(e));
+    }
+    *out = s;
+    return QS_OK;
+}
+
+qs_status qs_destroy_state(qs_state s) {
+    if (!s) return fail(QS_ERR_INVALID_ARGUMENT, "null state handle");
+    (void)hipStreamSynchronize(s->st);
+    // {amp, scratch} = {home, second buffer} as a set, whatever swaps happened
+    float2 *second = s->amp != s->home ? s->amp : s->scratch;
+    if (s->owns_home) (void)hipFree(s->home);
+    if (second && second != s->home) (void)hipFree(second);
+    if (s->red_partials) (void)hipFree(s->red_partials);
+    if (s->red_out) (void)hipFree(s->red_out);
+    if (s->red_host) (void)hipHostFree(s->red_host);
+    if (s->samp_sums) (void)hipFree(s->samp_sums);
+    if (s->samp_incl) (void)hipFree(s->samp_incl);
+    if (s->samp_norm) (void)hipFree(s->samp_norm);
+    if (s->samp_out) (void)hipFree(s->samp_out);
+    if (s->ring_dev) {
+        (void)hipFree(s->ring_dev);
+        (void)hipHostFree(s->ring_host);
+        for (int i = 0; i < kRingSlots; ++i) (void)hipEventDestroy(s->ring_ev[i]);
+    }
+    delete s;
+    return QS_OK;
+}
+
+qs_status qs_reset_state(qs_state s) {
+    QS_CHECK(check_handle(s));
+    s->pending.clear();
+    QS_CHECK(restore_home(s));
+    QS_HIP(s, qs::launch_set_basis(s->amp, s->n, 0, s->st));
+    return QS_OK;
+}
+
+qs_status qs_state_device_ptr(qs_state s, void **out) {
+    QS_CHECK(check_handle(s));
+    if (!out) return fail(QS_ERR_INVALID_ARGUMENT, "null output");
+    *out = s->amp;
+    return QS_OK;
+}
+
+qs_status qs_state_qubits(qs_state s, int *n_out) {
+    if (!s || !n_out) return fail(QS_ERR_INVALID_ARGUMENT, "null argument");
+    *n_out = s->n;
+    return QS_OK;
+}
+
+qs_status qs_flush(qs_state s) {
+    QS_CHECK(check_handle(s));
+    return flush_pending(s);
+}
+
+qs_status qs_copy_state_to_host(qs_state s, void *host_out, size_t bytes) {
+    QS_CHECK(check_handle(s));
+    const size_t need = sizeof(float2) << s->n;
+    if (!host_out || bytes < need) return fail(QS_ERR_INVALID_ARGUMENT, "host buffer too small");
+    QS_CHECK(flush_pending(s));
+    QS_HIP(s, hipStreamSynchronize(s->st));
+    QS_HIP(s, hipMemcpy(host_out, s->amp, need, hipMemcpyDeviceToHost));
+    return QS_OK;
+}
+
+qs_status qs_load_state_from_host(qs_state s, const void *host_in, size_t bytes) {
+    QS_CHECK(check_handle(s));
+    const size_t need = sizeof(float2) << s->n;
+    if (!host_in || bytes < need) return fail(QS_ERR_INVALID_ARGUMENT, "host buffer too small");
+    s->pending.clear();
+    QS_CHECK(restore_home(s));
+    QS_HIP(s, hipStreamSynchronize(s->st));
+    QS_HIP(s, hipMemcpy(s->amp, host_in, need, hipMemcpyHostToDevice));
+    return QS_OK;
+}
+
+qs_status qs_apply_fused_gate(qs_state s, int k, const int *targets, const double *matrix) {
+    QS_CHECK(check_handle(s));
+    QS_CHECK(check_targets(s->n, k, targets, qs::kMaxGateQubits));
+    if (!matrix) return fail(QS_ERR_INVALID_ARGUMENT, "null matrix");
+    const int D = 1 << k;
+    if (!finite_matrix(matrix, size_t(D) * D * 2)) return fail(QS_ERR_INVALID_ARGUMENT, "non-finite matrix");
+    QS_CHECK(flush_pending(s));
+    return enqueue_matrix(s, k, targets, reinterpret_cast<const cd *>(matrix));
+}
+
+qs_status qs_apply_channel(qs_state s, int k, const int *targets, int n_kraus,
+                           const double *kraus, uint64_t seed, uint32_t traj,
+                           uint32_t channel_index, qs_kraus_mode mode, int *chosen_out,
+                           int *path_out) {
+    QS_CHECK(check_handle(s));
+    if (k > qs::kMaxChannelQubits && k <= qs::kMaxGateQubits)
+        return fail(QS_ERR_NOT_SUPPORTED, "channels act on at most 2 qubits");
+    QS_CHECK(check_targets(s->n, k, targets, qs::kMaxChannelQubits));
+    if (n_kraus < 1 || n_kraus > 16 || !kraus) return fail(QS_ERR_INVALID_ARGUMENT, "bad Kraus list");
+    if (mode != QS_KRAUS_DELAYED && mode != QS_KRAUS_NAIVE) return fail(QS_ERR_INVALID_ARGUMENT, "bad mode");
+    const int D = 1 << k;
+    if (!finite_matrix(kraus, size_t(n_kraus) * D * D * 2))
+        return fail(QS_ERR_INVALID_ARGUMENT, "non-finite Kraus entries");
+    ChannelInfo c;
+    build_channel(k, targets, n_kraus, reinterpret_cast<const cd *>(kraus), c);
+    const double r = qs::philox_uniform(seed, channel_draw_index(channel_index), traj, 0,
+                                        qs::kStreamChannel);
+    int pick = -1, path = 0;
+    if (mode == QS_KRAUS_DELAYED) {
+        double residual = 0.0;
+        pick = select_fast(c, r, &residual);
+        if (pick >= 0) {
+            const cd *M = fast_pick_matrix(c, pick);
+            if (M) {
+                PendingOp op;
+                op.k = k;
+                for (int b = 0; b < 5; ++b) op.t[b] = b < k ? targets[b] : 0;
+                op.m.assign(M, M + D * D);
+                s->pending.push_back(std::move(op));
+            }
+        } else {
+            path = 1;
+            QS_CHECK(flush_pending(s));
+            QS_CHECK(device_rdm(s, k, c.ts));
+            double p = 0.0, N = 0.0;
+            pick = select_slow(c, s->red_host, residual, &p, &N);
+            if (!(N > 0.0) || !std::isfinite(N)) return fail(QS_ERR_ZERO_NORM, "state has zero norm");
+            if (!(p > 0.0)) return fail(QS_ERR_ZERO_NORM, "chosen Kraus operator has zero weight");
+            const double f = 1.0 / std::sqrt(p * N);
+            PendingOp op;
+            op.k = k;
+            for (int b = 0; b < 5; ++b) op.t[b] = b < k ? targets[b] : 0;
+            op.m.resize(D * D);
+            const cd *K = c.kraus + size_t(pick) * D * D;
+            for (int e = 0; e < D * D; ++e) op.m[e] = K[e] * f;
+            s->pending.push_back(std::move(op));
+        }
+    } else {
+        path = 1;
+        QS_CHECK(flush_pending(s));
+        double accepted = 0.0;
+        QS_CHECK(naive_channel(s, c, r, &pick, &accepted));
+        if (!(accepted > 0.0)) return fail(QS_ERR_ZERO_NORM, "chosen Kraus operator has zero weight");
+        // |psi> <- K_i |psi> / sqrt(p_i) up to the lazily kept norm; rescale
+        // only when the stored norm leaves a safe float range
+        if (accepted < 1e-20 || accepted > 1e20)
+            QS_HIP(s, qs::launch_scale(s->amp, s->n, float(1.0 / std::sqrt(accepted)), s->st));
+        if (s->home != s->amp && !s->owns_home) QS_CHECK(restore_home(s));
+    }
+    if (chosen_out) *chosen_out = pick;
+    if (path_out) *path_out = path;
+    return QS_OK;
+}
+
+qs_status qs_norm(qs_state s, double *norm_sq_out) {
+    QS_CHECK(check_handle(s));
+    if (!norm_sq_out) return fail(QS_ERR_INVALID_ARGUMENT, "null output");
+    QS_CHECK(flush_pending(s));
+    return device_norm(s, norm_sq_out);
+}
+
+namespace {
+
+qs_status fill_readout(int n, const double *p0to1, const double *p1to0, qs::ReadoutDesc &ro) {
+    std::memset(&ro, 0, sizeof(ro));
+    if (!p0to1 && !p1to0) return QS_OK;
+    if (!p0to1 || !p1to0) return fail(QS_ERR_INVALID_ARGUMENT, "give both readout arrays or neither");
+    for (int q = 0; q < n; ++q) {
+        if (!(p0to1[q] >= 0.0 && p0to1[q] <= 1.0 && p1to0[q] >= 0.0 && p1to0[q] <= 1.0))
+            return fail(QS_ERR_INVALID_ARGUMENT, "readout probability outside [0, 1]");
+        ro.e0[q] = p0to1[q];
+        ro.e1[q] = p1to0[q];
+    }
+    ro.enabled = 1;
+    return QS_OK;
+}
+
+}  // namespace
+
+qs_status qs_sample_measurements(qs_state s, uint64_t seed, uint32_t traj, int n_samples,
+                                 const double *p0to1, const double *p1to0,
+                                 uint64_t *bitstrings_out) {
+    QS_CHECK(check_handle(s));
+    if (n_samples < 0 || (n_samples > 0 && !bitstrings_out))
+        return fail(QS_ERR_INVALID_ARGUMENT, "bad sample arguments");
+    qs::ReadoutDesc ro;
+    QS_CHECK(fill_readout(s->n, p0to1, p1to0, ro));
+    QS_CHECK(flush_pending(s));
+    QS_CHECK(ensure_sampling(s, size_t(std::max(n_samples, 1))));
+    QS_CHECK(ensure_reduce(s));
+    QS_HIP(s, qs::launch_sample(s->amp, s->n, s->samp_sums, s->samp_incl, seed, traj, 0, n_samples,
+                                ro, s->samp_out, s->samp_norm, s->st));
+    QS_HIP(s, hipMemcpyAsync(s->red_host, s->samp_norm, sizeof(double), hipMemcpyDeviceToHost, s->st));
+    QS_HIP(s, hipStreamSynchronize(s->st));
+    const double N = s->red_host[0];
+    if (!(N > 0.0) || !std::isfinite(N)) return fail(QS_ERR_ZERO_NORM, "state has zero norm");
+    if (n_samples > 0)
+        QS_HIP(s, hipMemcpy(bitstrings_out, s->samp_out, sizeof(uint64_t) * n_samples, hipMemcpyDeviceToHost));
+    return QS_OK;
+}
+
+// --------------------------------------------------------------------------
+// Trajectory driver.
+// --------------------------------------------------------------------------
+
+namespace {
+
+struct CircuitModel {
+    int n = 0;
+    std::vector<qs::PlanOp> ops;
+    std::vector<int> kind;
+    std::vector<const cd *> gate_mat;    // gates: matrix; channels: nullptr
+    std::vector<double> gate_log_bound;  // log sigma_min^2 of a gate matrix (0 if unitary)
+    std::vector<int> channel_of_op;      // -1 for gates
+    std::vector<ChannelInfo> channels;
+};
+
+qs_status build_model(const qs_circuit *c, CircuitModel &m) {
+    if (!c || !c->ops || c->n_ops < 0 || !c->mat_pool || c->pool_len < 0)
+        return fail(QS_ERR_INVALID_ARGUMENT, "bad circuit");
+    m.n = c->n_qubits;
+    const cd *pool = reinterpret_cast<const cd *>(c->mat_pool);
+    if (!finite_matrix(c->mat_pool, size_t(c->pool_len) * 2))
+        return fail(QS_ERR_INVALID_ARGUMENT, "non-finite matrix entries");
+    m.ops.resize(c->n_ops);
+    m.kind.resize(c->n_ops);
+    m.gate_mat.assign(c->n_ops, nullptr);
+    m.gate_log_bound.assign(c->n_ops, 0.0);
+    m.channel_of_op.assign(c->n_ops, -1);
+    std::vector<cd> G(1024);
+    for (int o = 0; o < c->n_ops; ++o) {
+        const qs_op &op = c->ops[o];
+        const int kmax = op.kind == QS_OP_GATE ? qs::kMaxGateQubits : qs::kMaxChannelQubits;
+        if (op.kind != QS_OP_GATE && op.kind != QS_OP_CHANNEL)
+            return fail(QS_ERR_INVALID_ARGUMENT, "bad op kind");
+        if (op.kind == QS_OP_CHANNEL && op.k > qs::kMaxChannelQubits && op.k <= qs::kMaxGateQubits)
+            return fail(QS_ERR_NOT_SUPPORTED, "channels act on at most 2 qubits");
+        QS_CHECK(check_targets(m.n, op.k, op.targets, kmax));
+        const int D = 1 << op.k;
+        const int nm = op.kind == QS_OP_GATE ? 1 : op.n_mats;
+        if (nm < 1 || nm > 16 || (op.kind == QS_OP_GATE && op.n_mats != 1))
+            return fail(QS_ERR_INVALID_ARGUMENT, "bad matrix count");
+        if (op.mat_offset < 0 || op.mat_offset + int64_t(nm) * D * D > c->pool_len)
+            return fail(QS_ERR_INVALID_ARGUMENT, "matrix outside the pool");
+        m.ops[o].k = op.k;
+        for (int b = 0; b < 5; ++b) m.ops[o].q[b] = b < op.k ? op.targets[b] : 0;
+        m.kind[o] = op.kind;
+        if (op.kind == QS_OP_GATE) {
+            m.gate_mat[o] = pool + op.mat_offset;
+            qs::gram(D, m.gate_mat[o], G.data());
+            if (!qs::is_identity_multiple(D, G.data(), 1e-12, nullptr)) {
+                const double lam = qs::hermitian_min_eigenvalue(D, G.data());
+                m.gate_log_bound[o] = lam > 0 ? std::log(lam) : -1e300;
+            } else {
+                const double c0 = G[0].real();
+                m.gate_log_bound[o] = c0 > 0 ? std::log(c0) : -1e300;
+            }
+        } else {
+            ChannelInfo ci;
+            build_channel(op.k, op.targets, nm, pool + op.mat_offset, ci);
+            ci.op = o;
+            m.channel_of_op[o] = int(m.channels.size());
+            m.channels.push_back(std::move(ci));
+        }
+    }
+    return QS_OK;
+}
+
+struct BlockDesc {
+    qs::GateDesc g;
+    bool identity = false;
+    double log_bound = 0.0;
+};
+
+// Build a GateDesc for members (time-ordered) under the given per-op matrices.
+void build_block(const CircuitModel &m, const std::vector<int> &members,
+                 const std::vector<const cd *> &mats, std::vector<cd> &tmp, BlockDesc &out) {
+    int q[5];
+    const int k = qs::union_qubits(members, m.ops, q);
+    tmp.resize(size_t(1) << (2 * k));
+    qs::fused_matrix(k, q, members, m.ops, mats, tmp.data());
+    cd c;
+    out.identity = qs::is_identity_multiple(1 << k, tmp.data(), 1e-15, &c) && std::abs(c - cd(1.0)) < 1e-15;
+    out.g.k = k;
+    for (int b = 0; b < 5; ++b) out.g.t[b] = b < k ? q[b] : 0;
+    const int D = 1 << k;
+    for (int i = 0; i < D * D; ++i) out.g.m[i] = make_float2(float(tmp[i].real()), float(tmp[i].imag()));
+}
+
+// Event pairs around kernel launches, harvested lazily so the host never
+// waits on recent work.
+struct KernelTimer {
+    std::vector<hipEvent_t> ev;
+    std::vector<char> live;
+    int pos = 0;
+    double total_ms = 0.0;
+    int64_t count = 0;
+
+    ~KernelTimer() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    qs_status init(qs_state s, int cap) {
+        ev.assign(size_t(2) * cap, nullptr);
+        live.assign(cap, 0);
+        for (auto &e : ev) QS_HIP(s, hipEventCreate(&e));
+        return QS_OK;
+    }
+    qs_status harvest(qs_state s, int slot) {
+        if (!live[slot]) return QS_OK;
+        QS_HIP(s, hipEventSynchronize(ev[2 * slot + 1]));
+        float ms = 0.f;
+        QS_HIP(s, hipEventElapsedTime(&ms, ev[2 * slot], ev[2 * slot + 1]));
+        total_ms += ms;
+        ++count;
+        live[slot] = 0;
+        return QS_OK;
+    }
+    qs_status before(qs_state s) {
+        QS_CHECK(harvest(s, pos));
+        QS_HIP(s, hipEventRecord(ev[2 * pos], s->st));
+        return QS_OK;
+    }
+    qs_status after(qs_state s) {
+        QS_HIP(s, hipEventRecord(ev[2 * pos + 1], s->st));
+        live[pos] = 1;
+        pos = (pos + 1) % int(live.size());
+        return QS_OK;
+    }
+    qs_status finish(qs_state s) {
+        for (int i = 0; i < int(live.size()); ++i) QS_CHECK(harvest(s, i));
+        return QS_OK;
+    }
+};
+
+struct Runner {
+    qs_state s;
+    const CircuitModel &m;
+    const qs_traj_params &p;
+    qs_traj_result &res;
+    int max_fuse;
+    // delayed mode: default plan
+    std::vector<const cd *> default_mats;
+    std::vector<double> default_log;
+    std::vector<qs::Block> blocks;
+    std::vector<int> op_block;
+    std::vector<BlockDesc> block_desc;
+    // naive mode: gate blocks per inter-channel segment
+    std::vector<std::vector<BlockDesc>> naive_segments;
+    std::vector<cd> tmp;
+    std::deque<std::vector<cd>> slow_mats;
+    qs::ReadoutDesc ro;
+    double log_norm_bound = 0.0;
+    double pending_scale = 1.0;     // conventional method: 1/sqrt(p_i N) not yet applied
+    KernelTimer timer;
+    bool timing = false;
+    int64_t sample_fill = 0;        // samples buffered on the device
+    int64_t sample_first_traj = 0;  // trajectory index (relative) of the first buffered sample
+
+    Runner(qs_state s_, const CircuitModel &m_, const qs_traj_params &p_, qs_traj_result &r_)
+        : s(s_), m(m_), p(p_), res(r_) {
+        max_fuse = p.max_fuse > 0 ? p.max_fuse : kDefaultFuse;
+    }
+
+    void plan_delayed() {
+        const int n_ops = int(m.ops.size());
+        default_mats.assign(n_ops, nullptr);
+        default_log.assign(n_ops, 0.0);
+        for (int o = 0; o < n_ops; ++o) {
+            if (m.kind[o] == QS_OP_GATE) {
+                default_mats[o] = m.gate_mat[o];
+                default_log[o] = m.gate_log_bound[o];
+            } else {
+                const ChannelInfo &c = m.channels[m.channel_of_op[o]];
+                default_mats[o] = fast_pick_matrix(c, c.default_pick);
+                default_log[o] = c.log_pbar[c.default_pick];
+            }
+        }
+        blocks = qs::fuse_greedy(m.n, m.ops, max_fuse, &op_block);
+        block_desc.resize(blocks.size());
+        for (size_t b = 0; b < blocks.size(); ++b) {
+            build_block(m, blocks[b].ops, default_mats, tmp, block_desc[b]);
+            double lb = 0.0;
+            for (int o : blocks[b].ops) lb += default_log[o];
+            block_desc[b].log_bound = lb;
+        }
+    }
+
+    void plan_naive() {
+        // gates between consecutive channels, fused per segment
+        std::vector<int> seg;
+        std::vector<const cd *> mats(m.ops.size(), nullptr);
+        for (size_t o = 0; o < m.ops.size(); ++o) mats[o] = m.gate_mat[o];
+        auto close = [&]() {
+            std::vector<BlockDesc> out;
+            if (!seg.empty()) {
+                std::vector<qs::PlanOp> sub(seg.size());
+                std::vector<const cd *> submats(seg.size());
+                for (size_t i = 0; i < seg.size(); ++i) {
+                    sub[i] = m.ops[seg[i]];
+                    submats[i] = mats[seg[i]];
+                }
+                const auto bl = qs::fuse_greedy(m.n, sub, max_fuse);
+                for (const auto &b : bl) {
+                    BlockDesc d;
+                    int q[5];
+                    const int k = qs::union_qubits(b.ops, sub, q);
+                    tmp.resize(size_t(1) << (2 * k));
+                    qs::fused_matrix(k, q, b.ops, sub, submats, tmp.data());
+                    d.g.k = k;
+                    for (int j = 0; j < 5; ++j) d.g.t[j] = j < k ? q[j] : 0;
+                    const int D = 1 << k;
+                    for (int i = 0; i < D * D; ++i)
+                        d.g.m[i] = make_float2(float(tmp[i].real()), float(tmp[i].imag()));
+                    cd c;
+                    d.identity = qs::is_identity_multiple(D, tmp.data(), 1e-15, &c) && std::abs(c - cd(1.0)) < 1e-15;
+                    for (int o : b.ops) d.log_bound += m.gate_log_bound[seg[o]];
+                    out.push_back(d);
+                }
+            }
+            naive_segments.push_back(std::move(out));
+            seg.clear();
+        };
+        for (size_t o = 0; o < m.ops.size(); ++o) {
+            if (m.kind[o] == QS_OP_GATE) seg.push_back(int(o));
+            else close();
+        }
+        close();  // the tail after the last channel
+    }
+
+    qs_status launch_block(const BlockDesc &d) {
+        if (pending_scale != 1.0) {
+            BlockDesc sc = d;
+            const int D = 1 << d.g.k;
+            const float f = float(pending_scale);
+            for (int i = 0; i < D * D; ++i) sc.g.m[i] = make_float2(sc.g.m[i].x * f, sc.g.m[i].y * f);
+            sc.identity = false;
+            pending_scale = 1.0;
+            return launch_block(sc);
+        }
+        if (d.identity) return QS_OK;
+        if (timing) QS_CHECK(timer.before(s));
+        QS_CHECK(enqueue_desc(s, d.g));
+        if (timing) QS_CHECK(timer.after(s));
+        res.sweeps++;
+        res.gate_sweeps++;
+        res.gate_k_launches[d.g.k]++;
+        log_norm_bound += d.log_bound;
+        if (log_norm_bound < kRenormLogThreshold) {
+            QS_CHECK(renormalize_now(s));
+            res.sweeps += 2;
+            log_norm_bound = 0.0;
+        }
+        return QS_OK;
+    }
+
+    qs_status flush_samples() {
+        if (sample_fill == 0) return QS_OK;
+        QS_HIP(s, hipStreamSynchronize(s->st));
+        if (res.bitstrings)
+            QS_HIP(s, hipMemcpy(res.bitstrings + sample_first_traj * p.n_samples, s->samp_out,
+                                sizeof(uint64_t) * sample_fill, hipMemcpyDeviceToHost));
+        sample_fill = 0;
+        return QS_OK;
+    }
+
+    qs_status sample_trajectory(int64_t rel, uint32_t traj) {
+        if (p.n_samples <= 0) return QS_OK;
+        if (sample_fill + p.n_samples > int64_t(s->samp_cap)) QS_CHECK(flush_samples());
+        if (sample_fill == 0) sample_first_traj = rel;
+        QS_HIP(s, qs::launch_sample(s->amp, s->n, s->samp_sums, s->samp_incl, p.seed, traj,
+                                    p.circuit_id, p.n_samples, ro, s->samp_out + sample_fill,
+                                    s->samp_norm, s->st));
+        res.sweeps += 1;
+        sample_fill += p.n_samples;
+        return QS_OK;
+    }
+
+    qs_status run_delayed(int64_t rel, uint32_t traj) {
+        const int nch = int(m.channels.size());
+        // steps 1-11 of Algorithm 2 for every channel: state-independent
+        std::vector<int> pick(nch, -1);
+        std::vector<double> resid(nch, 0.0);
+        std::vector<int> slow_ops;
+        std::vector<std::pair<int, const cd *>> overrides;  // (op, matrix)
+        std::vector<double> override_log;
+        for (int c = 0; c < nch; ++c) {
+            const ChannelInfo &ci = m.channels[c];
+            const double r = qs::philox_uniform(p.seed, channel_draw_index(uint32_t(c)), traj,
+                                                p.circuit_id, qs::kStreamChannel);
+            pick[c] = select_fast(ci, r, &resid[c]);
+            if (pick[c] < 0) {
+                slow_ops.push_back(ci.op);
+            } else if (pick[c] != ci.default_pick) {
+                overrides.emplace_back(ci.op, fast_pick_matrix(ci, pick[c]));
+            }
+        }
+        int8_t *choices = res.kraus_choices ? res.kraus_choices + rel * nch : nullptr;
+        int8_t *paths = res.kraus_paths ? res.kraus_paths + rel * nch : nullptr;
+        for (int c = 0; c < nch; ++c) {
+            if (choices) choices[c] = int8_t(pick[c]);
+            if (paths) paths[c] = pick[c] < 0 ? 1 : 0;
+        }
+        if (res.n_slow) res.n_slow[rel] = int32_t(slow_ops.size());
+
+        QS_CHECK(restore_home(s));
+        QS_HIP(s, qs::launch_set_basis(s->amp, s->n, 0, s->st));
+        log_norm_bound = 0.0;
+
+        std::vector<const cd *> mats = default_mats;
+        std::vector<char> dirty(blocks.size(), 0);
+        for (auto &ov : overrides) {
+            mats[ov.first] = ov.second;
+            dirty[op_block[ov.first]] = 1;
+        }
+        slow_mats.clear();
+        const int n_ops = int(m.ops.size());
+        int seg_start = 0;
+        int slow_idx = 0;
+        BlockDesc bd;
+        std::vector<int> sub;
+        for (;;) {
+            const int seg_end = slow_idx < int(slow_ops.size()) ? slow_ops[slow_idx] : n_ops;
+            for (size_t b = 0; b < blocks.size(); ++b) {
+                const auto &ops = blocks[b].ops;
+                auto lo = std::lower_bound(ops.begin(), ops.end(), seg_start);
+                auto hi = std::lower_bound(lo, ops.end(), seg_end);
+                if (lo == hi) continue;
+                const bool whole = (lo == ops.begin() && hi == ops.end());
+                if (whole && !dirty[b]) {
+                    QS_CHECK(launch_block(block_desc[b]));
+                    continue;
+                }
+                sub.assign(lo, hi);
+                build_block(m, sub, mats, tmp, bd);
+                double lb = 0.0;
+                for (int o : sub) {
+                    if (m.kind[o] == QS_OP_GATE) lb += m.gate_log_bound[o];
+                    else {
+                        const ChannelInfo &ci = m.channels[m.channel_of_op[o]];
+                        const int pk = pick[m.channel_of_op[o]];
+                        lb += pk >= 0 ? ci.log_pbar[pk] : 0.0;
+                    }
+                }
+                bd.log_bound = lb;
+                QS_CHECK(launch_block(bd));
+            }
+            if (seg_end == n_ops) break;
+            // steps 12-20 for the channel at seg_end
+            const int c = m.channel_of_op[seg_end];
+            const ChannelInfo &ci = m.channels[c];
+            QS_CHECK(device_rdm(s, ci.k, ci.ts));
+            res.sweeps++;
+            double pp = 0.0, N = 0.0;
+            const int pk = select_slow(ci, s->red_host, resid[c], &pp, &N);
+            if (!(N > 0.0) || !std::isfinite(N)) return fail(QS_ERR_ZERO_NORM, "state has zero norm");
+            if (!(pp > 0.0)) return fail(QS_ERR_ZERO_NORM, "chosen Kraus operator has zero weight");
+            pick[c] = pk;
+            if (choices) choices[c] = int8_t(pk);
+            const int D = 1 << ci.k;
+            slow_mats.emplace_back(size_t(D) * D);
+            const double f = 1.0 / std::sqrt(pp * N);
+            const cd *K = ci.kraus + size_t(pk) * D * D;
+            for (int e = 0; e < D * D; ++e) slow_mats.back()[e] = K[e] * f;
+            mats[seg_end] = slow_mats.back().data();
+            dirty[op_block[seg_end]] = 1;
+            log_norm_bound = 0.0;  // renormalised by the folded 1/sqrt(p N)
+            seg_start = seg_end;
+            ++slow_idx;
+        }
+        return QS_OK;
+    }
+
+    qs_status run_naive(int64_t rel, uint32_t traj) {
+        const int nch = int(m.channels.size());
+        int8_t *choices = res.kraus_choices ? res.kraus_choices + rel * nch : nullptr;
+        int8_t *paths = res.kraus_paths ? res.kraus_paths + rel * nch : nullptr;
+        QS_CHECK(restore_home(s));
+        QS_HIP(s, qs::launch_set_basis(s->amp, s->n, 0, s->st));
+        log_norm_bound = 0.0;
+        pending_scale = 1.0;
+        for (int c = 0; c <= nch; ++c) {
+            for (const auto &d : naive_segments[c]) QS_CHECK(launch_block(d));
+            if (c == nch) break;
+            const ChannelInfo &ci = m.channels[c];
+            const double r = qs::philox_uniform(p.seed, channel_draw_index(uint32_t(c)), traj,
+                                                p.circuit_id, qs::kStreamChannel);
+            int pk = -1;
+            double accepted = 0.0;
+            QS_CHECK(naive_channel(s, ci, r, &pk, &accepted));
+            res.sweeps += pk + 1;
+            if (!(accepted > 0.0)) return fail(QS_ERR_ZERO_NORM, "chosen Kraus operator has zero weight");
+            if (choices) choices[c] = int8_t(pk);
+            if (paths) paths[c] = 1;
+            // |psi> <- K_i |psi> / sqrt(p_i): fold 1/sqrt(||K_i psi||^2) into the next block
+            pending_scale /= std::sqrt(accepted);
+            if (pending_scale > 1e15 || pending_scale < 1e-15) {
+                QS_HIP(s, qs::launch_scale(s->amp, s->n, float(pending_scale), s->st));
+                res.sweeps++;
+                pending_scale = 1.0;
+            }
+        }
+        if (res.n_slow) res.n_slow[rel] = nch;
+        return QS_OK;
+    }
+
+    qs_status run() {
+        QS_CHECK(fill_readout(m.n, p.p0to1, p.p1to0, ro));
+        if (p.n_samples > 0) {
+            const int64_t total = p.n_traj * int64_t(p.n_samples);
+            const int64_t cap = std::max<int64_t>(p.n_samples, std::min<int64_t>(total, int64_t(1) << 22));
+            QS_CHECK(ensure_sampling(s, size_t(cap)));
+        }
+        QS_CHECK(ensure_reduce(s));
+        timing = (p.flags & QS_TRAJ_TIME_KERNELS) != 0;
+        if (timing) QS_CHECK(timer.init(s, 4096));
+        if (p.mode == QS_KRAUS_DELAYED) plan_delayed();
+        else plan_naive();
+        for (int64_t rel = 0; rel < p.n_traj; ++rel) {
+            const uint32_t traj = uint32_t(p.traj_offset + rel);
+            if (p.mode == QS_KRAUS_DELAYED) QS_CHECK(run_delayed(rel, traj));
+            else QS_CHECK(run_naive(rel, traj));
+            QS_CHECK(sample_trajectory(rel, traj));
+        }
+        QS_CHECK(flush_samples());
+        if (timing) {
+            QS_CHECK(timer.finish(s));
+            res.gate_kernel_ms = timer.total_ms;
+            res.gate_kernel_launches = timer.count;
+        }
+        if ((p.flags & QS_TRAJ_RETURN_STATE) && res.final_state && p.n_traj > 0) {
+            QS_HIP(s, hipStreamSynchronize(s->st));
+            QS_HIP(s, hipMemcpy(res.final_state, s->amp, sizeof(float2) << s->n, hipMemcpyDeviceToHost));
+        }
+        QS_CHECK(restore_home(s));
+        QS_HIP(s, hipStreamSynchronize(s->st));
+        return QS_OK;
+    }
+};
+
+}  // namespace
+
+qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_params *p,
+                              qs_traj_result *r) {
+    const auto t0 = std::chrono::steady_clock::now();
+    QS_CHECK(check_handle(s));
+    if (!c || !p || !r) return fail(QS_ERR_INVALID_ARGUMENT, "null argument");
+    if (c->n_qubits != s->n) return fail(QS_ERR_INVALID_ARGUMENT, "circuit and state qubit counts differ");
+    if (p->n_traj < 0 || p->traj_offset < 0 || p->traj_offset + p->n_traj > (int64_t(1) << 32))
+        return fail(QS_ERR_INVALID_ARGUMENT, "trajectory range outside 32-bit counters");
+    if (p->mode != QS_KRAUS_DELAYED && p->mode != QS_KRAUS_NAIVE)
+        return fail(QS_ERR_INVALID_ARGUMENT, "bad mode");
+    if (p->max_fuse < 0 || p->max_fuse > qs::kMaxGateQubits)
+        return fail(QS_ERR_INVALID_ARGUMENT, "max_fuse outside 0..5");
+    if (p->n_samples < 0) return fail(QS_ERR_INVALID_ARGUMENT, "negative sample count");
+    if (int64_t(p->n_samples) * int64_t(s->n) > (int64_t(1) << 32))
+        return fail(QS_ERR_INVALID_ARGUMENT, "readout counter would overflow");
+    CircuitModel m;
+    QS_CHECK(build_model(c, m));
+    QS_CHECK(flush_pending(s));
+    r->sweeps = 0;
+    r->gate_sweeps = 0;
+    r->gate_kernel_ms = 0.0;
+    r->gate_kernel_launches = 0;
+    for (int i = 0; i < 6; ++i) r->gate_k_launches[i] = 0;
+    Runner run(s, m, *p, *r);
+    const qs_status st = run.run();
+    r->host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}
+
+qs_status qs_fusion_plan(const qs_circuit *c, int max_fuse, int32_t *n_blocks_out,
+                         int32_t *block_k, int32_t *block_targets, double *block_mats,
+                         int32_t *op_block) {
+    if (!c || !n_blocks_out || !block_k || !block_targets || !block_mats || !op_block)
+        return fail(QS_ERR_INVALID_ARGUMENT, "null argument");
+    if (max_fuse < 1 || max_fuse > qs::kMaxGateQubits)
+        return fail(QS_ERR_INVALID_ARGUMENT, "max_fuse outside 1..5");
+    if (c->n_qubits < 1 || c->n_qubits > qs::kMaxQubits)
+        return fail(QS_ERR_INVALID_ARGUMENT, "n out of range");
+    CircuitModel m;
+    QS_CHECK(build_model(c, m));
+    if (!m.channels.empty()) return fail(QS_ERR_INVALID_ARGUMENT, "fusion plan takes gates only");
+    std::vector<int> ob;
+    const auto blocks = qs::fuse_greedy(m.n, m.ops, max_fuse, &ob);
+    std::vector<cd> tmp(1024);
+    for (size_t b = 0; b < blocks.size(); ++b) {
+        block_k[b] = blocks[b].k;
+        for (int j = 0; j < 5; ++j) block_targets[5 * b + j] = j < blocks[b].k ? blocks[b].q[j] : 0;
+        qs::fused_matrix(blocks[b].k, blocks[b].q, blocks[b].ops, m.ops, m.gate_mat, tmp.data());
+        const int D = 1 << blocks[b].k;
+        double *dst = block_mats + b * 2048;
+        for (int i = 0; i < 2048; ++i) dst[i] = 0.0;
+        for (int i = 0; i < D * D; ++i) {
+            dst[2 * i] = tmp[i].real();
+            dst[2 * i + 1] = tmp[i].imag();
+        }
+    }
+    for (size_t o = 0; o < ob.size(); ++o) op_block[o] = ob[o];
+    *n_blocks_out = int32_t(blocks.size());
+    return QS_OK;
+}
+
+}  // extern "C"

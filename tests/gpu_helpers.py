@@ -1,0 +1,42 @@
+"""Comparison helpers for the GPU parity tests (no simulation arithmetic)."""
+
+import numpy as np
+
+# Amplitudes: relative L2 distance of the normalised states.
+AMP_TOL = 1e-5
+# Threshold ties (state-independent bound comparisons are FP64 on both sides).
+FAST_TIE = 1e-12
+# Ties on comparisons against inner products of a complex64 state.
+SLOW_TIE = 1e-5
+# Sampling ties: |u N - C(x)| / N below this counts as a tie.
+SAMPLE_TIE = 1e-5
+
+
+def rel_l2(gpu, ref) -> float:
+    g = np.asarray(gpu, dtype=np.complex128)
+    r = np.asarray(ref, dtype=np.complex128)
+    g = g / np.linalg.norm(g)
+    r = r / np.linalg.norm(r)
+    return float(np.linalg.norm(g - r))
+
+
+def random_state(n, rng):
+    v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    v /= np.linalg.norm(v)
+    return v.astype(np.complex64)
+
+
+def compare_choices(gpu_choices, orc_res):
+    """Per-trajectory channel choices: equal up to the first threshold tie.
+    Returns (compared, ties)."""
+    oc = orc_res["choices"]
+    mf = orc_res["margin_fast"]
+    ms = orc_res["margin_slow"]
+    compared = 0
+    for j in range(len(oc)):
+        if int(gpu_choices[j]) != int(oc[j]):
+            tie = mf[j] < FAST_TIE or ms[j] < SLOW_TIE
+            assert tie, (j, int(gpu_choices[j]), int(oc[j]), mf[j], ms[j])
+            return compared, 1
+        compared += 1
+    return compared, 0

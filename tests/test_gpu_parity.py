@@ -1,0 +1,269 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Bars: amplitudes within 1e-5 relative L2 (normalised states); FP64 norms to
+rounding; Kraus choices and bitstrings bit-exact away from threshold ties.
+"""
+
+import math
+
+import torch  # noqa: F401  (imported at collection: the first import can be slow)
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_helpers import (AMP_TOL, SAMPLE_TIE, compare_choices, random_state, rel_l2)
+
+pytestmark = pytest.mark.gpu
+
+TARGET_PATTERNS = {
+    1: [[0], [1], [5], [6], [-1]],
+    2: [[0, 1], [1, 0], [0, -1], [3, 7], [-2, -1], [6, 9]],
+    3: [[0, 1, 2], [2, 0, 5], [6, 7, 8], [0, 6, -1], [4, 5, 6]],
+    4: [[0, 1, 2, 3], [3, 1, 0, 2], [6, 7, 8, 9], [0, 3, 7, -1], [5, 6, -2, -1]],
+    5: [[0, 1, 2, 3, 4], [4, 2, 0, 1, 3], [6, 7, 8, 9, 10], [0, 2, 6, 9, -1], [1, 5, 7, -2, -1]],
+}
+
+
+def _resolve(targets, n):
+    return [t if t >= 0 else n + t for t in targets]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("n", [11, 16, 21])
+def test_apply_fused_gate_parity(qs, orc, k, n):
+    rng = np.random.default_rng(1000 * k + n)
+    psi0 = random_state(n, rng)
+    with qs.State(n) as st:
+        for pat in TARGET_PATTERNS[k]:
+            t = _resolve(pat, n)
+            U = W.random_matrix(k, rng)
+            qs.qs_load_state_from_host(st.h, psi0)
+            qs.qs_apply_fused_gate(st.h, t, U)
+            got = qs.qs_copy_state_to_host(st.h)
+            ref = psi0.astype(np.complex128)
+            orc.apply_matrix(ref, t, U)
+            err = rel_l2(got, ref)
+            assert err < AMP_TOL, (k, n, t, err)
+
+
+def test_norm_parity_and_determinism(qs, orc):
+    rng = np.random.default_rng(5)
+    for n in (3, 12, 20, 23):
+        psi = (random_state(n, rng) * np.float32(1.7)).astype(np.complex64)
+        with qs.State(n) as st:
+            qs.qs_load_state_from_host(st.h, psi)
+            a = qs.qs_norm(st.h)
+            b = qs.qs_norm(st.h)
+            assert a == b
+            ref = orc.norm_sq(psi.astype(np.complex128))
+            assert abs(a - ref) <= 1e-12 * ref
+
+
+def test_circuit_parity(qs, orc):
+    for n, ng, kmax, seed in [(10, 200, 3, 1), (14, 150, 5, 2), (17, 120, 4, 3)]:
+        c = W.random_gate_circuit(n, ng, seed=seed, max_k=kmax)
+        with qs.State(n) as st:
+            for op in c.ops:
+                qs.qs_apply_fused_gate(st.h, list(op.qubits), op.mats[0])
+            got = qs.qs_copy_state_to_host(st.h)
+        ref = orc.simulate(c)
+        assert rel_l2(got, ref) < AMP_TOL
+
+
+def test_invalid_arguments_leave_state(qs):
+    rng = np.random.default_rng(2)
+    psi = random_state(6, rng)
+    with qs.State(6) as st:
+        qs.qs_load_state_from_host(st.h, psi)
+        for t in ([6], [1, 1], [-1], [0, 1, 2, 3, 4, 5]):
+            with pytest.raises(qs.QsError) as e:
+                qs.qs_apply_fused_gate(st.h, t, np.eye(1 << len(t)))
+            assert e.value.code == qs.QS_ERR_INVALID_ARGUMENT
+        bad = np.eye(2, dtype=np.complex128)
+        bad[0, 0] = np.nan
+        with pytest.raises(qs.QsError):
+            qs.qs_apply_fused_gate(st.h, [0], bad)
+        with pytest.raises(qs.QsError) as e:
+            qs.qs_apply_channel(st.h, [0, 1, 2], [np.eye(8)], 0, 0, 0)
+        assert e.value.code == qs.QS_ERR_NOT_SUPPORTED
+        got = qs.qs_copy_state_to_host(st.h)
+        assert np.array_equal(got, psi)
+
+
+def test_zero_norm_reported(qs):
+    with qs.State(4) as st:
+        P1 = np.diag([0.0, 1.0]).astype(np.complex128)
+        qs.qs_apply_fused_gate(st.h, [2], P1)  # annihilates |0000>
+        assert qs.qs_norm(st.h) == 0.0
+        with pytest.raises(qs.QsError) as e:
+            qs.qs_sample_measurements(st.h, 0, 0, 4)
+        assert e.value.code == qs.QS_ERR_ZERO_NORM
+
+
+@pytest.mark.parametrize("n", [1, 5, 10, 13, 18])
+def test_sampling_parity(qs, orc, n):
+    rng = np.random.default_rng(40 + n)
+    psi = random_state(n, rng)
+    e0 = rng.uniform(0, 0.1, size=n)
+    e1 = rng.uniform(0, 0.1, size=n)
+    ns = 3000
+    with qs.State(n) as st:
+        qs.qs_load_state_from_host(st.h, psi)
+        got = qs.qs_sample_measurements(st.h, 17, 3, ns, e0, e1)
+        got_plain = qs.qs_sample_measurements(st.h, 17, 3, ns)
+    ref, margins = orc.sample(psi.astype(np.complex128), 17, 3, 0, ns, e0, e1)
+    ref_plain, _ = orc.sample(psi.astype(np.complex128), 17, 3, 0, ns)
+    mism = np.nonzero(got != ref)[0]
+    assert np.all(margins[mism] < SAMPLE_TIE), (mism[:5], margins[mism[:5]])
+    assert len(mism) <= max(2, ns // 500)
+    mism = np.nonzero(got_plain != ref_plain)[0]
+    assert np.all(margins[mism] < SAMPLE_TIE)
+
+
+def test_sampling_ghz_rule(qs, orc):
+    n = 20
+    psi = np.zeros(1 << n, dtype=np.complex64)
+    psi[0] = psi[-1] = 1 / math.sqrt(2)
+    with qs.State(n) as st:
+        qs.qs_load_state_from_host(st.h, psi)
+        got = qs.qs_sample_measurements(st.h, 11, 2, 400)
+    for s, x in enumerate(got):
+        u = orc.draw(11, s, 2, 0, 1)
+        assert int(x) == (0 if u < 0.5 else (1 << n) - 1)
+
+
+def _imperative_run(qs, c, seed, traj, mode, n_samples=0, e0=None, e1=None):
+    choices, paths = [], []
+    with qs.State(c.n) as st:
+        ch = 0
+        for op in c.ops:
+            if op.kind == W.GATE:
+                qs.qs_apply_fused_gate(st.h, list(op.qubits), op.mats[0])
+            else:
+                pick, path = qs.qs_apply_channel(st.h, list(op.qubits), op.mats, seed, traj, ch,
+                                                 mode)
+                choices.append(pick)
+                paths.append(path)
+                ch += 1
+        state = qs.qs_copy_state_to_host(st.h)
+        samples = qs.qs_sample_measurements(st.h, seed, traj, n_samples, e0, e1) if n_samples else None
+    return np.array(choices), np.array(paths), state, samples
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["delayed", "naive"])
+def test_channel_parity_imperative(qs, orc, mode):
+    c = W.random_noisy_circuit(9, 25, seed=4, p_dep=0.05, gamma=0.08, lam=0.05)
+    m = orc.Marshalled(c)
+    ties = 0
+    for traj in range(6):
+        ch, paths, state, samples = _imperative_run(qs, c, 7, traj, mode, n_samples=50)
+        ref = orc.run_trajectory(c, traj, mode=mode, seed=7, n_samples=50, return_state=True,
+                                 marshalled=m)
+        _, tie = compare_choices(ch, ref)
+        ties += tie
+        if tie:
+            continue
+        if mode == 0:
+            assert np.array_equal(paths, ref["paths"])
+        assert rel_l2(state, ref["state"]) < AMP_TOL
+        mism = np.nonzero(samples != ref["samples"])[0]
+        assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
+    assert ties <= 1
+
+
+def _driver(qs, c, n_traj, mode, seed=0, traj_offset=0, n_samples=0, e0=None, e1=None,
+            return_state=False, max_fuse=0, circuit_id=0):
+    with qs.State(c.n) as st:
+        return qs.qs_run_trajectories(st.h, c, n_traj, seed=seed, traj_offset=traj_offset,
+                                      mode=mode, n_samples=n_samples, p0to1=e0, p1to0=e1,
+                                      return_state=return_state, max_fuse=max_fuse,
+                                      circuit_id=circuit_id)
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["delayed", "naive"])
+@pytest.mark.parametrize("max_fuse", [2, 4, 5])
+def test_driver_parity_noisy_grid(qs, orc, mode, max_fuse):
+    """A 4x3 grid with the benchmark's noise kinds (depolarizing, amplitude
+    damping, readout) at strengths that make inner products frequent."""
+    c = W.grid_circuit(4, 3, 8, p_dep=0.02, gamma=0.03, seed=5)
+    e0, e1 = W.readout_arrays(12, 0.02, 0.05)
+    m = orc.Marshalled(c)
+    ties = 0
+    for t in range(5):
+        got = _driver(qs, c, 1, mode, seed=3, traj_offset=t, n_samples=40, e0=e0, e1=e1,
+                      return_state=True, max_fuse=max_fuse)
+        ref = orc.run_trajectory(c, t, mode=mode, seed=3, n_samples=40, e0=e0, e1=e1,
+                                 return_state=True, marshalled=m)
+        _, tie = compare_choices(got["choices"][0], ref)
+        ties += tie
+        if tie:
+            continue
+        if mode == 0:
+            assert np.array_equal(got["paths"][0], ref["paths"])
+            assert got["n_slow"][0] == int(np.sum(ref["paths"]))
+        assert rel_l2(got["state"], ref["state"]) < AMP_TOL
+        mism = np.nonzero(got["samples"][0] != ref["samples"])[0]
+        assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
+    assert ties <= 1
+
+
+def test_driver_chain12_workload(qs, orc):
+    """The 12-qubit chain workload: 100 trajectories x 1000 samples."""
+    w = W.chain12_workload()
+    c = w.circuit
+    got = _driver(qs, c, w.n_traj, 0, seed=w.seed, n_samples=w.n_samples, max_fuse=w.max_fuse)
+    m = orc.Marshalled(c)
+    sample_mism = 0
+    for t in range(w.n_traj):
+        ref = orc.run_trajectory(c, t, mode=0, seed=w.seed, n_samples=w.n_samples, marshalled=m)
+        _, tie = compare_choices(got["choices"][t], ref)
+        assert tie == 0
+        assert np.all(got["paths"][t] == 0)  # depolarizing only: never needs inner products
+        mism = np.nonzero(got["samples"][t] != ref["samples"])[0]
+        assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
+        sample_mism += len(mism)
+    assert sample_mism <= 10
+
+
+def test_driver_delayed_equals_naive_for_depolarizing(qs):
+    c = W.chain_circuit(10, 6, p_dep=0.05, seed=2)
+    a = _driver(qs, c, 8, 0, seed=1, n_samples=20)
+    b = _driver(qs, c, 8, 1, seed=1, n_samples=20)
+    assert np.array_equal(a["choices"], b["choices"])
+    mism = np.sum(a["samples"] != b["samples"])
+    assert mism <= 2
+
+
+def test_driver_resume_equals_uninterrupted(qs):
+    c = W.grid_circuit(3, 3, 6, p_dep=0.05, gamma=0.05, seed=1)
+    full = _driver(qs, c, 12, 0, seed=9, n_samples=5)
+    a = _driver(qs, c, 5, 0, seed=9, n_samples=5)
+    b = _driver(qs, c, 7, 0, seed=9, traj_offset=5, n_samples=5)
+    assert np.array_equal(full["choices"], np.concatenate([a["choices"], b["choices"]]))
+    assert np.array_equal(full["samples"], np.concatenate([a["samples"], b["samples"]]))
+
+
+def test_driver_deterministic(qs):
+    c = W.grid_circuit(3, 4, 6, p_dep=0.01, gamma=0.05, seed=4)
+    a = _driver(qs, c, 6, 0, seed=2, n_samples=30, return_state=True)
+    b = _driver(qs, c, 6, 0, seed=2, n_samples=30, return_state=True)
+    assert np.array_equal(a["choices"], b["choices"])
+    assert np.array_equal(a["samples"], b["samples"])
+    assert np.array_equal(a["state"], b["state"])
+
+
+def test_torch_buffer_and_stream(qs, orc):
+    import torch
+
+    n = 14
+    c = W.random_gate_circuit(n, 40, seed=12, max_k=3)
+    buf = torch.zeros(1 << n, dtype=torch.complex64, device="cuda")
+    stream = torch.cuda.Stream()
+    with qs.State(n, buf.data_ptr(), buf.numel() * 8, stream.cuda_stream) as st:
+        for op in c.ops:
+            qs.qs_apply_fused_gate(st.h, list(op.qubits), op.mats[0])
+        qs.qs_flush(st.h)
+        stream.synchronize()
+        got = buf.cpu().numpy()
+    assert rel_l2(got, orc.simulate(c)) < AMP_TOL
