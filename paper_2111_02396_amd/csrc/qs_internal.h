@@ -30,6 +30,37 @@ struct GateDesc {
     float2 m[32 * 32];  // leading (2^k)^2 entries used, row-major
 };
 
+struct TargetArgs {
+    int t[kMaxGateQubits];
+};
+
+// Tiled sweeps: a tile is 2^tb amplitudes whose index bits are pos[0..tb-1]
+// (ascending, always starting with bits 0..5); the gates g[0..n_gates-1]
+// act in order on tile-local bit positions lt[] (ascending), with their
+// matrices (2^k x 2^k complex64, rows/columns in lt order) read from device
+// address `mat` and staged in LDS at float2 offset `lofs` of a region of
+// mat_total entries.
+constexpr int kMaxTileBits = 13;
+constexpr int kMaxTileGates = 48;
+constexpr int kTileMinQubits = 10;
+constexpr int kTileMatBudget = 4096;  // float2 of matrices staged per launch (32 KiB)
+
+struct TileGate {
+    int k;
+    int lt[kMaxGateQubits];
+    int lofs;
+    int pad;
+    const float2 *mat;
+};
+
+struct TileArgs {
+    int tb;
+    int pos[kMaxTileBits];
+    int n_gates;
+    int mat_total;
+    TileGate g[kMaxTileGates];
+};
+
 struct ReadoutDesc {
     int enabled;
     double e0[kMaxQubits];  // P(read 1 | 0)
@@ -42,10 +73,14 @@ hipError_t launch_set_basis(float2 *amp, int n, uint64_t index, hipStream_t st);
 
 hipError_t launch_scale(float2 *amp, int n, float s, hipStream_t st);
 
-// Algorithm 1 for one fused gate.  mat_dev: device copy of g.m, required
-// when g.k == 5 (too large for kernel arguments), ignored otherwise.
+// Algorithm 1 for one fused gate.  mat_dev: device copy of g.m
+// ((2^k)^2 complex64, ascending-target order).  Gates with a target below 6
+// go through the tiled path, the others through the direct path.
 hipError_t launch_apply_gate(float2 *amp, int n, const GateDesc &g, const float2 *mat_dev,
                              hipStream_t st);
+
+// Several gates in one sweep: every gate's targets are bits of the tile.
+hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t st);
 
 // FP64 reductions with a fixed tree.  Each writes `width` doubles to out_dev.
 // norm: width 1 (sum |psi|^2).

@@ -1,10 +1,11 @@
 // gfx950 kernels for the state-vector hot path.
 //
-//  * gate application (Section 3.1, Algorithm 1): one 2^k-amplitude index
-//    group per work-item; consecutive work-items own consecutive groups, so
-//    with the target bits removed the loads of a wavefront are contiguous;
-//    the fused matrix travels in the kernel arguments (k <= 4, read through
-//    scalar loads) or in device memory (k = 5);
+//  * gate application (Section 3.1, Algorithm 1), k <= 5: a direct path
+//    for gates whose targets are all >= 6 (one index group per work-item,
+//    64-amplitude rows per wavefront load) and a tiled path that stages
+//    2^tb-amplitude tiles in LDS for gates touching bits 0..5 and for
+//    several gates per sweep; fused matrices always sit in LDS and are read
+//    with wave-uniform (broadcast) addresses;
 //  * FP64 reductions (norm, two-qubit reduced density matrix, the
 //    conventional method's trial norm) with a fixed grid and a fixed
 //    butterfly/tree order, so results are bit-identical run to run;
@@ -24,9 +25,6 @@ struct GateArgs {
     int t[K];
 };
 
-struct TargetArgs {
-    int t[kMaxGateQubits];
-};
 
 // Insert a zero bit at each ascending target position.
 template <int K, typename Idx>
@@ -59,49 +57,155 @@ __device__ __forceinline__ float2 cmac(float2 acc, float2 a, float2 b) {
 
 // ---------------------------------------------------------------- gates
 
+// Direct path (every target >= 6): one 2^K-amplitude group per work-item;
+// the low six index bits are lane bits, so each load instruction of a
+// wavefront reads 64 consecutive amplitudes (512 B).  A work-item issues its
+// group's loads before the workgroup stages the matrix.  K <= 2 matrices are
+// read with wave-uniform addresses straight from memory (scalar loads);
+// larger ones are staged once per workgroup in LDS and read as broadcasts.
 template <int K, typename Idx>
-__global__ __launch_bounds__(kBlock) void apply_gate_args(float2 *__restrict__ amp, Idx groups,
-                                                          GateArgs<K> a) {
+__global__ __launch_bounds__(kBlock) void apply_direct(float2 *__restrict__ amp, Idx groups,
+                                                       const float2 *__restrict__ mat,
+                                                       TargetArgs ta) {
     constexpr int D = 1 << K;
+    constexpr bool kLds = K >= 3;
+    __shared__ float2 sm[kLds ? D * D : 1];
     const Idx stride = Idx(gridDim.x) * Idx(kBlock);
-    for (Idx g = Idx(blockIdx.x) * Idx(kBlock) + Idx(threadIdx.x); g < groups; g += stride) {
-        const Idx base = spread_index<K, Idx>(g, a.t);
-        float2 v[D];
+    Idx g = Idx(blockIdx.x) * Idx(kBlock) + Idx(threadIdx.x);
+    float2 v[D];
+    if (g < groups) {
+        const Idx base = spread_index<K, Idx>(g, ta.t);
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = amp[base + local_offset<K, Idx>(j, a.t)];
-#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = amp[base + local_offset<K, Idx>(j, ta.t)];
+    }
+    if (kLds) {
+        for (int i = threadIdx.x; i < D * D; i += kBlock) sm[i] = mat[i];
+        __syncthreads();
+    }
+    const float2 *m = kLds ? sm : mat;
+    for (;;) {
+        if (g >= groups) break;
+        const Idx base = spread_index<K, Idx>(g, ta.t);
+#pragma unroll(K >= 3 ? 2 : D)
         for (int j = 0; j < D; ++j) {
             float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int l = 0; l < D; ++l) acc = cmac(acc, a.m[j * D + l], v[l]);
-            amp[base + local_offset<K, Idx>(j, a.t)] = acc;
+            for (int l = 0; l < D; ++l) acc = cmac(acc, m[j * D + l], v[l]);
+            amp[base + local_offset<K, Idx>(j, ta.t)] = acc;
         }
+        g += stride;
+        if (g >= groups) break;
+        const Idx nb = spread_index<K, Idx>(g, ta.t);
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = amp[nb + local_offset<K, Idx>(j, ta.t)];
     }
 }
 
-// k = 5: the 32x32 matrix (8 KiB) is staged once per workgroup in LDS and
-// read with wave-uniform addresses (broadcast).
-template <typename Idx>
-__global__ __launch_bounds__(kBlock) void apply_gate5_lds(float2 *__restrict__ amp, Idx groups,
-                                                          const float2 *__restrict__ mat,
-                                                          TargetArgs ta) {
-    constexpr int K = 5, D = 32;
-    __shared__ float2 sm[D * D];
-    for (int i = threadIdx.x; i < D * D; i += kBlock) sm[i] = mat[i];
-    __syncthreads();
-    const Idx stride = Idx(gridDim.x) * Idx(kBlock);
-    for (Idx g = Idx(blockIdx.x) * Idx(kBlock) + Idx(threadIdx.x); g < groups; g += stride) {
-        const Idx base = spread_index<K, Idx>(g, ta.t);
+// One gate on a tile held in LDS: every group of the tile is owned by one
+// work-item, which gathers its 2^K amplitudes, multiplies, and writes back
+// in place.
+template <int K>
+__device__ __forceinline__ void tile_gate(float2 *__restrict__ sd, const float2 *__restrict__ sm,
+                                          const int *lt, int tb) {
+    constexpr int D = 1 << K;
+    int off[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) off[j] = local_offset<K, int>(j, lt);
+    const int groups = 1 << (tb - K);
+    for (int gg = threadIdx.x; gg < groups; gg += kBlock) {
+        const int lb = spread_index<K, int>(gg, lt);
         float2 v[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = amp[base + local_offset<K, Idx>(j, ta.t)];
-#pragma unroll 4
+        for (int j = 0; j < D; ++j) v[j] = sd[lb + off[j]];
+#pragma unroll(K >= 3 ? 2 : D)
         for (int j = 0; j < D; ++j) {
             float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
             for (int l = 0; l < D; ++l) acc = cmac(acc, sm[j * D + l], v[l]);
-            amp[base + local_offset<K, Idx>(j, ta.t)] = acc;
+            sd[lb + off[j]] = acc;
         }
+    }
+}
+
+// Tiled path: persistent workgroups stage every gate matrix of the launch in
+// LDS once, then loop over tiles of 2^TB amplitudes -- the index bits in
+// a.pos, bits 0..5 first, so each wavefront load is a 512 B row.  A tile is
+// written to LDS, the next tile's loads are issued into registers, the
+// gates run on the LDS copy in order, and the tile is written back: any
+// number of gates inside the tile cost one HBM read and one write.
+template <int TB, typename Idx>
+__global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, Idx n_tiles,
+                                                     TileArgs a) {
+    constexpr int E = 1 << TB;
+    constexpr int R = E / kBlock;
+    extern __shared__ float2 smem[];
+    float2 *sd = smem;
+    float2 *sm = smem + E;
+    Idx tile = blockIdx.x;
+    if (tile >= n_tiles) return;  // uniform over the workgroup
+    Idx off_tid = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if ((threadIdx.x >> b) & 1) off_tid |= Idx(1) << a.pos[b];
+    Idx off_r[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        Idx o = 0;
+#pragma unroll
+        for (int b = 8; b < TB; ++b)
+            if (((r << 8) >> b) & 1) o |= Idx(1) << a.pos[b];
+        off_r[r] = o;
+    }
+    auto tile_base = [&](Idx t) {
+        Idx base = t;
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+            const int q = a.pos[b];
+            base = ((base >> q) << (q + 1)) | (base & ((Idx(1) << q) - Idx(1)));
+        }
+        return base + off_tid;
+    };
+    float2 v[R];
+    {
+        const Idx base = tile_base(tile);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = amp[base + off_r[r]];
+    }
+    for (int gi = 0; gi < a.n_gates; ++gi) {
+        const int dd = 1 << (2 * a.g[gi].k);
+        const float2 *src = a.g[gi].mat;
+        float2 *dst = sm + a.g[gi].lofs;
+        for (int i = threadIdx.x; i < dd; i += kBlock) dst[i] = src[i];
+    }
+    for (; tile < n_tiles; tile += gridDim.x) {
+        __syncthreads();  // the previous tile is out of LDS; matrices staged
+#pragma unroll
+        for (int r = 0; r < R; ++r) sd[threadIdx.x + (r << 8)] = v[r];
+        const Idx base = tile_base(tile);
+        const Idx next = tile + gridDim.x;
+        if (next < n_tiles) {
+            const Idx nb = tile_base(next);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = amp[nb + off_r[r]];
+        }
+        __syncthreads();
+        for (int gi = 0; gi < a.n_gates; ++gi) {
+            const int k = a.g[gi].k;
+            int lt[kMaxGateQubits];
+#pragma unroll
+            for (int b = 0; b < kMaxGateQubits; ++b) lt[b] = a.g[gi].lt[b];
+            const float2 *m = sm + a.g[gi].lofs;
+            switch (k) {
+                case 1: tile_gate<1>(sd, m, lt, TB); break;
+                case 2: tile_gate<2>(sd, m, lt, TB); break;
+                case 3: tile_gate<3>(sd, m, lt, TB); break;
+                case 4: tile_gate<4>(sd, m, lt, TB); break;
+                default: tile_gate<5>(sd, m, lt, TB); break;
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) amp[base + off_r[r]] = sd[threadIdx.x + (r << 8)];
     }
 }
 
@@ -356,24 +460,68 @@ GateArgs<K> make_args(const GateDesc &g) {
 }
 
 template <typename Idx>
-hipError_t apply_gate_idx(float2 *amp, int n, const GateDesc &g, const float2 *mat_dev,
-                          hipStream_t st) {
+hipError_t apply_direct_idx(float2 *amp, int n, const GateDesc &g, const float2 *mat_dev,
+                            hipStream_t st) {
     const Idx groups = Idx(1) << (n - g.k);
     const unsigned grid = grid_for(uint64_t(groups));
+    TargetArgs ta;
+    for (int b = 0; b < kMaxGateQubits; ++b) ta.t[b] = b < g.k ? g.t[b] : 0;
     switch (g.k) {
-        case 1: apply_gate_args<1, Idx><<<grid, kBlock, 0, st>>>(amp, groups, make_args<1>(g)); break;
-        case 2: apply_gate_args<2, Idx><<<grid, kBlock, 0, st>>>(amp, groups, make_args<2>(g)); break;
-        case 3: apply_gate_args<3, Idx><<<grid, kBlock, 0, st>>>(amp, groups, make_args<3>(g)); break;
-        case 4: apply_gate_args<4, Idx><<<grid, kBlock, 0, st>>>(amp, groups, make_args<4>(g)); break;
-        case 5: {
-            TargetArgs ta;
-            for (int b = 0; b < 5; ++b) ta.t[b] = g.t[b];
-            apply_gate5_lds<Idx><<<grid, kBlock, 0, st>>>(amp, groups, mat_dev, ta);
-            break;
-        }
+        case 1: apply_direct<1, Idx><<<grid, kBlock, 0, st>>>(amp, groups, mat_dev, ta); break;
+        case 2: apply_direct<2, Idx><<<grid, kBlock, 0, st>>>(amp, groups, mat_dev, ta); break;
+        case 3: apply_direct<3, Idx><<<grid, kBlock, 0, st>>>(amp, groups, mat_dev, ta); break;
+        case 4: apply_direct<4, Idx><<<grid, kBlock, 0, st>>>(amp, groups, mat_dev, ta); break;
+        case 5: apply_direct<5, Idx><<<grid, kBlock, 0, st>>>(amp, groups, mat_dev, ta); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+template <int TB, typename Idx>
+hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
+    static bool attr_set = false;
+    const size_t lds = sizeof(float2) * ((size_t(1) << TB) + size_t(a.mat_total));
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_tile<TB, Idx>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           int(sizeof(float2) * ((size_t(1) << TB) + kTileMatBudget)));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const Idx n_tiles = Idx(1) << (n - TB);
+    // persistent grid: as many workgroups as fit on the chip at this LDS size
+    int per_cu = int((160u * 1024u) / lds);
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 8) per_cu = 8;
+    uint64_t grid = uint64_t(device_cus()) * uint64_t(per_cu);
+    if (grid > uint64_t(n_tiles)) grid = uint64_t(n_tiles);
+    apply_tile<TB, Idx><<<unsigned(grid), kBlock, lds, st>>>(amp, n_tiles, a);
+    return hipGetLastError();
+}
+
+template <typename Idx>
+hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
+    switch (a.tb) {
+        case 8: return tile_launch<8, Idx>(amp, n, a, st);
+        case 9: return tile_launch<9, Idx>(amp, n, a, st);
+        case 10: return tile_launch<10, Idx>(amp, n, a, st);
+        case 11: return tile_launch<11, Idx>(amp, n, a, st);
+        case 12: return tile_launch<12, Idx>(amp, n, a, st);
+        case 13: return tile_launch<13, Idx>(amp, n, a, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -407,10 +555,66 @@ hipError_t launch_scale(float2 *amp, int n, float s, hipStream_t st) {
     return hipGetLastError();
 }
 
+bool tile_for_gate(int n, const GateDesc &g, TileArgs &a) {
+    if (n < kTileMinQubits) return false;
+    bool low = false;
+    for (int b = 0; b < g.k; ++b) low |= g.t[b] < 6;
+    if (!low) return false;
+    bool in_tile[kMaxQubits] = {false};
+    int cnt = 0;
+    for (int q = 0; q < 6; ++q) { in_tile[q] = true; ++cnt; }
+    for (int b = 0; b < g.k; ++b)
+        if (!in_tile[g.t[b]]) { in_tile[g.t[b]] = true; ++cnt; }
+    int tb = cnt;
+    if (tb < 10) tb = 10;
+    if (tb < g.k + 8) tb = g.k + 8;
+    if (tb > n) tb = n;
+    for (int q = 0; q < n && cnt < tb; ++q)
+        if (!in_tile[q]) { in_tile[q] = true; ++cnt; }
+    a.tb = tb;
+    int i = 0;
+    for (int q = 0; q < n; ++q)
+        if (in_tile[q]) a.pos[i++] = q;
+    a.n_gates = 1;
+    a.mat_total = 1 << (2 * g.k);
+    a.g[0].k = g.k;
+    a.g[0].lofs = 0;
+    a.g[0].pad = 0;
+    a.g[0].mat = nullptr;
+    for (int b = 0; b < g.k; ++b) {
+        int lp = 0;
+        while (a.pos[lp] != g.t[b]) ++lp;
+        a.g[0].lt[b] = lp;  // ascending because g.t is ascending
+    }
+    return true;
+}
+
 hipError_t launch_apply_gate(float2 *amp, int n, const GateDesc &g, const float2 *mat_dev,
                              hipStream_t st) {
-    if (n <= 31) return apply_gate_idx<uint32_t>(amp, n, g, mat_dev, st);
-    return apply_gate_idx<uint64_t>(amp, n, g, mat_dev, st);
+    TileArgs a;
+    if (tile_for_gate(n, g, a)) {
+        a.g[0].mat = mat_dev;
+        return launch_apply_tile(amp, n, a, st);
+    }
+    if (n <= 31) return apply_direct_idx<uint32_t>(amp, n, g, mat_dev, st);
+    return apply_direct_idx<uint64_t>(amp, n, g, mat_dev, st);
+}
+
+hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
+    if (a.tb < 8 || a.tb > kMaxTileBits || a.tb > n || a.n_gates < 0 ||
+        a.n_gates > kMaxTileGates || a.mat_total < 0 || a.mat_total > kTileMatBudget)
+        return hipErrorInvalidValue;
+    for (int gi = 0; gi < a.n_gates; ++gi) {
+        const TileGate &g = a.g[gi];
+        if (g.k < 1 || g.k > kMaxGateQubits || g.k > a.tb || !g.mat || g.lofs < 0 ||
+            g.lofs + (1 << (2 * g.k)) > a.mat_total)
+            return hipErrorInvalidValue;
+        for (int b = 0; b < g.k; ++b)
+            if (g.lt[b] < 0 || g.lt[b] >= a.tb || (b > 0 && g.lt[b] <= g.lt[b - 1]))
+                return hipErrorInvalidValue;
+    }
+    if (n <= 31) return apply_tile_idx<uint32_t>(amp, n, a, st);
+    return apply_tile_idx<uint64_t>(amp, n, a, st);
 }
 
 hipError_t launch_norm(const float2 *amp, int n, double *partials, double *out_dev,

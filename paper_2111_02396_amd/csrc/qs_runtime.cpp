@@ -26,8 +26,8 @@ qs_status fail(qs_status st, const std::string &msg) {
     return st;
 }
 
-constexpr int kRingSlots = 64;
 constexpr int kDefaultFuse = 4;
+constexpr size_t kArenaHalf = size_t(1) << 18;  // float2 per half of the staging ring (2 MiB)
 constexpr double kRenormLogThreshold = -46.0;  // ~1e-20 on the norm squared
 
 struct PendingOp {
@@ -53,11 +53,15 @@ struct qs_state_s {
     double *samp_norm = nullptr;
     uint64_t *samp_out = nullptr;
     size_t samp_cap = 0;
-    float2 *ring_dev = nullptr;   // k = 5 matrices
-    float2 *ring_host = nullptr;  // pinned staging
-    hipEvent_t ring_ev[kRingSlots] = {};
-    bool ring_live[kRingSlots] = {};
-    int ring_pos = 0;
+    // matrix staging: two halves of a pinned host buffer mirrored on the
+    // device; a half is refilled only after its last copy has completed
+    float2 *arena_dev = nullptr;
+    float2 *arena_host = nullptr;
+    hipEvent_t arena_ev[2] = {};
+    bool arena_live[2] = {false, false};
+    int arena_half = 0;
+    size_t arena_head = 0;       // next free float2 in the current half
+    size_t arena_committed = 0;  // first float2 not yet copied
     std::vector<PendingOp> pending;
     bool poisoned = false;
 };
@@ -118,32 +122,63 @@ void make_desc(int k, const int *t, const cd *m, qs::GateDesc &g) {
         g.m[i] = make_float2(float(sorted[i].real()), float(sorted[i].imag()));
 }
 
-qs_status ensure_ring(qs_state s) {
-    if (s->ring_dev) return QS_OK;
-    QS_HIP(s, hipMalloc(&s->ring_dev, sizeof(float2) * 1024 * kRingSlots));
-    QS_HIP(s, hipHostMalloc(&s->ring_host, sizeof(float2) * 1024 * kRingSlots, hipHostMallocDefault));
-    for (int i = 0; i < kRingSlots; ++i) {
-        QS_HIP(s, hipEventCreateWithFlags(&s->ring_ev[i], hipEventDisableTiming));
-        s->ring_live[i] = false;
+qs_status ensure_arena(qs_state s) {
+    if (s->arena_dev) return QS_OK;
+    QS_HIP(s, hipMalloc(&s->arena_dev, sizeof(float2) * 2 * kArenaHalf));
+    QS_HIP(s, hipHostMalloc(&s->arena_host, sizeof(float2) * 2 * kArenaHalf, hipHostMallocDefault));
+    for (int i = 0; i < 2; ++i) QS_HIP(s, hipEventCreateWithFlags(&s->arena_ev[i], hipEventDisableTiming));
+    s->arena_half = 0;
+    s->arena_head = s->arena_committed = 0;
+    return QS_OK;
+}
+
+// Copy everything staged since the last commit to the device (one copy).
+qs_status arena_commit(qs_state s) {
+    if (s->arena_head == s->arena_committed) return QS_OK;
+    const size_t base = size_t(s->arena_half) * kArenaHalf;
+    QS_HIP(s, hipMemcpyAsync(s->arena_dev + base + s->arena_committed,
+                             s->arena_host + base + s->arena_committed,
+                             sizeof(float2) * (s->arena_head - s->arena_committed),
+                             hipMemcpyHostToDevice, s->st));
+    QS_HIP(s, hipEventRecord(s->arena_ev[s->arena_half], s->st));
+    s->arena_live[s->arena_half] = true;
+    s->arena_committed = s->arena_head;
+    return QS_OK;
+}
+
+// Whether `count` float2 fit in the current half without switching halves.
+bool arena_fits(qs_state s, size_t count) {
+    return s->arena_dev && s->arena_head + count <= kArenaHalf;
+}
+
+// Reserve `count` float2 of staging; returns the host slot and device address.
+// A full half is committed and the other half reused once its copy is done.
+qs_status arena_stage(qs_state s, size_t count, float2 **host, const float2 **dev) {
+    QS_CHECK(ensure_arena(s));
+    if (count > kArenaHalf) return fail(QS_ERR_INVALID_ARGUMENT, "matrix staging request too large");
+    if (s->arena_head + count > kArenaHalf) {
+        QS_CHECK(arena_commit(s));
+        s->arena_half ^= 1;
+        if (s->arena_live[s->arena_half]) QS_HIP(s, hipEventSynchronize(s->arena_ev[s->arena_half]));
+        s->arena_live[s->arena_half] = false;
+        s->arena_head = s->arena_committed = 0;
     }
+    const size_t base = size_t(s->arena_half) * kArenaHalf + s->arena_head;
+    *host = s->arena_host + base;
+    *dev = s->arena_dev + base;
+    s->arena_head += (count + 31) & ~size_t(31);  // 256 B alignment
+    if (s->arena_head > kArenaHalf) s->arena_head = kArenaHalf;
     return QS_OK;
 }
 
 qs_status enqueue_desc(qs_state s, const qs::GateDesc &g) {
-    const float2 *mat_dev = nullptr;
-    if (g.k == 5) {
-        QS_CHECK(ensure_ring(s));
-        const int slot = s->ring_pos;
-        s->ring_pos = (s->ring_pos + 1) % kRingSlots;
-        if (s->ring_live[slot]) QS_HIP(s, hipEventSynchronize(s->ring_ev[slot]));
-        std::memcpy(s->ring_host + size_t(slot) * 1024, g.m, sizeof(float2) * 1024);
-        QS_HIP(s, hipMemcpyAsync(s->ring_dev + size_t(slot) * 1024, s->ring_host + size_t(slot) * 1024,
-                                 sizeof(float2) * 1024, hipMemcpyHostToDevice, s->st));
-        QS_HIP(s, hipEventRecord(s->ring_ev[slot], s->st));
-        s->ring_live[slot] = true;
-        mat_dev = s->ring_dev + size_t(slot) * 1024;
-    }
-    QS_HIP(s, qs::launch_apply_gate(s->amp, s->n, g, mat_dev, s->st));
+    const size_t dd = size_t(1) << (2 * g.k);
+    float2 *h = nullptr;
+    const float2 *d = nullptr;
+    QS_CHECK(arena_stage(s, dd, &h, &d));
+    std::memcpy(h, g.m, sizeof(float2) * dd);
+    QS_CHECK(arena_commit(s));
+    QS_HIP(s, qs::launch_apply_gate(s->amp, s->n, g, d, s->st));
     return QS_OK;
 }
 
@@ -494,10 +529,10 @@ qs_status qs_destroy_state(qs_state s) {
     if (s->samp_incl) (void)hipFree(s->samp_incl);
     if (s->samp_norm) (void)hipFree(s->samp_norm);
     if (s->samp_out) (void)hipFree(s->samp_out);
-    if (s->ring_dev) {
-        (void)hipFree(s->ring_dev);
-        (void)hipHostFree(s->ring_host);
-        for (int i = 0; i < kRingSlots; ++i) (void)hipEventDestroy(s->ring_ev[i]);
+    if (s->arena_dev) {
+        (void)hipFree(s->arena_dev);
+        (void)hipHostFree(s->arena_host);
+        for (int i = 0; i < 2; ++i) (void)hipEventDestroy(s->arena_ev[i]);
     }
     delete s;
     return QS_OK;
@@ -742,7 +777,18 @@ struct BlockDesc {
     qs::GateDesc g;
     bool identity = false;
     double log_bound = 0.0;
+    const float2 *dev = nullptr;  // device copy of g.m
 };
+
+// Stage a block's matrix in the arena (committed later, before its launch).
+qs_status stage_block(qs_state s, BlockDesc &d) {
+    if (d.identity) return QS_OK;
+    const size_t dd = size_t(1) << (2 * d.g.k);
+    float2 *h = nullptr;
+    QS_CHECK(arena_stage(s, dd, &h, &d.dev));
+    std::memcpy(h, d.g.m, sizeof(float2) * dd);
+    return QS_OK;
+}
 
 // Build a GateDesc for members (time-ordered) under the given per-op matrices.
 void build_block(const CircuitModel &m, const std::vector<int> &members,
@@ -825,6 +871,39 @@ struct Runner {
     double pending_scale = 1.0;     // conventional method: 1/sqrt(p_i N) not yet applied
     KernelTimer timer;
     bool timing = false;
+    float2 *static_mats = nullptr;  // default-plan matrices, uploaded once per call
+
+    ~Runner() {
+        if (static_mats) {
+            (void)hipStreamSynchronize(s->st);
+            (void)hipFree(static_mats);
+        }
+    }
+
+    // Upload the matrices of `descs` to one device buffer and point at it.
+    qs_status upload_static(std::vector<BlockDesc *> &descs) {
+        size_t total = 0;
+        for (auto *d : descs)
+            if (!d->identity) total += size_t(1) << (2 * d->g.k);
+        if (total == 0) return QS_OK;
+        std::vector<float2> host(total);
+        size_t pos = 0;
+        for (auto *d : descs) {
+            if (d->identity) continue;
+            const size_t dd = size_t(1) << (2 * d->g.k);
+            std::memcpy(host.data() + pos, d->g.m, sizeof(float2) * dd);
+            pos += dd;
+        }
+        QS_HIP(s, hipMalloc(&static_mats, sizeof(float2) * total));
+        QS_HIP(s, hipMemcpy(static_mats, host.data(), sizeof(float2) * total, hipMemcpyHostToDevice));
+        pos = 0;
+        for (auto *d : descs) {
+            if (d->identity) continue;
+            d->dev = static_mats + pos;
+            pos += size_t(1) << (2 * d->g.k);
+        }
+        return QS_OK;
+    }
     int64_t sample_fill = 0;        // samples buffered on the device
     int64_t sample_first_traj = 0;  // trajectory index (relative) of the first buffered sample
 
@@ -833,7 +912,7 @@ struct Runner {
         max_fuse = p.max_fuse > 0 ? p.max_fuse : kDefaultFuse;
     }
 
-    void plan_delayed() {
+    qs_status plan_delayed() {
         const int n_ops = int(m.ops.size());
         default_mats.assign(n_ops, nullptr);
         default_log.assign(n_ops, 0.0);
@@ -855,9 +934,12 @@ struct Runner {
             for (int o : blocks[b].ops) lb += default_log[o];
             block_desc[b].log_bound = lb;
         }
+        std::vector<BlockDesc *> all;
+        for (auto &d : block_desc) all.push_back(&d);
+        return upload_static(all);
     }
 
-    void plan_naive() {
+    qs_status plan_naive() {
         // gates between consecutive channels, fused per segment
         std::vector<int> seg;
         std::vector<const cd *> mats(m.ops.size(), nullptr);
@@ -897,6 +979,10 @@ struct Runner {
             else close();
         }
         close();  // the tail after the last channel
+        std::vector<BlockDesc *> all;
+        for (auto &segv : naive_segments)
+            for (auto &d : segv) all.push_back(&d);
+        return upload_static(all);
     }
 
     qs_status launch_block(const BlockDesc &d) {
@@ -907,11 +993,13 @@ struct Runner {
             for (int i = 0; i < D * D; ++i) sc.g.m[i] = make_float2(sc.g.m[i].x * f, sc.g.m[i].y * f);
             sc.identity = false;
             pending_scale = 1.0;
+            QS_CHECK(stage_block(s, sc));
+            QS_CHECK(arena_commit(s));
             return launch_block(sc);
         }
         if (d.identity) return QS_OK;
         if (timing) QS_CHECK(timer.before(s));
-        QS_CHECK(enqueue_desc(s, d.g));
+        QS_HIP(s, qs::launch_apply_gate(s->amp, s->n, d.g, d.dev, s->st));
         if (timing) QS_CHECK(timer.after(s));
         res.sweeps++;
         res.gate_sweeps++;
@@ -988,10 +1076,13 @@ struct Runner {
         const int n_ops = int(m.ops.size());
         int seg_start = 0;
         int slow_idx = 0;
-        BlockDesc bd;
         std::vector<int> sub;
+        std::deque<BlockDesc> dyn;
+        std::vector<const BlockDesc *> seq;
         for (;;) {
             const int seg_end = slow_idx < int(slow_ops.size()) ? slow_ops[slow_idx] : n_ops;
+            dyn.clear();
+            seq.clear();
             for (size_t b = 0; b < blocks.size(); ++b) {
                 const auto &ops = blocks[b].ops;
                 auto lo = std::lower_bound(ops.begin(), ops.end(), seg_start);
@@ -999,11 +1090,19 @@ struct Runner {
                 if (lo == hi) continue;
                 const bool whole = (lo == ops.begin() && hi == ops.end());
                 if (whole && !dirty[b]) {
-                    QS_CHECK(launch_block(block_desc[b]));
+                    seq.push_back(&block_desc[b]);
                     continue;
                 }
                 sub.assign(lo, hi);
+                dyn.emplace_back();
+                BlockDesc &bd = dyn.back();
                 build_block(m, sub, mats, tmp, bd);
+                if (!arena_fits(s, size_t(1) << (2 * bd.g.k))) {
+                    // launch what is staged before the ring can wrap onto it
+                    QS_CHECK(arena_commit(s));
+                    for (const BlockDesc *d : seq) QS_CHECK(launch_block(*d));
+                    seq.clear();
+                }
                 double lb = 0.0;
                 for (int o : sub) {
                     if (m.kind[o] == QS_OP_GATE) lb += m.gate_log_bound[o];
@@ -1014,8 +1113,11 @@ struct Runner {
                     }
                 }
                 bd.log_bound = lb;
-                QS_CHECK(launch_block(bd));
+                QS_CHECK(stage_block(s, bd));
+                seq.push_back(&bd);
             }
+            QS_CHECK(arena_commit(s));
+            for (const BlockDesc *d : seq) QS_CHECK(launch_block(*d));
             if (seg_end == n_ops) break;
             // steps 12-20 for the channel at seg_end
             const int c = m.channel_of_op[seg_end];
@@ -1085,8 +1187,8 @@ struct Runner {
         QS_CHECK(ensure_reduce(s));
         timing = (p.flags & QS_TRAJ_TIME_KERNELS) != 0;
         if (timing) QS_CHECK(timer.init(s, 4096));
-        if (p.mode == QS_KRAUS_DELAYED) plan_delayed();
-        else plan_naive();
+        if (p.mode == QS_KRAUS_DELAYED) QS_CHECK(plan_delayed());
+        else QS_CHECK(plan_naive());
         for (int64_t rel = 0; rel < p.n_traj; ++rel) {
             const uint32_t traj = uint32_t(p.traj_offset + rel);
             if (p.mode == QS_KRAUS_DELAYED) QS_CHECK(run_delayed(rel, traj));
