@@ -100,6 +100,10 @@ typedef struct {
     uint32_t circuit_id;   /* Philox counter word 2 */
     int32_t mode;          /* qs_kraus_mode */
     int32_t max_fuse;      /* largest fused gate (Section 3.2); 0 = library default (4) */
+    int32_t tile_bits;     /* LDS tile sweeps: fused gates whose qubits fit a tile of this
+                              many index bits (bits 0..5 always included) share one pass
+                              over the state; 0 = library default (13), 1 = off (one pass
+                              per fused gate), otherwise 10..13 */
     int32_t n_samples;     /* measurement samples per trajectory (>= 0) */
     const double *p0to1;   /* per-qubit readout P(read 1 | state 0), host, or NULL */
     const double *p1to0;   /* per-qubit readout P(read 0 | state 1), host, or NULL */
@@ -228,6 +232,15 @@ qs_status qs_kraus_bounds(int k, int n_kraus, const double *kraus, double *pbar_
 qs_status qs_fusion_plan(const qs_circuit *c, int max_fuse, int32_t *n_blocks_out,
                          int32_t *block_k, int32_t *block_targets, double *block_mats,
                          int32_t *op_block);
+
+/* Tile-sweep grouping of the blocks of qs_fusion_plan (same max_fuse): the
+ * order in which the trajectory driver applies them, one pass over the state
+ * per sweep.  Outputs (capacity n_ops): n_sweeps_out; order_out[i] = block
+ * applied i-th; sweep_of_order[i] = its sweep; sweep_bits[s] = bit mask of
+ * the index bits staged in LDS by sweep s (bits 0..5 always included).
+ * tile_bits as in qs_traj_params (0 = 13).  Host only. */
+qs_status qs_sweep_plan(const qs_circuit *c, int max_fuse, int tile_bits, int32_t *n_sweeps_out,
+                        int32_t *order_out, int32_t *sweep_of_order, uint64_t *sweep_bits);
 
 /* Philox4x32-10 of one counter/key (the library's own generator). */
 qs_status qs_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -59,7 +59,7 @@ class QsTrajParams(ctypes.Structure):
     _fields_ = [("n_traj", ctypes.c_int64), ("traj_offset", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("circuit_id", ctypes.c_uint32),
                 ("mode", ctypes.c_int32), ("max_fuse", ctypes.c_int32),
-                ("n_samples", ctypes.c_int32), ("p0to1", ctypes.c_void_p),
+                ("tile_bits", ctypes.c_int32), ("n_samples", ctypes.c_int32), ("p0to1", ctypes.c_void_p),
                 ("p1to0", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
 
 
@@ -100,6 +100,7 @@ def load():
         "qs_kraus_bounds": [i32, i32, vp, vp, vp],
         "qs_fusion_plan": [vp, i32, vp, vp, vp, vp, vp],
         "qs_philox4x32_10": [vp, vp, vp],
+        "qs_sweep_plan": [vp, i32, i32, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -257,6 +258,7 @@ class MarshalledCircuit:
 
 def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int = 0,
                         circuit_id: int = 0, mode: int = QS_KRAUS_DELAYED, max_fuse: int = 0,
+                        tile_bits: int = 0,
                         n_samples: int = 0, p0to1=None, p1to0=None, return_state: bool = False,
                         record_choices: bool = True, time_kernels: bool = False,
                         marshalled: Optional[MarshalledCircuit] = None) -> Dict:
@@ -266,8 +268,8 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
     e1 = None if p1to0 is None else np.ascontiguousarray(p1to0, dtype=np.float64)
     flags = (QS_TRAJ_RETURN_STATE if return_state else 0) | \
         (QS_TRAJ_TIME_KERNELS if time_kernels else 0)
-    params = QsTrajParams(n_traj, traj_offset, seed, circuit_id, mode, max_fuse, n_samples,
-                          _p(e0), _p(e1), flags)
+    params = QsTrajParams(n_traj, traj_offset, seed, circuit_id, mode, max_fuse, tile_bits,
+                          n_samples, _p(e0), _p(e1), flags)
     bits = np.zeros(max(n_traj * n_samples, 1), dtype=np.uint64)
     choices = np.zeros(max(n_traj * nch, 1), dtype=np.int8) if record_choices else None
     paths = np.zeros(max(n_traj * nch, 1), dtype=np.int8) if record_choices else None
@@ -312,6 +314,19 @@ def qs_fusion_plan(circuit, max_fuse: int):
         m = bm[b * 2048:b * 2048 + 2 * D * D].view(np.complex128).reshape(D, D).copy()
         blocks.append((tuple(int(x) for x in bt[5 * b:5 * b + k]), m))
     return blocks, ob[:n_ops].copy()
+
+
+def qs_sweep_plan(circuit, max_fuse: int, tile_bits: int = 0):
+    mc = MarshalledCircuit(circuit)
+    n_ops = max(len(circuit.ops), 1)
+    ns = ctypes.c_int32()
+    order = np.zeros(n_ops, dtype=np.int32)
+    sw_of = np.zeros(n_ops, dtype=np.int32)
+    bits = np.zeros(n_ops, dtype=np.uint64)
+    _check(load().qs_sweep_plan(ctypes.byref(mc.c), max_fuse, tile_bits, ctypes.byref(ns),
+                                _p(order), _p(sw_of), _p(bits)))
+    n_blocks = len(qs_fusion_plan(circuit, max_fuse)[0])
+    return ns.value, order[:n_blocks].copy(), sw_of[:n_blocks].copy(), bits[:ns.value].copy()
 
 
 def qs_last_error_message() -> str:

@@ -259,4 +259,89 @@ void to_ascending_order(int k, const int *t, const cd *in, cd *out, int *t_sorte
         for (int c = 0; c < D; ++c) out[map(r) * D + map(c)] = in[r * D + c];
 }
 
+std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, int max_bits,
+                                int low_bits, int max_blocks, int mat_budget) {
+    const int nb = int(blocks.size());
+    // predecessor counts and successor lists from per-qubit chains
+    std::vector<int> last(n_qubits, -1);
+    std::vector<int> npred(nb, 0);
+    std::vector<std::vector<int>> succ(nb);
+    for (int b = 0; b < nb; ++b) {
+        for (int i = 0; i < blocks[b].k; ++i) {
+            const int q = blocks[b].q[i];
+            const int p = last[q];
+            if (p >= 0 && (succ[p].empty() || succ[p].back() != b)) {
+                succ[p].push_back(b);
+                ++npred[b];
+            }
+            last[q] = b;
+        }
+    }
+    std::vector<int> ready;
+    for (int b = 0; b < nb; ++b)
+        if (npred[b] == 0) ready.push_back(b);
+    std::vector<Sweep> out;
+    int done = 0;
+    const int low = std::min(low_bits, n_qubits);
+    while (done < nb) {
+        Sweep sw;
+        std::vector<char> in(n_qubits, 0);
+        int nbits = 0;
+        for (int q = 0; q < low; ++q) {
+            in[q] = 1;
+            ++nbits;
+        }
+        int mats = 0;
+        for (;;) {
+            int best = -1, best_pos = -1, best_growth = 1 << 30;
+            for (int i = 0; i < int(ready.size()); ++i) {
+                const int b = ready[i];
+                int growth = 0;
+                for (int j = 0; j < blocks[b].k; ++j) growth += in[blocks[b].q[j]] ? 0 : 1;
+                if (nbits + growth > max_bits) continue;
+                if (mats + (1 << (2 * blocks[b].k)) > mat_budget) continue;
+                if (growth < best_growth || (growth == best_growth && b < best)) {
+                    best = b;
+                    best_pos = i;
+                    best_growth = growth;
+                }
+            }
+            if (best < 0 || int(sw.blocks.size()) >= max_blocks) break;
+            ready.erase(ready.begin() + best_pos);
+            sw.blocks.push_back(best);
+            mats += 1 << (2 * blocks[best].k);
+            for (int j = 0; j < blocks[best].k; ++j) {
+                const int q = blocks[best].q[j];
+                if (!in[q]) {
+                    in[q] = 1;
+                    ++nbits;
+                }
+            }
+            ++done;
+            for (int s : succ[best])
+                if (--npred[s] == 0) ready.push_back(s);
+        }
+        if (sw.blocks.empty()) {
+            // no ready block fits even an empty tile: it gets a sweep of its own,
+            // wider than max_bits (the caller applies such sweeps block by block)
+            int b = ready[0], pos = 0;
+            for (int i = 1; i < int(ready.size()); ++i)
+                if (ready[i] < b) {
+                    b = ready[i];
+                    pos = i;
+                }
+            ready.erase(ready.begin() + pos);
+            sw.blocks.push_back(b);
+            for (int j = 0; j < blocks[b].k; ++j) in[blocks[b].q[j]] = 1;
+            ++done;
+            for (int s : succ[b])
+                if (--npred[s] == 0) ready.push_back(s);
+        }
+        for (int q = 0; q < n_qubits; ++q)
+            if (in[q]) sw.bits.push_back(q);
+        out.push_back(std::move(sw));
+    }
+    return out;
+}
+
 }  // namespace qs

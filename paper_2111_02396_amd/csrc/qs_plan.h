@@ -61,4 +61,23 @@ void to_ascending_order(int k, const int *t, const cd *in, cd *out, int *t_sorte
 
 bool is_identity_multiple(int d, const cd *M, double tol, cd *scalar_out);
 
+// A tile sweep: blocks (indices into the block list, in application order)
+// whose qubits all lie in the tile's bit set, which always holds bits
+// 0..low_bits-1.  `bits` is ascending.
+struct Sweep {
+    std::vector<int> bits;
+    std::vector<int> blocks;
+};
+
+// Group an ordered, valid block list into tile sweeps of at most max_bits
+// tile bits.  Blocks are taken in a dependency-respecting order (a block
+// waits for the previous block on each of its qubits): a sweep repeatedly
+// takes a ready block that adds the fewest new bits (earliest first), as
+// long as the bit budget, max_blocks and the matrix budget (sum of 4^k)
+// allow.  The result, sweep by sweep, is again a valid application order.
+// A block that fits no tile of max_bits gets a sweep of its own whose bit
+// set is wider than max_bits.
+std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, int max_bits,
+                                int low_bits, int max_blocks, int mat_budget);
+
 }  // namespace qs

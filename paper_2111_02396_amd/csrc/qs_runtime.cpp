@@ -862,6 +862,19 @@ struct Runner {
     std::vector<qs::Block> blocks;
     std::vector<int> op_block;
     std::vector<BlockDesc> block_desc;
+    // tile sweeps over the default plan: the sweep order is the launch order
+    struct TileLayout {
+        bool tiled = false;
+        int tb = 0;
+        int pos[qs::kMaxTileBits] = {};
+        int8_t local[qs::kMaxQubits] = {};
+    };
+    std::vector<qs::Sweep> sweeps;
+    std::vector<TileLayout> layouts;
+    struct Unit {
+        int sweep;
+        std::vector<const BlockDesc *> items;
+    };
     // naive mode: gate blocks per inter-channel segment
     std::vector<std::vector<BlockDesc>> naive_segments;
     std::vector<cd> tmp;
@@ -934,9 +947,91 @@ struct Runner {
             for (int o : blocks[b].ops) lb += default_log[o];
             block_desc[b].log_bound = lb;
         }
+        plan_sweeps();
         std::vector<BlockDesc *> all;
         for (auto &d : block_desc) all.push_back(&d);
         return upload_static(all);
+    }
+
+    void plan_sweeps() {
+        const int T = p.tile_bits == 0 ? qs::kMaxTileBits : p.tile_bits;
+        sweeps.clear();
+        layouts.clear();
+        if (T >= 10 && m.n >= qs::kTileMinQubits) {
+            sweeps = qs::group_sweeps(m.n, blocks, std::min(T, m.n), 6, qs::kMaxTileGates,
+                                      qs::kTileMatBudget);
+        } else {
+            for (size_t b = 0; b < blocks.size(); ++b) {
+                qs::Sweep sw;
+                sw.blocks.push_back(int(b));
+                sweeps.push_back(std::move(sw));
+            }
+        }
+        layouts.resize(sweeps.size());
+        for (size_t u = 0; u < sweeps.size(); ++u) {
+            TileLayout &L = layouts[u];
+            const auto &bits = sweeps[u].bits;
+            if (bits.empty() || int(bits.size()) > qs::kMaxTileBits) continue;
+            int maxk = 1;
+            for (int b : sweeps[u].blocks) maxk = std::max(maxk, blocks[b].k);
+            int tb = std::max<int>(int(bits.size()), std::min(qs::kMaxTileBits, std::max(10, maxk + 8)));
+            tb = std::min(tb, m.n);
+            std::vector<char> in(m.n, 0);
+            for (int q : bits) in[q] = 1;
+            int cnt = int(bits.size());
+            for (int q = 0; q < m.n && cnt < tb; ++q)
+                if (!in[q]) {
+                    in[q] = 1;
+                    ++cnt;
+                }
+            L.tb = tb;
+            int i = 0;
+            for (int q = 0; q < qs::kMaxQubits; ++q) L.local[q] = -1;
+            for (int q = 0; q < m.n; ++q)
+                if (in[q]) {
+                    L.pos[i] = q;
+                    L.local[q] = int8_t(i);
+                    ++i;
+                }
+            L.tiled = true;
+        }
+    }
+
+    qs_status launch_unit(const Unit &u) {
+        const TileLayout &L = layouts[u.sweep];
+        if (!L.tiled) {
+            for (const BlockDesc *d : u.items) QS_CHECK(launch_block(*d));
+            return QS_OK;
+        }
+        qs::TileArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.tb = L.tb;
+        for (int i = 0; i < L.tb; ++i) a.pos[i] = L.pos[i];
+        int lofs = 0;
+        double lb = 0.0;
+        for (const BlockDesc *d : u.items) {
+            qs::TileGate &g = a.g[a.n_gates++];
+            g.k = d->g.k;
+            for (int b = 0; b < d->g.k; ++b) g.lt[b] = L.local[d->g.t[b]];
+            g.lofs = lofs;
+            g.mat = d->dev;
+            lofs += 1 << (2 * d->g.k);
+            lb += d->log_bound;
+            res.gate_k_launches[d->g.k]++;
+        }
+        a.mat_total = lofs;
+        if (timing) QS_CHECK(timer.before(s));
+        QS_HIP(s, qs::launch_apply_tile(s->amp, s->n, a, s->st));
+        if (timing) QS_CHECK(timer.after(s));
+        res.sweeps++;
+        res.gate_sweeps++;
+        log_norm_bound += lb;
+        if (log_norm_bound < kRenormLogThreshold) {
+            QS_CHECK(renormalize_now(s));
+            res.sweeps += 2;
+            log_norm_bound = 0.0;
+        }
+        return QS_OK;
     }
 
     qs_status plan_naive() {
@@ -1078,46 +1173,51 @@ struct Runner {
         int slow_idx = 0;
         std::vector<int> sub;
         std::deque<BlockDesc> dyn;
-        std::vector<const BlockDesc *> seq;
+        std::vector<Unit> units;
         for (;;) {
             const int seg_end = slow_idx < int(slow_ops.size()) ? slow_ops[slow_idx] : n_ops;
             dyn.clear();
-            seq.clear();
-            for (size_t b = 0; b < blocks.size(); ++b) {
-                const auto &ops = blocks[b].ops;
-                auto lo = std::lower_bound(ops.begin(), ops.end(), seg_start);
-                auto hi = std::lower_bound(lo, ops.end(), seg_end);
-                if (lo == hi) continue;
-                const bool whole = (lo == ops.begin() && hi == ops.end());
-                if (whole && !dirty[b]) {
-                    seq.push_back(&block_desc[b]);
-                    continue;
-                }
-                sub.assign(lo, hi);
-                dyn.emplace_back();
-                BlockDesc &bd = dyn.back();
-                build_block(m, sub, mats, tmp, bd);
-                if (!arena_fits(s, size_t(1) << (2 * bd.g.k))) {
-                    // launch what is staged before the ring can wrap onto it
-                    QS_CHECK(arena_commit(s));
-                    for (const BlockDesc *d : seq) QS_CHECK(launch_block(*d));
-                    seq.clear();
-                }
-                double lb = 0.0;
-                for (int o : sub) {
-                    if (m.kind[o] == QS_OP_GATE) lb += m.gate_log_bound[o];
-                    else {
-                        const ChannelInfo &ci = m.channels[m.channel_of_op[o]];
-                        const int pk = pick[m.channel_of_op[o]];
-                        lb += pk >= 0 ? ci.log_pbar[pk] : 0.0;
+            units.clear();
+            for (size_t u = 0; u < sweeps.size(); ++u) {
+                Unit unit{int(u), {}};
+                for (int b : sweeps[u].blocks) {
+                    const auto &ops = blocks[b].ops;
+                    auto lo = std::lower_bound(ops.begin(), ops.end(), seg_start);
+                    auto hi = std::lower_bound(lo, ops.end(), seg_end);
+                    if (lo == hi) continue;
+                    const bool whole = (lo == ops.begin() && hi == ops.end());
+                    if (whole && !dirty[b]) {
+                        if (!block_desc[b].identity) unit.items.push_back(&block_desc[b]);
+                        continue;
                     }
+                    sub.assign(lo, hi);
+                    dyn.emplace_back();
+                    BlockDesc &bd = dyn.back();
+                    build_block(m, sub, mats, tmp, bd);
+                    if (bd.identity) continue;
+                    double lb = 0.0;
+                    for (int o : sub) {
+                        if (m.kind[o] == QS_OP_GATE) lb += m.gate_log_bound[o];
+                        else {
+                            const ChannelInfo &ci = m.channels[m.channel_of_op[o]];
+                            const int pk = pick[m.channel_of_op[o]];
+                            lb += pk >= 0 ? ci.log_pbar[pk] : 0.0;
+                        }
+                    }
+                    bd.log_bound = lb;
+                    if (!arena_fits(s, size_t(1) << (2 * bd.g.k))) {
+                        // launch what is staged before the ring can wrap onto it
+                        QS_CHECK(arena_commit(s));
+                        for (const Unit &x : units) QS_CHECK(launch_unit(x));
+                        units.clear();
+                    }
+                    QS_CHECK(stage_block(s, bd));
+                    unit.items.push_back(&bd);
                 }
-                bd.log_bound = lb;
-                QS_CHECK(stage_block(s, bd));
-                seq.push_back(&bd);
+                if (!unit.items.empty()) units.push_back(std::move(unit));
             }
             QS_CHECK(arena_commit(s));
-            for (const BlockDesc *d : seq) QS_CHECK(launch_block(*d));
+            for (const Unit &x : units) QS_CHECK(launch_unit(x));
             if (seg_end == n_ops) break;
             // steps 12-20 for the channel at seg_end
             const int c = m.channel_of_op[seg_end];
@@ -1225,6 +1325,9 @@ qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_par
         return fail(QS_ERR_INVALID_ARGUMENT, "bad mode");
     if (p->max_fuse < 0 || p->max_fuse > qs::kMaxGateQubits)
         return fail(QS_ERR_INVALID_ARGUMENT, "max_fuse outside 0..5");
+    if (!(p->tile_bits == 0 || p->tile_bits == 1 ||
+          (p->tile_bits >= 10 && p->tile_bits <= qs::kMaxTileBits)))
+        return fail(QS_ERR_INVALID_ARGUMENT, "tile_bits must be 0, 1 or 10..13");
     if (p->n_samples < 0) return fail(QS_ERR_INVALID_ARGUMENT, "negative sample count");
     if (int64_t(p->n_samples) * int64_t(s->n) > (int64_t(1) << 32))
         return fail(QS_ERR_INVALID_ARGUMENT, "readout counter would overflow");
@@ -1271,6 +1374,46 @@ qs_status qs_fusion_plan(const qs_circuit *c, int max_fuse, int32_t *n_blocks_ou
     }
     for (size_t o = 0; o < ob.size(); ++o) op_block[o] = ob[o];
     *n_blocks_out = int32_t(blocks.size());
+    return QS_OK;
+}
+
+qs_status qs_sweep_plan(const qs_circuit *c, int max_fuse, int tile_bits, int32_t *n_sweeps_out,
+                        int32_t *order_out, int32_t *sweep_of_order, uint64_t *sweep_bits) {
+    if (!c || !n_sweeps_out || !order_out || !sweep_of_order || !sweep_bits)
+        return fail(QS_ERR_INVALID_ARGUMENT, "null argument");
+    if (max_fuse < 1 || max_fuse > qs::kMaxGateQubits)
+        return fail(QS_ERR_INVALID_ARGUMENT, "max_fuse outside 1..5");
+    if (!(tile_bits == 0 || tile_bits == 1 || (tile_bits >= 10 && tile_bits <= qs::kMaxTileBits)))
+        return fail(QS_ERR_INVALID_ARGUMENT, "tile_bits must be 0, 1 or 10..13");
+    if (c->n_qubits < 1 || c->n_qubits > qs::kMaxQubits)
+        return fail(QS_ERR_INVALID_ARGUMENT, "n out of range");
+    CircuitModel m;
+    QS_CHECK(build_model(c, m));
+    const auto blocks = qs::fuse_greedy(m.n, m.ops, max_fuse);
+    const int T = tile_bits == 0 ? qs::kMaxTileBits : tile_bits;
+    std::vector<qs::Sweep> sw;
+    if (T >= 10 && m.n >= qs::kTileMinQubits) {
+        sw = qs::group_sweeps(m.n, blocks, std::min(T, m.n), 6, qs::kMaxTileGates, qs::kTileMatBudget);
+    } else {
+        for (size_t b = 0; b < blocks.size(); ++b) {
+            qs::Sweep one;
+            one.blocks.push_back(int(b));
+            for (int j = 0; j < blocks[b].k; ++j) one.bits.push_back(blocks[b].q[j]);
+            sw.push_back(std::move(one));
+        }
+    }
+    int i = 0;
+    for (size_t u = 0; u < sw.size(); ++u) {
+        uint64_t mask = 0;
+        for (int q : sw[u].bits) mask |= uint64_t(1) << q;
+        sweep_bits[u] = mask;
+        for (int b : sw[u].blocks) {
+            order_out[i] = b;
+            sweep_of_order[i] = int32_t(u);
+            ++i;
+        }
+    }
+    *n_sweeps_out = int32_t(sw.size());
     return QS_OK;
 }
 

@@ -173,12 +173,12 @@ def test_channel_parity_imperative(qs, orc, mode):
 
 
 def _driver(qs, c, n_traj, mode, seed=0, traj_offset=0, n_samples=0, e0=None, e1=None,
-            return_state=False, max_fuse=0, circuit_id=0):
+            return_state=False, max_fuse=0, circuit_id=0, tile_bits=0):
     with qs.State(c.n) as st:
         return qs.qs_run_trajectories(st.h, c, n_traj, seed=seed, traj_offset=traj_offset,
                                       mode=mode, n_samples=n_samples, p0to1=e0, p1to0=e1,
                                       return_state=return_state, max_fuse=max_fuse,
-                                      circuit_id=circuit_id)
+                                      circuit_id=circuit_id, tile_bits=tile_bits)
 
 
 @pytest.mark.parametrize("mode", [0, 1], ids=["delayed", "naive"])
@@ -267,3 +267,70 @@ def test_torch_buffer_and_stream(qs, orc):
         stream.synchronize()
         got = buf.cpu().numpy()
     assert rel_l2(got, orc.simulate(c)) < AMP_TOL
+
+
+@pytest.mark.parametrize("tile_bits", [1, 10, 12, 13])
+@pytest.mark.parametrize("max_fuse", [2, 4])
+def test_driver_tile_sweeps_16q(qs, orc, tile_bits, max_fuse):
+    """16 qubits: tiles narrower than the state, fused blocks regrouped into
+    LDS sweeps, slow paths splitting the sweeps."""
+    c = W.grid_circuit(4, 4, 6, p_dep=0.01, gamma=0.02, seed=8)
+    e0, e1 = W.readout_arrays(16, 0.01, 0.03)
+    m = orc.Marshalled(c)
+    ties = 0
+    for t in range(2):
+        got = _driver(qs, c, 1, 0, seed=4, traj_offset=t, n_samples=30, e0=e0, e1=e1,
+                      return_state=True, max_fuse=max_fuse, tile_bits=tile_bits)
+        ref = orc.run_trajectory(c, t, mode=0, seed=4, n_samples=30, e0=e0, e1=e1,
+                                 return_state=True, marshalled=m)
+        _, tie = compare_choices(got["choices"][0], ref)
+        ties += tie
+        if tie:
+            continue
+        assert np.array_equal(got["paths"][0], ref["paths"])
+        assert rel_l2(got["state"], ref["state"]) < AMP_TOL
+        mism = np.nonzero(got["samples"][0] != ref["samples"])[0]
+        assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
+    assert ties <= 1
+
+
+def test_driver_noiseless_grid_matches_oracle_20q(qs, orc):
+    c = W.grid_circuit(4, 5, 10, seed=3)
+    got = _driver(qs, c, 1, 0, n_samples=200, return_state=True)
+    ref = orc.run_trajectory(c, 0, n_samples=200, return_state=True)
+    assert rel_l2(got["state"], ref["state"]) < AMP_TOL
+    mism = np.nonzero(got["samples"][0] != ref["samples"])[0]
+    assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
+
+
+def test_grid24_full_size_classification(qs, orc):
+    """The benchmark workload at full size in the benchmark's launch
+    configuration: every channel resolved from the bounds must pick the same
+    Kraus operator as the oracle's rule on the same draw, and the channels
+    that need inner products must be the same ones."""
+    w = W.grid24_workload()
+    c = w.circuit
+    n_traj = 24
+    got = _driver(qs, c, n_traj, 0, seed=w.seed, n_samples=1, e0=w.e0, e1=w.e1)
+    m = orc.Marshalled(c)
+    chans = [o for o in c.ops if o.kind == W.CHANNEL]
+    bounds = {}
+    dummy = orc.zero_state(1)
+    slow_total = 0
+    for t in range(n_traj):
+        for j, op in enumerate(chans):
+            key = id(op.mats)
+            if key not in bounds:
+                bounds[key] = orc.kraus_bounds(op.mats)
+            pbar, mix = bounds[key]
+            r = orc.draw(w.seed, j, t, 0, 0)
+            res = orc.select_branch(dummy, [0], op.mats, 0, r, pbar=pbar, mixture=mix)
+            if res["path"] == 0:
+                assert got["paths"][t][j] == 0 or res["margin_fast"] < 1e-12
+                if got["paths"][t][j] == 0:
+                    assert got["choices"][t][j] == res["choice"] or res["margin_fast"] < 1e-12
+            else:
+                slow_total += 1
+                assert got["paths"][t][j] == 1 or res["margin_fast"] < 1e-12
+    assert slow_total == int(got["n_slow"].sum())
+    assert np.all(got["samples"] < (1 << 24))

@@ -146,3 +146,38 @@ def test_grid24_plan_size(lib):
     c = W.grid24_workload().circuit.gates_only()
     sizes = {f: len(lib.qs_fusion_plan(c, f)[0]) for f in (2, 3, 4, 5)}
     assert sizes[4] < sizes[2] < len(c.ops)
+
+
+@pytest.mark.parametrize("tile_bits", [1, 10, 12, 13])
+@pytest.mark.parametrize("f", [2, 4])
+def test_sweep_grouping_keeps_order(lib, tile_bits, f):
+    """Regrouping fused blocks into tile sweeps reorders them; the product in
+    the new order must still equal the circuit."""
+    c = W.grid_circuit(2, 5, 8, seed=2)  # 10 qubits: tiles are narrower than the state
+    blocks, _ = lib.qs_fusion_plan(c, f)
+    ns, order, sweep_of, bits = lib.qs_sweep_plan(c, f, tile_bits)
+    assert sorted(order.tolist()) == list(range(len(blocks)))
+    assert np.all(np.diff(sweep_of) >= 0)
+    rng = np.random.default_rng(tile_bits + 10 * f)
+    psi0 = rng.standard_normal(1 << c.n) + 1j * rng.standard_normal(1 << c.n)
+    psi = psi0.copy()
+    for b in order:
+        targets, m = blocks[b]
+        psi = dense.apply_tensor(psi, list(targets), m)
+    ref = psi0.copy()
+    for op in c.ops:
+        ref = dense.apply_tensor(ref, list(op.qubits), op.mats[0])
+    assert np.max(np.abs(psi - ref)) < 1e-12
+    if tile_bits >= 10:
+        for i, b in enumerate(order):
+            mask = int(bits[sweep_of[i]])
+            assert all((mask >> q) & 1 for q in blocks[b][0])
+            assert mask & 0x3F == 0x3F
+            assert bin(mask).count("1") <= tile_bits
+
+
+def test_sweep_grouping_cuts_passes(lib):
+    c = W.grid24_workload().circuit.gates_only()
+    ns_off, *_ = lib.qs_sweep_plan(c, 4, 1)
+    ns_13, *_ = lib.qs_sweep_plan(c, 4, 13)
+    assert ns_13 * 3 < ns_off
