@@ -29,6 +29,29 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2111_02396_amd", "csrc", "qs_kernels.hip")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "apply_tile_grid24_counters.md")
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed counter summary, only if
+    it was taken on the kernel source that is built now (else None)."""
+    import hashlib
+
+    try:
+        digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+        text = open(COUNTER_SUMMARY).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("kernel_source_sha256_prefix:", "traffic_bytes_per_launch:")))
+    if fields.get("kernel_source_sha256_prefix", "").strip() != digest:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg: str) -> None:
@@ -138,6 +161,10 @@ def main() -> int:
     avg_gate_s = (gate_ms / 1e3) / max(gate_launches, 1)
     bytes_per_launch = 16 * (1 << n)  # one read + one write of the complex64 state
     achieved = bytes_per_launch / avg_gate_s / 1e9
+    traffic = measured_traffic()
+    # complex mat-vec flops of the fused blocks applied (8 * 2^k per amplitude, Section 3.1)
+    flops = sum(k_hist[k] * (8 << k) for k in range(1, 6)) * float(1 << n)
+    flops_tf = flops / (gate_ms / 1e3) / 1e12 if gate_ms > 0 else 0.0
 
     naive = None
     if args.naive_traj > 0:
@@ -183,11 +210,15 @@ def main() -> int:
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": None,
-            "kernel": "apply_gate (fused-gate sweep, all widths)",
+            "traffic": (traffic / 1e9) if traffic else None,
+            "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "kernel": "fused-gate sweep (apply_tile / apply_direct): one read + one write of the state",
             "avg_launch_us": avg_gate_s * 1e6,
             "launches": gate_launches,
         },
+        "compute": {"achieved": flops_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": flops_tf / FP32_PEAK_TFLOPS,
+                    "basis": "8*2^k flops per amplitude per fused k-qubit block, summed per sweep"},
         "cpu_baseline": cpu,
         "naive": naive,
         "speedup_vs_naive": (value / naive["value"]) if naive else None,

@@ -1265,8 +1265,10 @@ struct Runner {
             if (!(accepted > 0.0)) return fail(QS_ERR_ZERO_NORM, "chosen Kraus operator has zero weight");
             if (choices) choices[c] = int8_t(pk);
             if (paths) paths[c] = 1;
-            // |psi> <- K_i |psi> / sqrt(p_i): fold 1/sqrt(||K_i psi||^2) into the next block
-            pending_scale /= std::sqrt(accepted);
+            // |psi> <- K_i |psi> / sqrt(p_i): the stored vector is now K_i psi_stored with
+            // norm^2 `accepted`, so 1/sqrt(accepted) (replacing any scale still
+            // pending for the old vector) normalises it; fold it into the next block
+            pending_scale = 1.0 / std::sqrt(accepted);
             if (pending_scale > 1e15 || pending_scale < 1e-15) {
                 QS_HIP(s, qs::launch_scale(s->amp, s->n, float(pending_scale), s->st));
                 res.sweeps++;
