@@ -91,6 +91,8 @@ def main() -> int:
     ap.add_argument("--traj", type=int, default=1000, help="trajectories per step")
     ap.add_argument("--p-dep", type=float, default=1e-3)
     ap.add_argument("--max-fuse", type=int, default=0)
+    ap.add_argument("--tile-bits", type=int, default=0,
+                    help="LDS tile sweep width (0 = library default, 1 = one pass per fused gate)")
     ap.add_argument("--naive-traj", type=int, default=3,
                     help="trajectories timed with the conventional method (0 = skip)")
     ap.add_argument("--cpu-cycles", type=int, default=1,
@@ -124,7 +126,8 @@ def main() -> int:
     def step(offset: int, timed: bool, mode=qs.QS_KRAUS_DELAYED, n_traj=None):
         return qs.qs_run_trajectories(
             st.h, c, n_traj or args.traj, seed=w.seed, traj_offset=offset, mode=mode,
-            max_fuse=args.max_fuse, n_samples=w.n_samples, p0to1=w.e0, p1to0=w.e1,
+            max_fuse=args.max_fuse, tile_bits=args.tile_bits, n_samples=w.n_samples,
+            p0to1=w.e0, p1to0=w.e1,
             record_choices=False, time_kernels=timed, marshalled=mc)
 
     log(f"workload {w.name}: n={n}, ops={len(c.ops)}, channels={mc.n_channels}")
@@ -202,6 +205,7 @@ def main() -> int:
             "samples_per_trajectory": w.n_samples,
             "mode": "delayed",
             "max_fuse": args.max_fuse or 4,
+            "tile_bits": args.tile_bits or 13,
             "parallelism": "none (1 GPU)",
         },
         "roofline": {

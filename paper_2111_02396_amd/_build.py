@@ -28,6 +28,9 @@ def hipcc() -> str:
 def build(verbose: bool = False, jobs: int = 4) -> str:
     common = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-I", INCLUDE, "-I", CSRC,
               "-Wall", "-Wno-unused-function"]
+    # a failed build must not leave an older library behind to be tested
+    if os.path.exists(LIB):
+        os.remove(LIB)
     tmpdir = tempfile.mkdtemp(prefix="qs_build_")
     objs, procs = [], []
     try:

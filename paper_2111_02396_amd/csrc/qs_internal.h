@@ -38,12 +38,19 @@ struct TargetArgs {
 // (ascending, always starting with bits 0..5); the gates g[0..n_gates-1]
 // act in order on tile-local bit positions lt[] (ascending), with their
 // matrices (2^k x 2^k complex64, rows/columns in lt order) read from device
-// address `mat` and staged in LDS at float2 offset `lofs` of a region of
-// mat_total entries.
+// address `mat` (16-byte aligned) and, for k >= 3, staged in LDS at float2
+// offset `lofs` (even) of a region of mat_total entries.
 constexpr int kMaxTileBits = 13;
 constexpr int kMaxTileGates = 48;
 constexpr int kTileMinQubits = 10;
 constexpr int kTileMatBudget = 4096;  // float2 of matrices staged per launch (32 KiB)
+
+// LDS float2 slots a gate's matrix takes in a tile launch: none for k <= 2
+// (read from global memory), MFMA fragments for k = 3 (256 floats) and
+// k = 4 (1024 floats), the plain 32x32 matrix for k = 5.
+__host__ __device__ inline int tile_mat_slots(int k) {
+    return k <= 2 ? 0 : (k == 3 ? 128 : (k == 4 ? 512 : 1024));
+}
 
 struct TileGate {
     int k;

@@ -47,6 +47,15 @@ __device__ __forceinline__ Idx local_offset(int j, const int *t) {
     return off;
 }
 
+// Read-only, wave-uniform matrices are read through the constant address
+// space, so the compiler fetches them with scalar loads into SGPRs.
+typedef const __attribute__((address_space(4))) float *ConstFloats;
+
+__device__ __forceinline__ float2 const_entry(const float2 *p, int i) {
+    const ConstFloats c = (ConstFloats)(p);
+    return make_float2(c[2 * i], c[2 * i + 1]);
+}
+
 __device__ __forceinline__ float2 cmac(float2 acc, float2 a, float2 b) {
     acc.x = fmaf(a.x, b.x, acc.x);
     acc.x = fmaf(-a.y, b.y, acc.x);
@@ -82,7 +91,12 @@ __global__ __launch_bounds__(kBlock) void apply_direct(float2 *__restrict__ amp,
         for (int i = threadIdx.x; i < D * D; i += kBlock) sm[i] = mat[i];
         __syncthreads();
     }
-    const float2 *m = kLds ? sm : mat;
+    float2 um[kLds ? 1 : D * D];
+    if (!kLds) {
+#pragma unroll
+        for (int i = 0; i < (kLds ? 1 : D * D); ++i) um[i] = const_entry(mat, i);
+    }
+    const float2 *m = kLds ? sm : um;
     for (;;) {
         if (g >= groups) break;
         const Idx base = spread_index<K, Idx>(g, ta.t);
@@ -101,12 +115,14 @@ __global__ __launch_bounds__(kBlock) void apply_direct(float2 *__restrict__ amp,
     }
 }
 
-// One gate on a tile held in LDS: every group of the tile is owned by one
-// work-item, which gathers its 2^K amplitudes, multiplies, and writes back
-// in place.
+// One gate on a tile held in LDS with VALU multiply-adds: every group of the
+// tile is owned by one work-item, which gathers its 2^K amplitudes,
+// multiplies, and writes back in place.  `m` is the matrix: a global
+// address for K <= 2 (wave-uniform, so the entries arrive through scalar
+// loads) or an LDS copy for K = 5.
 template <int K>
-__device__ __forceinline__ void tile_gate(float2 *__restrict__ sd, const float2 *__restrict__ sm,
-                                          const int *lt, int tb) {
+__device__ __forceinline__ void tile_gate_valu(float2 *__restrict__ sd, const float2 *__restrict__ m,
+                                               const int *lt, int tb) {
     constexpr int D = 1 << K;
     int off[D];
 #pragma unroll
@@ -121,21 +137,160 @@ __device__ __forceinline__ void tile_gate(float2 *__restrict__ sd, const float2 
         for (int j = 0; j < D; ++j) {
             float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int l = 0; l < D; ++l) acc = cmac(acc, sm[j * D + l], v[l]);
+            for (int l = 0; l < D; ++l) acc = cmac(acc, m[j * D + l], v[l]);
             sd[lb + off[j]] = acc;
         }
     }
 }
 
+// K <= 2: the matrix (at most 16 entries) sits in SGPRs for the whole tile.
+template <int K>
+__device__ __forceinline__ void tile_gate_small(float2 *__restrict__ sd, const float2 *gm,
+                                                const int *lt, int tb) {
+    constexpr int D = 1 << K;
+    float2 u[D * D];
+#pragma unroll
+    for (int i = 0; i < D * D; ++i) u[i] = const_entry(gm, i);
+    int off[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) off[j] = local_offset<K, int>(j, lt);
+    const int groups = 1 << (tb - K);
+    for (int gg = threadIdx.x; gg < groups; gg += kBlock) {
+        const int lb = spread_index<K, int>(gg, lt);
+        float2 v[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = sd[lb + off[j]];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc = cmac(acc, u[j * D + l], v[l]);
+            sd[lb + off[j]] = acc;
+        }
+    }
+}
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// A fused k-qubit block is a dense contraction W = U V over the tile's
+// 2^(tb-k) index groups.  For k = 3, 4 it runs on FP32 MFMA with U in its
+// real form [[Re U, -Im U], [Im U, Re U]], rows and columns interleaved as
+// 2 j + c (c = 0 real, 1 imaginary).  The A operand (the real form) is laid
+// out per lane once per launch ("fragments"); B comes from the tile in LDS.
+
+// Real-form entry (row 2 jo + co, column 2 ji + ci) of a complex matrix.
+__device__ __forceinline__ float real_form(float2 u, int co, int ci) {
+    return co == 0 ? (ci == 0 ? u.x : -u.y) : (ci == 0 ? u.y : u.x);
+}
+
+// k = 4, v_mfma_f32_32x32x2f32: lane l supplies A[l%32][l/32] and B[l/32][l%32]
+// per step; step s covers real columns 2s, 2s+1, ordered so that lane half
+// h = l/32 reads amplitude j = 2(s/2) + h and uses its component s%2.
+// Fragment layout: frag[lane * 16 + s].
+__device__ __forceinline__ void stage_frag4(float *__restrict__ frag, const float2 *__restrict__ u) {
+    for (int i = threadIdx.x; i < 64 * 16; i += kBlock) {
+        const int lane = i >> 4, s = i & 15;
+        const int m = lane & 31, h = lane >> 5;
+        const int ji = 2 * (s >> 1) + h;
+        frag[i] = real_form(u[(m >> 1) * 16 + ji], m & 1, s & 1);
+    }
+}
+
+// k = 3, v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16] and B[l/16][l%16];
+// step s covers real columns 4s..4s+3: lane quarter q = l/16 reads amplitude
+// j = 2s + q/2 and uses component q%2.  Fragment layout: frag[lane * 4 + s].
+__device__ __forceinline__ void stage_frag3(float *__restrict__ frag, const float2 *__restrict__ u) {
+    for (int i = threadIdx.x; i < 64 * 4; i += kBlock) {
+        const int lane = i >> 2, s = i & 3;
+        const int m = lane & 15, q = lane >> 4;
+        const int ji = 2 * s + (q >> 1);
+        frag[i] = real_form(u[(m >> 1) * 8 + ji], m & 1, q & 1);
+    }
+}
+
+// 32 groups per wavefront iteration.  Output rows 8(r/4) + 4h + r%4 of the
+// accumulator r pair up as (re, im) of amplitudes jo = 4(r/4)/... so each lane
+// writes 8 whole complex amplitudes.  All LDS reads of an iteration precede
+// its writes (the MFMAs consume every loaded value first), and one
+// iteration's groups are disjoint from every other's.
+__device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const float *__restrict__ frag,
+                                                const int *lt, int tb) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 31, h = lane >> 5;
+    const f32x4 *fp = reinterpret_cast<const f32x4 *>(frag + lane * 16);
+    const f32x4 a0 = fp[0], a1 = fp[1], a2 = fp[2], a3 = fp[3];
+    const float afr[16] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3],
+                           a2[0], a2[1], a2[2], a2[3], a3[0], a3[1], a3[2], a3[3]};
+    int off_in[8], off_out[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        off_in[i] = local_offset<4, int>(2 * i + h, lt);
+        const int r = 2 * i;
+        const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+        off_out[i] = local_offset<4, int>(row >> 1, lt);
+    }
+    const int batches = 1 << (tb - 4 - 5);
+    for (int b = wave; b < batches; b += kBlock / 64) {
+        const int lb = spread_index<4, int>(b * 32 + n, lt);
+        float2 v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = sd[lb + off_in[i]];
+        f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const float bv = (s & 1) ? v[s >> 1].y : v[s >> 1].x;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[s], bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) sd[lb + off_out[i]] = make_float2(acc[2 * i], acc[2 * i + 1]);
+    }
+}
+
+// 16 groups per wavefront iteration; the accumulator rows 4q + r give lane
+// quarter q the amplitudes 2q (r = 0, 1) and 2q + 1 (r = 2, 3).
+__device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const float *__restrict__ frag,
+                                                const int *lt, int tb) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, q = lane >> 4;
+    const f32x4 afr = *reinterpret_cast<const f32x4 *>(frag + lane * 4);
+    int off_in[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) off_in[s] = local_offset<3, int>(2 * s + (q >> 1), lt);
+    const int off_o0 = local_offset<3, int>(2 * q, lt);
+    const int off_o1 = local_offset<3, int>(2 * q + 1, lt);
+    const bool im = (q & 1) != 0;
+    const int batches = 1 << (tb - 3 - 4);
+    for (int b = wave; b < batches; b += kBlock / 64) {
+        const int lb = spread_index<3, int>(b * 16 + n, lt);
+        float bv[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float2 v = sd[lb + off_in[s]];
+            bv[s] = im ? v.y : v.x;
+        }
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[s], bv[s], acc, 0, 0, 0);
+        // every lane's reads of this iteration are complete before any write
+        __builtin_amdgcn_wave_barrier();
+        sd[lb + off_o0] = make_float2(acc[0], acc[1]);
+        sd[lb + off_o1] = make_float2(acc[2], acc[3]);
+    }
+}
+
 // Tiled path: persistent workgroups stage every gate matrix of the launch in
-// LDS once, then loop over tiles of 2^TB amplitudes -- the index bits in
-// a.pos, bits 0..5 first, so each wavefront load is a 512 B row.  A tile is
-// written to LDS, the next tile's loads are issued into registers, the
-// gates run on the LDS copy in order, and the tile is written back: any
-// number of gates inside the tile cost one HBM read and one write.
+// LDS once (as MFMA fragments for k = 3, 4; plain for k = 5; k <= 2 matrices
+// stay in global memory and arrive through scalar loads), then loop over
+// tiles of 2^TB amplitudes -- the index bits in a.pos, bits 0..5 first, so
+// each wavefront load is a 512 B row.  A tile is written to LDS, the next
+// tile's loads are issued into registers, the gates run on the LDS copy in
+// order, and the tile is written back: any number of gates inside the tile
+// cost one HBM read and one write.
 template <int TB, typename Idx>
 __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, Idx n_tiles,
                                                      TileArgs a) {
+    static_assert(TB >= 10, "the MFMA gates need at least 32 groups per tile");
     constexpr int E = 1 << TB;
     constexpr int R = E / kBlock;
     extern __shared__ float2 smem[];
@@ -172,10 +327,16 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
         for (int r = 0; r < R; ++r) v[r] = amp[base + off_r[r]];
     }
     for (int gi = 0; gi < a.n_gates; ++gi) {
-        const int dd = 1 << (2 * a.g[gi].k);
+        const int k = a.g[gi].k;
         const float2 *src = a.g[gi].mat;
         float2 *dst = sm + a.g[gi].lofs;
-        for (int i = threadIdx.x; i < dd; i += kBlock) dst[i] = src[i];
+        if (k == 4) {
+            stage_frag4(reinterpret_cast<float *>(dst), src);
+        } else if (k == 3) {
+            stage_frag3(reinterpret_cast<float *>(dst), src);
+        } else if (k == 5) {
+            for (int i = threadIdx.x; i < 1024; i += kBlock) dst[i] = src[i];
+        }
     }
     for (; tile < n_tiles; tile += gridDim.x) {
         __syncthreads();  // the previous tile is out of LDS; matrices staged
@@ -194,13 +355,12 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
             int lt[kMaxGateQubits];
 #pragma unroll
             for (int b = 0; b < kMaxGateQubits; ++b) lt[b] = a.g[gi].lt[b];
-            const float2 *m = sm + a.g[gi].lofs;
             switch (k) {
-                case 1: tile_gate<1>(sd, m, lt, TB); break;
-                case 2: tile_gate<2>(sd, m, lt, TB); break;
-                case 3: tile_gate<3>(sd, m, lt, TB); break;
-                case 4: tile_gate<4>(sd, m, lt, TB); break;
-                default: tile_gate<5>(sd, m, lt, TB); break;
+                case 1: tile_gate_small<1>(sd, a.g[gi].mat, lt, TB); break;
+                case 2: tile_gate_small<2>(sd, a.g[gi].mat, lt, TB); break;
+                case 3: tile_gate_mfma3(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs), lt, TB); break;
+                case 4: tile_gate_mfma4(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs), lt, TB); break;
+                default: tile_gate_valu<5>(sd, sm + a.g[gi].lofs, lt, TB); break;
             }
             __syncthreads();
         }
@@ -514,8 +674,6 @@ hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
 template <typename Idx>
 hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
     switch (a.tb) {
-        case 8: return tile_launch<8, Idx>(amp, n, a, st);
-        case 9: return tile_launch<9, Idx>(amp, n, a, st);
         case 10: return tile_launch<10, Idx>(amp, n, a, st);
         case 11: return tile_launch<11, Idx>(amp, n, a, st);
         case 12: return tile_launch<12, Idx>(amp, n, a, st);
@@ -576,7 +734,7 @@ bool tile_for_gate(int n, const GateDesc &g, TileArgs &a) {
     for (int q = 0; q < n; ++q)
         if (in_tile[q]) a.pos[i++] = q;
     a.n_gates = 1;
-    a.mat_total = 1 << (2 * g.k);
+    a.mat_total = tile_mat_slots(g.k);
     a.g[0].k = g.k;
     a.g[0].lofs = 0;
     a.g[0].pad = 0;
@@ -601,13 +759,13 @@ hipError_t launch_apply_gate(float2 *amp, int n, const GateDesc &g, const float2
 }
 
 hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
-    if (a.tb < 8 || a.tb > kMaxTileBits || a.tb > n || a.n_gates < 0 ||
+    if (a.tb < 10 || a.tb > kMaxTileBits || a.tb > n || a.n_gates < 0 ||
         a.n_gates > kMaxTileGates || a.mat_total < 0 || a.mat_total > kTileMatBudget)
         return hipErrorInvalidValue;
     for (int gi = 0; gi < a.n_gates; ++gi) {
         const TileGate &g = a.g[gi];
         if (g.k < 1 || g.k > kMaxGateQubits || g.k > a.tb || !g.mat || g.lofs < 0 ||
-            g.lofs + (1 << (2 * g.k)) > a.mat_total)
+            g.lofs + tile_mat_slots(g.k) > a.mat_total)
             return hipErrorInvalidValue;
         for (int b = 0; b < g.k; ++b)
             if (g.lt[b] < 0 || g.lt[b] >= a.tb || (b > 0 && g.lt[b] <= g.lt[b - 1]))

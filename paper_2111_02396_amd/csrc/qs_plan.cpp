@@ -260,7 +260,8 @@ void to_ascending_order(int k, const int *t, const cd *in, cd *out, int *t_sorte
 }
 
 std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, int max_bits,
-                                int low_bits, int max_blocks, int mat_budget) {
+                                int low_bits, int max_blocks, int mat_budget,
+                                const int *slot_per_k) {
     const int nb = int(blocks.size());
     // predecessor counts and successor lists from per-qubit chains
     std::vector<int> last(n_qubits, -1);
@@ -299,7 +300,7 @@ std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, 
                 int growth = 0;
                 for (int j = 0; j < blocks[b].k; ++j) growth += in[blocks[b].q[j]] ? 0 : 1;
                 if (nbits + growth > max_bits) continue;
-                if (mats + (1 << (2 * blocks[b].k)) > mat_budget) continue;
+                if (mats + slot_per_k[blocks[b].k] > mat_budget) continue;
                 if (growth < best_growth || (growth == best_growth && b < best)) {
                     best = b;
                     best_pos = i;
@@ -309,7 +310,7 @@ std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, 
             if (best < 0 || int(sw.blocks.size()) >= max_blocks) break;
             ready.erase(ready.begin() + best_pos);
             sw.blocks.push_back(best);
-            mats += 1 << (2 * blocks[best].k);
+            mats += slot_per_k[blocks[best].k];
             for (int j = 0; j < blocks[best].k; ++j) {
                 const int q = blocks[best].q[j];
                 if (!in[q]) {

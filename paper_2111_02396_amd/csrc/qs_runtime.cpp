@@ -68,6 +68,12 @@ struct qs_state_s {
 
 namespace {
 
+const int *tile_slots() {
+    static const int slots[6] = {0, qs::tile_mat_slots(1), qs::tile_mat_slots(2),
+                                 qs::tile_mat_slots(3), qs::tile_mat_slots(4), qs::tile_mat_slots(5)};
+    return slots;
+}
+
 qs_status device_fail(qs_state s, hipError_t e, const char *what) {
     if (s) s->poisoned = true;
     return fail(QS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -959,7 +965,7 @@ struct Runner {
         layouts.clear();
         if (T >= 10 && m.n >= qs::kTileMinQubits) {
             sweeps = qs::group_sweeps(m.n, blocks, std::min(T, m.n), 6, qs::kMaxTileGates,
-                                      qs::kTileMatBudget);
+                                      qs::kTileMatBudget, tile_slots());
         } else {
             for (size_t b = 0; b < blocks.size(); ++b) {
                 qs::Sweep sw;
@@ -1015,7 +1021,7 @@ struct Runner {
             for (int b = 0; b < d->g.k; ++b) g.lt[b] = L.local[d->g.t[b]];
             g.lofs = lofs;
             g.mat = d->dev;
-            lofs += 1 << (2 * d->g.k);
+            lofs += qs::tile_mat_slots(d->g.k);
             lb += d->log_bound;
             res.gate_k_launches[d->g.k]++;
         }
@@ -1395,7 +1401,8 @@ qs_status qs_sweep_plan(const qs_circuit *c, int max_fuse, int tile_bits, int32_
     const int T = tile_bits == 0 ? qs::kMaxTileBits : tile_bits;
     std::vector<qs::Sweep> sw;
     if (T >= 10 && m.n >= qs::kTileMinQubits) {
-        sw = qs::group_sweeps(m.n, blocks, std::min(T, m.n), 6, qs::kMaxTileGates, qs::kTileMatBudget);
+        sw = qs::group_sweeps(m.n, blocks, std::min(T, m.n), 6, qs::kMaxTileGates, qs::kTileMatBudget,
+                              tile_slots());
     } else {
         for (size_t b = 0; b < blocks.size(); ++b) {
             qs::Sweep one;
