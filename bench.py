@@ -97,6 +97,11 @@ def main() -> int:
                     help="trajectories timed with the conventional method (0 = skip)")
     ap.add_argument("--cpu-cycles", type=int, default=1,
                     help="cycles of trajectory 0 timed on the oracle (0 = skip)")
+    ap.add_argument("--workload", default="grid24", choices=["grid24", "batched", "serving"],
+                    help="grid24 (default): the headline line; batched / serving: the other forms")
+    ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
+    ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals/s (0 = ~70%% load)")
+    ap.add_argument("--max-qubits", type=int, default=26, help="serving: largest request")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -115,6 +120,10 @@ def main() -> int:
         return 2
     qs.load()
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     w = W.grid24_workload(p_dep=args.p_dep)
     c = w.circuit
     n = c.n
@@ -230,6 +239,96 @@ def main() -> int:
         "sweeps_per_traj": sweeps / total_traj,
         "slow_paths_per_traj": slow / total_traj,
         "gate_width_histogram": k_hist[1:],
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_batched(args) -> int:
+    """4096 trajectories = 256 circuits x 16, n ~ U{12..18}, depth ~ U{10..40},
+    depolarizing 1e-3, in one persistent launch; the same work one trajectory
+    per qs_run_trajectories call on a sample is the comparison."""
+    import torch
+
+    import paper_2111_02396_amd as qs
+    import workloads as W
+
+    items = W.batched_workload()
+    n_traj = sum(w.n_traj for w in items)
+    for _ in range(args.warmup):
+        qs.qs_run_batched(items)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(args.steps):
+        _, stats = qs.qs_run_batched(items, time_kernels=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = args.steps * n_traj / dt
+    # one trajectory per call, on every 16th circuit's trajectories
+    sample = items[::16]
+    t1 = time.perf_counter()
+    done = 0
+    for w in sample:
+        with qs.State(w.circuit.n) as st:
+            for t in range(w.n_traj):
+                qs.qs_run_trajectories(st.h, w.circuit, 1, seed=w.seed, traj_offset=t,
+                                       circuit_id=w.circuit_id, n_samples=w.n_samples,
+                                       max_fuse=3, record_choices=False)
+                done += 1
+    dt1 = time.perf_counter() - t1
+    per_call = done / dt1
+    out = {
+        "metric": "batched trajectories/s (persistent launch)",
+        "value": value, "unit": "trajectories/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": "batched 256 circuits x 16 trajectories, n 12-18, depth 10-40, "
+                               "depolarizing 1e-3", "trajectories_per_step": n_traj},
+        "kernel_ms": stats["kernel_ms"], "plan_seconds": stats["plan_seconds"],
+        "resident_jobs": stats["resident_jobs"],
+        "one_trajectory_per_call": {"value": per_call, "unit": "trajectories/s",
+                                    "sample": f"{done} trajectories of {len(sample)} circuits"},
+        "speedup_vs_one_per_call": value / per_call,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_serving(args) -> int:
+    """Poisson arrivals of random grid circuits (n uniform up to --max-qubits,
+    depth 10-40, depolarizing log-uniform in [1e-4, 1e-2], 1-1000
+    trajectories, one shot each), admission by 16 * 2^n bytes."""
+    import paper_2111_02396_amd as qs  # noqa: F401
+    from paper_2111_02396_amd import serving
+    import workloads as W
+
+    def requests(rate):
+        return W.serving_requests(args.requests, rate, seed=1, n_hi=args.max_qubits)
+
+    rate = args.rate
+    if rate <= 0:
+        # offered load ~70%: modelled service time from a 6 TB/s sweep rate
+        reqs = requests(1.0)
+        work = sum(r.workload.n_traj * 30 * 16.0 * (1 << r.workload.circuit.n) / 6e12
+                   + 2e-4 for r in reqs)
+        rate = 0.7 * len(reqs) / work
+    reqs = requests(rate)
+    srv = serving.Server()
+    stats = srv.run(reqs)
+    d = stats.as_dict()
+    lanes = {}
+    for r in reqs:
+        lanes[srv.results[r.rid].lane] = lanes.get(srv.results[r.rid].lane, 0) + 1
+    out = {
+        "metric": "served trajectories/s; p50/p99 request latency",
+        "value": d["trajectories_per_s"], "unit": "trajectories/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": 1e3 * d["wall_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"serving {args.requests} requests, Poisson {rate:.2f}/s, "
+                               f"n 10-{args.max_qubits}"},
+        "p50_s": d["p50_s"], "p99_s": d["p99_s"], "requests": d["requests"], "lanes": lanes,
+        "errors": sum(1 for r in reqs if srv.results[r.rid].error),
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -214,6 +214,55 @@ qs_status qs_sample_measurements(qs_state s, uint64_t seed, uint32_t traj, int n
 qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_params *p,
                               qs_traj_result *r);
 
+/* ---- batched persistent launch ------------------------------------------ */
+
+/* One circuit of a batched launch and where its results go. */
+typedef struct {
+    const qs_circuit *circuit; /* 1 <= n_qubits <= 18; every channel a mixture of unitaries
+                                  (all K_i^dag K_i multiples of I, so Algorithm 2 never
+                                  needs inner products) */
+    int64_t n_traj;            /* trajectories traj_offset .. traj_offset+n_traj-1 */
+    int64_t traj_offset;
+    uint64_t seed;             /* Philox key */
+    uint32_t circuit_id;       /* Philox counter word 2 */
+    int32_t n_samples;         /* per trajectory, 0..4096 */
+    const double *p0to1;       /* per-qubit readout P(1|0), host, or NULL */
+    const double *p1to0;       /* per-qubit readout P(0|1), host, or NULL */
+    uint64_t *bitstrings;      /* host out [n_traj * n_samples] */
+    int8_t *kraus_choices;     /* host out [n_traj * n_channels], or NULL */
+} qs_batch_item;
+
+typedef struct {
+    int32_t max_fuse;          /* 0 = library default (3) */
+    uint32_t flags;            /* QS_TRAJ_TIME_KERNELS: time the launch with HIP events */
+    void *hip_stream;          /* hipStream_t, or NULL */
+} qs_batch_params;
+
+typedef struct {
+    int64_t jobs;              /* trajectories run */
+    int64_t resident_jobs;     /* of which kept their state in LDS throughout */
+    int64_t gate_blocks;       /* fused blocks applied, summed over trajectories */
+    double host_seconds;       /* wall time of the call */
+    double plan_seconds;       /* host planning (draws, patched blocks, packing) */
+    double kernel_ms;          /* QS_TRAJ_TIME_KERNELS: the persistent launch */
+} qs_batch_result;
+
+/* Many small noisy circuits in ONE persistent kernel launch (Section 3.5's
+ * trajectories, run side by side).  Every trajectory's draws are resolved
+ * from the Kraus bounds on the host (mixtures only), each circuit is fused
+ * once (Section 3.2) and a trajectory carries only the blocks whose picks
+ * differ from the circuit's most likely ones.  On the device each
+ * workgroup takes trajectories in turn: a state of n <= 13 qubits lives in
+ * LDS for the whole trajectory; a larger one streams 2^12-amplitude tiles
+ * of a per-workgroup slot in device memory, one pass per tile sweep.  The
+ * workgroup then samples with readout flips exactly as
+ * qs_sample_measurements does (same Philox streams, circuit id from the
+ * item).  Results are written to each item's host arrays.
+ * Errors: INVALID_ARGUMENT, NOT_SUPPORTED (n > 18, a channel that is not a
+ * mixture), OUT_OF_MEMORY, DEVICE. */
+qs_status qs_run_batched(const qs_batch_item *items, int n_items, const qs_batch_params *p,
+                         qs_batch_result *r);
+
 /* ---- host-side helpers (no device work) --------------------------------- */
 
 /* Kraus lower bounds pbar_i = lambda_min(K_i^dag K_i), clamped at 0

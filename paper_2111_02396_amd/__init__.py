@@ -72,6 +72,25 @@ class QsTrajResult(ctypes.Structure):
                 ("gate_k_launches", ctypes.c_int64 * 6)]
 
 
+class QsBatchItem(ctypes.Structure):
+    _fields_ = [("circuit", ctypes.c_void_p), ("n_traj", ctypes.c_int64),
+                ("traj_offset", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("circuit_id", ctypes.c_uint32), ("n_samples", ctypes.c_int32),
+                ("p0to1", ctypes.c_void_p), ("p1to0", ctypes.c_void_p),
+                ("bitstrings", ctypes.c_void_p), ("kraus_choices", ctypes.c_void_p)]
+
+
+class QsBatchParams(ctypes.Structure):
+    _fields_ = [("max_fuse", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("hip_stream", ctypes.c_void_p)]
+
+
+class QsBatchResult(ctypes.Structure):
+    _fields_ = [("jobs", ctypes.c_int64), ("resident_jobs", ctypes.c_int64),
+                ("gate_blocks", ctypes.c_int64), ("host_seconds", ctypes.c_double),
+                ("plan_seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
+
+
 def load():
     """Load libqs.so (built by __graft_entry__.build()); raises if absent."""
     global _lib
@@ -101,6 +120,7 @@ def load():
         "qs_fusion_plan": [vp, i32, vp, vp, vp, vp, vp],
         "qs_philox4x32_10": [vp, vp, vp],
         "qs_sweep_plan": [vp, i32, i32, vp, vp, vp, vp],
+        "qs_run_batched": [vp, i32, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -295,6 +315,46 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
         out["choices"] = choices[:n_traj * nch].reshape(n_traj, nch)
         out["paths"] = paths[:n_traj * nch].reshape(n_traj, nch)
     return out
+
+
+def qs_run_batched(workloads, max_fuse: int = 0, hip_stream: Optional[int] = None,
+                   time_kernels: bool = False, record_choices: bool = True):
+    """Run TrajectoryWorkload-like objects (circuit, n_traj, seed, circuit_id,
+    n_samples, e0, e1, and optional traj_offset) in one persistent launch."""
+    keep = []
+    items = (QsBatchItem * max(len(workloads), 1))()
+    outs = []
+    for i, w in enumerate(workloads):
+        mc = MarshalledCircuit(w.circuit)
+        e0 = None if w.e0 is None else np.ascontiguousarray(w.e0, dtype=np.float64)
+        e1 = None if w.e1 is None else np.ascontiguousarray(w.e1, dtype=np.float64)
+        bits = np.zeros(max(w.n_traj * w.n_samples, 1), dtype=np.uint64)
+        ch = np.zeros(max(w.n_traj * mc.n_channels, 1), dtype=np.int8) if record_choices else None
+        keep += [mc, e0, e1, bits, ch]
+        it = items[i]
+        it.circuit = ctypes.cast(ctypes.pointer(mc.c), ctypes.c_void_p)
+        it.n_traj = w.n_traj
+        it.traj_offset = getattr(w, "traj_offset", 0)
+        it.seed = w.seed
+        it.circuit_id = w.circuit_id
+        it.n_samples = w.n_samples
+        it.p0to1, it.p1to0 = _p(e0), _p(e1)
+        it.bitstrings = _p(bits)
+        it.kraus_choices = _p(ch)
+        outs.append((bits, ch, mc.n_channels, w))
+    params = QsBatchParams(max_fuse, QS_TRAJ_TIME_KERNELS if time_kernels else 0, hip_stream)
+    res = QsBatchResult()
+    _check(load().qs_run_batched(items, len(workloads), ctypes.byref(params), ctypes.byref(res)))
+    results = []
+    for bits, ch, nch, w in outs:
+        d = {"samples": bits[:w.n_traj * w.n_samples].reshape(w.n_traj, w.n_samples)}
+        if ch is not None:
+            d["choices"] = ch[:w.n_traj * nch].reshape(w.n_traj, nch)
+        results.append(d)
+    stats = {"jobs": res.jobs, "resident_jobs": res.resident_jobs, "gate_blocks": res.gate_blocks,
+             "host_seconds": res.host_seconds, "plan_seconds": res.plan_seconds,
+             "kernel_ms": res.kernel_ms}
+    return results, stats
 
 
 def qs_fusion_plan(circuit, max_fuse: int):

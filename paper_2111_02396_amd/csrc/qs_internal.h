@@ -68,6 +68,64 @@ struct TileArgs {
     TileGate g[kMaxTileGates];
 };
 
+// ---- batched persistent launch -------------------------------------------
+// Device program of many small circuits, run one trajectory per workgroup
+// iteration.  A circuit whose state fits in LDS (n <= kBatchLdsQubits) keeps
+// it there for the whole trajectory; larger ones stream tiles of a per-
+// workgroup global slot, one pass per sweep.
+constexpr int kBatchLdsQubits = 13;
+constexpr int kBatchMaxQubits = 18;
+constexpr int kBatchTileBits = 12;
+constexpr int kBatchMaxSamples = 4096;
+
+struct BatchGate {
+    int k;
+    int lt[kMaxGateQubits];  // ascending; global bits (resident) or tile-local bits
+    int mat;                 // float2 offset of the default matrix in the pool
+};
+
+struct BatchSweep {
+    int tb;                  // tile bits (tiled circuits); n for resident ones
+    int pos[kMaxTileBits];
+    int g0, g1;              // gate range
+};
+
+struct BatchCircuit {
+    int n;
+    int resident;
+    int s0, s1;              // sweep range
+    int n_samples;
+    int readout;             // offset of 2n doubles (e0[], e1[]) in the readout pool, or -1
+};
+
+struct BatchJob {
+    int circuit;
+    uint32_t traj;           // Philox counter word 1
+    uint32_t circ_id;        // Philox counter word 2
+    int p0, p1;              // patch range
+    uint64_t seed;           // Philox key
+    int64_t out;             // first output sample
+};
+
+struct BatchPatch {
+    int gate;                // absolute gate index
+    int mat;                 // float2 offset of the trajectory's matrix
+};
+
+struct BatchArgs {
+    const BatchCircuit *circs;
+    const BatchSweep *sweeps;
+    const BatchGate *gates;
+    const BatchPatch *patches;
+    const BatchJob *jobs;
+    const float2 *mats;
+    const double *readout;
+    float2 *slots;           // per-workgroup state slots (tiled circuits)
+    int64_t slot_amps;
+    uint64_t *out;
+    int n_jobs;
+};
+
 struct ReadoutDesc {
     int enabled;
     double e0[kMaxQubits];  // P(read 1 | 0)
@@ -112,5 +170,12 @@ hipError_t launch_sample(const float2 *amp, int n, double *sums, double *incl,
                          uint64_t seed, uint32_t traj, uint32_t circ, int n_samples,
                          const ReadoutDesc &ro, uint64_t *out_dev, double *norm_dev,
                          hipStream_t st);
+
+// One persistent launch over all jobs; `grid` workgroups, each owning slot
+// blockIdx.x of `slots` when it runs a tiled circuit.
+hipError_t launch_batched(const BatchArgs &a, int grid, hipStream_t st);
+
+// Workgroups the batched launch uses (persistent grid size).
+int batched_grid();
 
 }  // namespace qs

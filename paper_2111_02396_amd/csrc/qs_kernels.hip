@@ -338,12 +338,17 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
             for (int i = threadIdx.x; i < 1024; i += kBlock) dst[i] = src[i];
         }
     }
-    for (; tile < n_tiles; tile += gridDim.x) {
+    // One tile: the prefetched amplitudes go to LDS, the next tile's loads are
+    // issued, the gates run, the tile is stored.  The first tile is peeled off
+    // the loop so that at the loop head the only pending memory operations are
+    // the prefetch loads followed by the previous tile's stores; the wait for
+    // the loads then leaves the younger stores in flight.
+    auto run_tile = [&](Idx t) {
         __syncthreads();  // the previous tile is out of LDS; matrices staged
 #pragma unroll
         for (int r = 0; r < R; ++r) sd[threadIdx.x + (r << 8)] = v[r];
-        const Idx base = tile_base(tile);
-        const Idx next = tile + gridDim.x;
+        const Idx base = tile_base(t);
+        const Idx next = t + gridDim.x;
         if (next < n_tiles) {
             const Idx nb = tile_base(next);
 #pragma unroll
@@ -366,6 +371,176 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) amp[base + off_r[r]] = sd[threadIdx.x + (r << 8)];
+    };
+    run_tile(tile);
+    for (tile += gridDim.x; tile < n_tiles; tile += gridDim.x) run_tile(tile);
+}
+
+// ---------------------------------------------------------------- batched
+
+// One fused block on amplitudes held in LDS (a whole resident state, or a
+// tile).  Fragments for the MFMA gates are staged per block; the trailing
+// barrier lets the next block reuse the staging area.
+__device__ __forceinline__ void batched_gate(float2 *__restrict__ sd, float *__restrict__ frag,
+                                             const BatchGate &g, const float2 *__restrict__ m,
+                                             int tb) {
+    int lt[kMaxGateQubits];
+#pragma unroll
+    for (int b = 0; b < kMaxGateQubits; ++b) lt[b] = g.lt[b];
+    if (g.k == 1) {
+        tile_gate_small<1>(sd, m, lt, tb);
+    } else if (g.k == 2) {
+        tile_gate_small<2>(sd, m, lt, tb);
+    } else if (g.k == 3 && tb >= 10) {
+        stage_frag3(frag, m);
+        __syncthreads();
+        tile_gate_mfma3(sd, frag, lt, tb);
+    } else if (g.k == 4 && tb >= 10) {
+        stage_frag4(frag, m);
+        __syncthreads();
+        tile_gate_mfma4(sd, frag, lt, tb);
+    } else {
+        const int dd = 1 << (2 * g.k);
+        float2 *mm = reinterpret_cast<float2 *>(frag);
+        for (int i = threadIdx.x; i < dd; i += kBlock) mm[i] = m[i];
+        __syncthreads();
+        switch (g.k) {
+            case 3: tile_gate_valu<3>(sd, mm, lt, tb); break;
+            case 4: tile_gate_valu<4>(sd, mm, lt, tb); break;
+            default: tile_gate_valu<5>(sd, mm, lt, tb); break;
+        }
+    }
+    __syncthreads();
+}
+
+// Persistent launch: each workgroup takes jobs blockIdx.x, + gridDim.x, ...
+// A job is one trajectory: the state starts as |0...0>, the circuit's blocks
+// run with this trajectory's patched matrices in place of the defaults, and
+// the workgroup samples the final state (inverse CDF over 256 contiguous
+// chunks whose FP64 sums are scanned in order; readout flips as in
+// sample_draw).
+__global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
+    extern __shared__ float2 smem[];
+    float2 *sd = smem;                                                   // 2^13 amplitudes
+    float *frag = reinterpret_cast<float *>(smem + (1 << kBatchLdsQubits));  // 2048 floats
+    __shared__ double part[kBlock];
+    float2 *slot = A.slots ? A.slots + size_t(blockIdx.x) * size_t(A.slot_amps) : nullptr;
+    for (int job = blockIdx.x; job < A.n_jobs; job += gridDim.x) {
+        const BatchJob J = A.jobs[job];
+        const BatchCircuit C = A.circs[J.circuit];
+        const int n = C.n;
+        const int dim = 1 << n;
+        float2 *state = C.resident ? sd : slot;
+        for (int i = threadIdx.x; i < dim; i += kBlock)
+            state[i] = make_float2(i == 0 ? 1.f : 0.f, 0.f);
+        if (!C.resident) __threadfence();
+        __syncthreads();
+        int p = J.p0;
+        for (int si = C.s0; si < C.s1; ++si) {
+            const BatchSweep &S = A.sweeps[si];
+            if (C.resident) {
+                for (int gi = S.g0; gi < S.g1; ++gi) {
+                    const BatchGate g = A.gates[gi];
+                    int mo = g.mat;
+                    if (p < J.p1 && A.patches[p].gate == gi) mo = A.patches[p++].mat;
+                    batched_gate(sd, frag, g, A.mats + mo, n);
+                }
+                continue;
+            }
+            // tiled: one pass over the slot, tile by tile
+            const int tb = S.tb;
+            const int R = (1 << tb) / kBlock;
+            int off_tid = 0;
+            for (int b = 0; b < 8; ++b)
+                if ((threadIdx.x >> b) & 1) off_tid |= 1 << S.pos[b];
+            const int n_tiles = dim >> tb;
+            const int p_sweep = p;
+            for (int t = 0; t < n_tiles; ++t) {
+                int base = t;
+                for (int b = 0; b < tb; ++b) {
+                    const int q = S.pos[b];
+                    base = ((base >> q) << (q + 1)) | (base & ((1 << q) - 1));
+                }
+                base += off_tid;
+                for (int r = 0; r < R; ++r) {
+                    int o = 0;
+                    for (int b = 8; b < tb; ++b)
+                        if (((r << 8) >> b) & 1) o |= 1 << S.pos[b];
+                    sd[threadIdx.x + (r << 8)] = slot[base + o];
+                }
+                __syncthreads();
+                p = p_sweep;
+                for (int gi = S.g0; gi < S.g1; ++gi) {
+                    const BatchGate g = A.gates[gi];
+                    int mo = g.mat;
+                    if (p < J.p1 && A.patches[p].gate == gi) mo = A.patches[p++].mat;
+                    batched_gate(sd, frag, g, A.mats + mo, tb);
+                }
+                for (int r = 0; r < R; ++r) {
+                    int o = 0;
+                    for (int b = 8; b < tb; ++b)
+                        if (((r << 8) >> b) & 1) o |= 1 << S.pos[b];
+                    slot[base + o] = sd[threadIdx.x + (r << 8)];
+                }
+                __syncthreads();
+            }
+            __threadfence();  // this pass's stores reach L2, stale L1 lines go
+            __syncthreads();
+        }
+        // sampling: chunk c = amplitudes [c*L, (c+1)*L), L = dim / 256 (>= 1)
+        const int L = dim >= kBlock ? dim / kBlock : 1;
+        const int chunks = dim >= kBlock ? kBlock : dim;
+        double acc = 0.0;
+        if (int(threadIdx.x) < chunks) {
+            for (int i = 0; i < L; ++i) {
+                const float2 v = state[threadIdx.x * L + i];
+                acc = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), acc));
+            }
+        }
+        part[threadIdx.x] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double run = 0.0;
+            for (int c = 0; c < chunks; ++c) {
+                run += part[c];
+                part[c] = run;  // inclusive prefix
+            }
+        }
+        __syncthreads();
+        const double N = part[chunks - 1];
+        for (int smp = threadIdx.x; smp < C.n_samples; smp += kBlock) {
+            const double target = philox_uniform(J.seed, uint32_t(smp), J.traj, J.circ_id, kStreamMeasure) * N;
+            int lo = 0, hi = chunks;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (target < part[mid]) hi = mid; else lo = mid + 1;
+            }
+            uint32_t x;
+            if (lo >= chunks) {
+                x = uint32_t(dim - 1);
+            } else {
+                double run = lo > 0 ? part[lo - 1] : 0.0;
+                int pick = L - 1;
+                for (int i = 0; i < L; ++i) {
+                    const float2 v = state[lo * L + i];
+                    run += fma(double(v.x), double(v.x), double(v.y) * double(v.y));
+                    if (target < run) { pick = i; break; }
+                }
+                x = uint32_t(lo * L + pick);
+            }
+            if (C.readout >= 0) {
+                const double *e0 = A.readout + C.readout;
+                const double *e1 = e0 + n;
+                for (int q = 0; q < n; ++q) {
+                    const int bit = int((x >> q) & 1u);
+                    const double u = philox_uniform(J.seed, uint32_t(smp * n + q), J.traj, J.circ_id,
+                                                    kStreamReadout);
+                    if (u < (bit ? e1[q] : e0[q])) x ^= 1u << q;
+                }
+            }
+            A.out[J.out + smp] = x;
+        }
+        __syncthreads();
     }
 }
 
@@ -683,6 +858,26 @@ hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st)
 }
 
 }  // namespace
+
+int batched_grid() {
+    const int per_cu = int((160u * 1024u) / (sizeof(float2) * ((1u << kBatchLdsQubits) + 1024u) +
+                                             sizeof(double) * kBlock));
+    return device_cus() * (per_cu < 1 ? 1 : per_cu);
+}
+
+hipError_t launch_batched(const BatchArgs &a, int grid, hipStream_t st) {
+    static bool attr_set = false;
+    const size_t lds = sizeof(float2) * ((size_t(1) << kBatchLdsQubits) + 1024);
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&run_batched),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    if (grid < 1) return hipErrorInvalidValue;
+    run_batched<<<unsigned(grid), kBlock, lds, st>>>(a);
+    return hipGetLastError();
+}
 
 int reduce_blocks_for(int n, int k) {
     // at least 4 groups per work-item; a fixed count per (n, k)

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <deque>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "qs.h"
@@ -1427,3 +1428,373 @@ qs_status qs_sweep_plan(const qs_circuit *c, int max_fuse, int tile_bits, int32_
 }
 
 }  // extern "C"
+
+// --------------------------------------------------------------------------
+// Batched persistent launch: host planning.
+// --------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kBatchDefaultFuse = 3;
+
+struct BatchPlanCircuit {
+    CircuitModel m;
+    std::vector<qs::Block> blocks;
+    std::vector<int> op_block;
+    std::vector<const cd *> default_mats;
+    std::vector<int> gate_of_block;  // absolute gate index of each block
+    int64_t gate_base = 0;           // first absolute gate index
+    int64_t default_mat_base = 0;    // float2 offset of this circuit's default matrices
+    int circuit_index = 0;
+    bool resident = false;
+};
+
+// Host-side pieces produced per trajectory by the planning threads.
+struct BatchTrajOut {
+    std::vector<qs::BatchPatch> patches;  // gate index, matrix offset in `pool` (local)
+    std::vector<float2> pool;             // patched matrices
+};
+
+void to_float2(int D, const cd *m, float2 *out) {
+    for (int i = 0; i < D * D; ++i) out[i] = make_float2(float(m[i].real()), float(m[i].imag()));
+}
+
+}  // namespace
+
+extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
+                                    const qs_batch_params *bp, qs_batch_result *r) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!items || n_items < 0 || !bp || !r) return fail(QS_ERR_INVALID_ARGUMENT, "null argument");
+    if (bp->max_fuse < 0 || bp->max_fuse > qs::kMaxGateQubits)
+        return fail(QS_ERR_INVALID_ARGUMENT, "max_fuse outside 0..5");
+    const int f = bp->max_fuse > 0 ? bp->max_fuse : kBatchDefaultFuse;
+    hipStream_t st = static_cast<hipStream_t>(bp->hip_stream);
+    std::memset(r, 0, sizeof(*r));
+
+    // ---- per-circuit plans
+    std::vector<BatchPlanCircuit> plans(n_items);
+    std::vector<qs::BatchCircuit> circs(n_items);
+    std::vector<qs::BatchSweep> sweeps;
+    std::vector<qs::BatchGate> gates;
+    std::vector<float2> pool;
+    std::vector<double> readout;
+    int max_tiled_n = 0;
+    int64_t total_jobs = 0, total_samples = 0;
+    std::vector<cd> tmp(1024);
+    for (int it = 0; it < n_items; ++it) {
+        const qs_batch_item &I = items[it];
+        if (!I.circuit) return fail(QS_ERR_INVALID_ARGUMENT, "null circuit");
+        if (I.circuit->n_qubits < 1) return fail(QS_ERR_INVALID_ARGUMENT, "n out of range");
+        if (I.circuit->n_qubits > qs::kBatchMaxQubits)
+            return fail(QS_ERR_NOT_SUPPORTED, "batched circuits have at most 18 qubits");
+        if (I.n_traj < 0 || I.traj_offset < 0 || I.traj_offset + I.n_traj > (int64_t(1) << 32))
+            return fail(QS_ERR_INVALID_ARGUMENT, "trajectory range outside 32-bit counters");
+        if (I.n_samples < 0 || I.n_samples > qs::kBatchMaxSamples)
+            return fail(QS_ERR_INVALID_ARGUMENT, "n_samples outside 0..4096");
+        if (I.n_samples > 0 && I.n_traj > 0 && !I.bitstrings)
+            return fail(QS_ERR_INVALID_ARGUMENT, "null bitstrings");
+        BatchPlanCircuit &P = plans[it];
+        P.circuit_index = it;
+        QS_CHECK(build_model(I.circuit, P.m));
+        for (const auto &c : P.m.channels)
+            if (!c.mixture)
+                return fail(QS_ERR_NOT_SUPPORTED,
+                            "batched launch takes channels whose Kraus operators are all proportional to unitaries");
+        qs::ReadoutDesc ro;
+        QS_CHECK(fill_readout(P.m.n, I.p0to1, I.p1to0, ro));
+        const int n = P.m.n;
+        P.resident = n <= qs::kBatchLdsQubits;
+        if (!P.resident) max_tiled_n = std::max(max_tiled_n, n);
+        const int n_ops = int(P.m.ops.size());
+        P.default_mats.assign(n_ops, nullptr);
+        for (int o = 0; o < n_ops; ++o) {
+            if (P.m.kind[o] == QS_OP_GATE) P.default_mats[o] = P.m.gate_mat[o];
+            else {
+                const ChannelInfo &c = P.m.channels[P.m.channel_of_op[o]];
+                P.default_mats[o] = fast_pick_matrix(c, c.default_pick);
+            }
+        }
+        P.blocks = qs::fuse_greedy(n, P.m.ops, f, &P.op_block);
+        // sweeps: one for a resident state; LDS tile passes otherwise
+        std::vector<qs::Sweep> sw;
+        if (P.resident) {
+            qs::Sweep one;
+            for (size_t b = 0; b < P.blocks.size(); ++b) one.blocks.push_back(int(b));
+            sw.push_back(std::move(one));
+        } else {
+            static const int no_budget[6] = {0, 0, 0, 0, 0, 0};
+            sw = qs::group_sweeps(n, P.blocks, qs::kBatchTileBits, 6, 1 << 30, 1 << 30, no_budget);
+        }
+        qs::BatchCircuit &C = circs[it];
+        C.n = n;
+        C.resident = P.resident ? 1 : 0;
+        C.s0 = int(sweeps.size());
+        C.n_samples = I.n_samples;
+        C.readout = -1;
+        if (ro.enabled) {
+            C.readout = int(readout.size());
+            for (int q = 0; q < n; ++q) readout.push_back(ro.e0[q]);
+            for (int q = 0; q < n; ++q) readout.push_back(ro.e1[q]);
+        }
+        P.gate_base = int64_t(gates.size());
+        P.gate_of_block.assign(P.blocks.size(), -1);
+        for (const auto &w : sw) {
+            qs::BatchSweep S;
+            std::memset(&S, 0, sizeof(S));
+            int local[64];
+            for (int q = 0; q < 64; ++q) local[q] = q;
+            if (P.resident) {
+                S.tb = n;
+            } else {
+                std::vector<char> in(n, 0);
+                for (int q : w.bits) in[q] = 1;
+                int cnt = int(w.bits.size());
+                for (int q = 0; q < n && cnt < qs::kBatchTileBits; ++q)
+                    if (!in[q]) {
+                        in[q] = 1;
+                        ++cnt;
+                    }
+                if (cnt > qs::kMaxTileBits) return fail(QS_ERR_NOT_SUPPORTED, "block too wide for a tile");
+                S.tb = cnt;
+                int i = 0;
+                for (int q = 0; q < n; ++q)
+                    if (in[q]) {
+                        S.pos[i] = q;
+                        local[q] = i;
+                        ++i;
+                    }
+            }
+            S.g0 = int(gates.size());
+            for (int b : w.blocks) {
+                const qs::Block &B = P.blocks[b];
+                qs::BatchGate G;
+                std::memset(&G, 0, sizeof(G));
+                G.k = B.k;
+                for (int j = 0; j < B.k; ++j) G.lt[j] = local[B.q[j]];
+                qs::fused_matrix(B.k, B.q, B.ops, P.m.ops, P.default_mats, tmp.data());
+                const int D = 1 << B.k;
+                G.mat = int(pool.size());
+                pool.resize(pool.size() + size_t(D) * D + (D * D) % 2);
+                to_float2(D, tmp.data(), pool.data() + G.mat);
+                P.gate_of_block[b] = int(gates.size());
+                gates.push_back(G);
+            }
+            S.g1 = int(gates.size());
+            sweeps.push_back(S);
+        }
+        C.s1 = int(sweeps.size());
+        total_jobs += I.n_traj;
+        total_samples += I.n_traj * int64_t(I.n_samples);
+    }
+    if (pool.size() > (size_t(1) << 30)) return fail(QS_ERR_OUT_OF_MEMORY, "matrix pool too large");
+
+    // ---- per-trajectory draws and patched blocks, spread over host threads
+    struct JobRef {
+        int item;
+        int64_t rel;
+        double cost;
+    };
+    std::vector<JobRef> refs;
+    refs.reserve(size_t(total_jobs));
+    for (int it = 0; it < n_items; ++it)
+        for (int64_t t = 0; t < items[it].n_traj; ++t)
+            refs.push_back({it, t, double(int64_t(1) << plans[it].m.n) * double(plans[it].blocks.size())});
+    std::vector<BatchTrajOut> outs(refs.size());
+    unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nthreads = unsigned(std::min<size_t>(nthreads, std::max<size_t>(refs.size() / 64, 1)));
+    auto worker = [&](size_t lo, size_t hi) {
+        std::vector<cd> t2(1024);
+        std::vector<int> sub;
+        for (size_t j = lo; j < hi; ++j) {
+            const qs_batch_item &I = items[refs[j].item];
+            const BatchPlanCircuit &P = plans[refs[j].item];
+            const uint32_t traj = uint32_t(I.traj_offset + refs[j].rel);
+            const int nch = int(P.m.channels.size());
+            int8_t *choices = I.kraus_choices ? I.kraus_choices + refs[j].rel * nch : nullptr;
+            std::vector<std::pair<int, const cd *>> over;  // op, matrix
+            for (int c = 0; c < nch; ++c) {
+                const ChannelInfo &ci = P.m.channels[c];
+                const double rr = qs::philox_uniform(I.seed, channel_draw_index(uint32_t(c)), traj,
+                                                     I.circuit_id, qs::kStreamChannel);
+                double resid = 0.0;
+                const int pk = select_fast(ci, rr, &resid);  // mixtures always resolve here
+                if (choices) choices[c] = int8_t(pk);
+                if (pk != ci.default_pick) over.emplace_back(ci.op, fast_pick_matrix(ci, pk));
+            }
+            if (over.empty()) continue;
+            std::vector<const cd *> mats = P.default_mats;
+            std::vector<int> dirty_blocks;
+            for (auto &o : over) {
+                mats[o.first] = o.second;
+                dirty_blocks.push_back(P.op_block[o.first]);
+            }
+            std::sort(dirty_blocks.begin(), dirty_blocks.end());
+            dirty_blocks.erase(std::unique(dirty_blocks.begin(), dirty_blocks.end()), dirty_blocks.end());
+            BatchTrajOut &O = outs[j];
+            for (int b : dirty_blocks) {
+                const qs::Block &B = P.blocks[b];
+                qs::fused_matrix(B.k, B.q, B.ops, P.m.ops, mats, t2.data());
+                const int D = 1 << B.k;
+                qs::BatchPatch pt;
+                pt.gate = P.gate_of_block[b];
+                pt.mat = int(O.pool.size());
+                O.pool.resize(O.pool.size() + size_t(D) * D + (D * D) % 2);
+                to_float2(D, t2.data(), O.pool.data() + pt.mat);
+                O.patches.push_back(pt);
+            }
+            std::sort(O.patches.begin(), O.patches.end(),
+                      [](const qs::BatchPatch &a, const qs::BatchPatch &b) { return a.gate < b.gate; });
+        }
+    };
+    {
+        std::vector<std::thread> th;
+        const size_t per = (refs.size() + nthreads - 1) / std::max(nthreads, 1u);
+        for (unsigned w = 0; w < nthreads; ++w) {
+            const size_t lo = w * per, hi = std::min(refs.size(), lo + per);
+            if (lo >= hi) break;
+            th.emplace_back(worker, lo, hi);
+        }
+        for (auto &x : th) x.join();
+    }
+    // ---- jobs (largest first, so the persistent workgroups finish together)
+    std::vector<size_t> order(refs.size());
+    for (size_t j = 0; j < order.size(); ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return refs[a].cost > refs[b].cost; });
+    std::vector<qs::BatchJob> jobs(refs.size());
+    std::vector<qs::BatchPatch> patches;
+    std::vector<int64_t> item_out_base(n_items, 0);
+    {
+        int64_t acc = 0;
+        for (int it = 0; it < n_items; ++it) {
+            item_out_base[it] = acc;
+            acc += items[it].n_traj * int64_t(items[it].n_samples);
+        }
+    }
+    int64_t blocks_applied = 0, resident_jobs = 0;
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+        const size_t j = order[oi];
+        const JobRef &R = refs[j];
+        const qs_batch_item &I = items[R.item];
+        qs::BatchJob &J = jobs[oi];
+        J.circuit = R.item;
+        J.traj = uint32_t(I.traj_offset + R.rel);
+        J.circ_id = I.circuit_id;
+        J.seed = I.seed;
+        J.out = item_out_base[R.item] + R.rel * I.n_samples;
+        J.p0 = int(patches.size());
+        const int64_t shift = int64_t(pool.size());
+        for (const auto &pt : outs[j].patches) patches.push_back({pt.gate, int(pt.mat + shift)});
+        pool.insert(pool.end(), outs[j].pool.begin(), outs[j].pool.end());
+        J.p1 = int(patches.size());
+        blocks_applied += int64_t(plans[R.item].blocks.size());
+        resident_jobs += plans[R.item].resident ? 1 : 0;
+        if (pool.size() > (size_t(1) << 30)) return fail(QS_ERR_OUT_OF_MEMORY, "matrix pool too large");
+    }
+    const auto t_plan = std::chrono::steady_clock::now();
+    r->plan_seconds = std::chrono::duration<double>(t_plan - t0).count();
+    r->jobs = int64_t(jobs.size());
+    r->resident_jobs = resident_jobs;
+    r->gate_blocks = blocks_applied;
+    if (jobs.empty()) {
+        r->host_seconds = r->plan_seconds;
+        return QS_OK;
+    }
+
+    // ---- device buffers (one allocation, one upload)
+    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t b_circ = align(sizeof(qs::BatchCircuit) * circs.size());
+    const size_t b_sweep = align(sizeof(qs::BatchSweep) * std::max<size_t>(sweeps.size(), 1));
+    const size_t b_gate = align(sizeof(qs::BatchGate) * std::max<size_t>(gates.size(), 1));
+    const size_t b_patch = align(sizeof(qs::BatchPatch) * std::max<size_t>(patches.size(), 1));
+    const size_t b_job = align(sizeof(qs::BatchJob) * jobs.size());
+    const size_t b_pool = align(sizeof(float2) * std::max<size_t>(pool.size(), 1));
+    const size_t b_ro = align(sizeof(double) * std::max<size_t>(readout.size(), 1));
+    const size_t b_out = align(sizeof(uint64_t) * std::max<int64_t>(total_samples, 1));
+    const size_t total = b_circ + b_sweep + b_gate + b_patch + b_job + b_pool + b_ro + b_out;
+    const int grid = qs::batched_grid();
+    const size_t slot_amps = max_tiled_n > 0 ? size_t(1) << max_tiled_n : 0;
+    const size_t b_slots = sizeof(float2) * slot_amps * size_t(grid);
+    size_t free_b = 0, total_b = 0;
+    hipError_t e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) return fail(QS_ERR_DEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+    if (free_b < total + b_slots) return fail(QS_ERR_OUT_OF_MEMORY, "batched launch does not fit in free memory");
+    char *dbuf = nullptr;
+    float2 *slots = nullptr;
+    std::vector<char> host(total, 0);
+    size_t off = 0;
+    auto put = [&](const void *src, size_t bytes, size_t cap) {
+        std::memcpy(host.data() + off, src, bytes);
+        const size_t at = off;
+        off += cap;
+        return at;
+    };
+    const size_t o_circ = put(circs.data(), sizeof(qs::BatchCircuit) * circs.size(), b_circ);
+    const size_t o_sweep = put(sweeps.data(), sizeof(qs::BatchSweep) * sweeps.size(), b_sweep);
+    const size_t o_gate = put(gates.data(), sizeof(qs::BatchGate) * gates.size(), b_gate);
+    const size_t o_patch = put(patches.data(), sizeof(qs::BatchPatch) * patches.size(), b_patch);
+    const size_t o_job = put(jobs.data(), sizeof(qs::BatchJob) * jobs.size(), b_job);
+    const size_t o_pool = put(pool.data(), sizeof(float2) * pool.size(), b_pool);
+    const size_t o_ro = put(readout.data(), sizeof(double) * readout.size(), b_ro);
+    const size_t o_out = off;
+    qs_status status = QS_OK;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<uint64_t> out(size_t(std::max<int64_t>(total_samples, 1)));
+    do {
+        if ((e = hipMalloc(&dbuf, total)) != hipSuccess) {
+            status = fail(QS_ERR_OUT_OF_MEMORY, "allocating the batched program failed");
+            dbuf = nullptr;
+            break;
+        }
+        if (b_slots && (e = hipMalloc(&slots, b_slots)) != hipSuccess) {
+            status = fail(QS_ERR_OUT_OF_MEMORY, "allocating batched state slots failed");
+            slots = nullptr;
+            break;
+        }
+        if ((e = hipMemcpyAsync(dbuf, host.data(), o_out, hipMemcpyHostToDevice, st)) != hipSuccess) break;
+        qs::BatchArgs A;
+        A.circs = reinterpret_cast<const qs::BatchCircuit *>(dbuf + o_circ);
+        A.sweeps = reinterpret_cast<const qs::BatchSweep *>(dbuf + o_sweep);
+        A.gates = reinterpret_cast<const qs::BatchGate *>(dbuf + o_gate);
+        A.patches = reinterpret_cast<const qs::BatchPatch *>(dbuf + o_patch);
+        A.jobs = reinterpret_cast<const qs::BatchJob *>(dbuf + o_job);
+        A.mats = reinterpret_cast<const float2 *>(dbuf + o_pool);
+        A.readout = reinterpret_cast<const double *>(dbuf + o_ro);
+        A.slots = slots;
+        A.slot_amps = int64_t(slot_amps);
+        A.out = reinterpret_cast<uint64_t *>(dbuf + o_out);
+        A.n_jobs = int(jobs.size());
+        const bool timing = (bp->flags & QS_TRAJ_TIME_KERNELS) != 0;
+        if (timing) {
+            if ((e = hipEventCreate(&ev0)) != hipSuccess) break;
+            if ((e = hipEventCreate(&ev1)) != hipSuccess) break;
+            if ((e = hipEventRecord(ev0, st)) != hipSuccess) break;
+        }
+        if ((e = qs::launch_batched(A, std::min<int64_t>(grid, int64_t(jobs.size())), st)) != hipSuccess) break;
+        if (timing && (e = hipEventRecord(ev1, st)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(out.data(), dbuf + o_out, sizeof(uint64_t) * size_t(total_samples),
+                                hipMemcpyDeviceToHost, st)) != hipSuccess)
+            break;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) break;
+        if (timing) {
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, ev0, ev1)) != hipSuccess) break;
+            r->kernel_ms = ms;
+        }
+    } while (false);
+    if (status == QS_OK && e != hipSuccess)
+        status = fail(QS_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
+    (void)hipStreamSynchronize(st);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (slots) (void)hipFree(slots);
+    if (dbuf) (void)hipFree(dbuf);
+    if (status != QS_OK) return status;
+    for (int it = 0; it < n_items; ++it) {
+        const int64_t cnt = items[it].n_traj * int64_t(items[it].n_samples);
+        if (cnt > 0)
+            std::memcpy(items[it].bitstrings, out.data() + item_out_base[it], sizeof(uint64_t) * size_t(cnt));
+    }
+    r->host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return QS_OK;
+}

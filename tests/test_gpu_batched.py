@@ -1,0 +1,77 @@
+"""GPU parity of the batched persistent launch (many small circuits in one
+kernel) against the oracle and against the one-trajectory-per-call driver."""
+
+import numpy as np
+import pytest
+
+import torch  # noqa: F401  (imported at collection: the first import can be slow)
+
+import workloads as W
+from workloads.configs import TrajectoryWorkload
+from gpu_helpers import SAMPLE_TIE, compare_choices
+
+pytestmark = pytest.mark.gpu
+
+
+def _items(specs):
+    out = []
+    for i, (n, depth, p, ntraj, nsamp) in enumerate(specs):
+        c = W.generic_grid_circuit(n, depth, p_dep=p, seed=100 + i)
+        e0, e1 = W.readout_arrays(n, 0.01, 0.02)
+        out.append(TrajectoryWorkload(f"b{i}", c, n_traj=ntraj, seed=7, circuit_id=i,
+                                      n_samples=nsamp, e0=e0, e1=e1, max_fuse=3))
+    return out
+
+
+def test_batched_matches_oracle(qs, orc):
+    items = _items([(10, 6, 0.05, 3, 20), (12, 8, 0.03, 3, 20), (13, 5, 0.05, 2, 20),
+                    (14, 5, 0.03, 2, 20), (15, 4, 0.05, 2, 20)])
+    res, stats = qs.qs_run_batched(items)
+    assert stats["jobs"] == sum(w.n_traj for w in items)
+    assert stats["resident_jobs"] == 3 + 3 + 2
+    for w, r in zip(items, res):
+        m = orc.Marshalled(w.circuit)
+        for t in range(w.n_traj):
+            ref = orc.run_trajectory(w.circuit, t, seed=w.seed, circ=w.circuit_id,
+                                     n_samples=w.n_samples, e0=w.e0, e1=w.e1, marshalled=m)
+            _, tie = compare_choices(r["choices"][t], ref)
+            assert tie == 0
+            mism = np.nonzero(r["samples"][t] != ref["samples"])[0]
+            assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE), (w.name, t, mism)
+
+
+def test_batched_matches_driver_all_sizes(qs):
+    items = _items([(n, 8, 0.01, 4, 8) for n in range(12, 19)])
+    res, _ = qs.qs_run_batched(items)
+    for w, r in zip(items, res):
+        with qs.State(w.circuit.n) as st:
+            d = qs.qs_run_trajectories(st.h, w.circuit, w.n_traj, seed=w.seed,
+                                       circuit_id=w.circuit_id, n_samples=w.n_samples,
+                                       p0to1=w.e0, p1to0=w.e1, max_fuse=3)
+        assert np.array_equal(r["choices"], d["choices"])
+        assert np.mean(r["samples"] == d["samples"]) > 0.95
+
+
+def test_batched_offsets_and_determinism(qs):
+    items = _items([(12, 6, 0.05, 6, 5), (16, 4, 0.05, 3, 5)])
+    a, _ = qs.qs_run_batched(items)
+    b, _ = qs.qs_run_batched(items)
+    for x, y in zip(a, b):
+        assert np.array_equal(x["samples"], y["samples"])
+        assert np.array_equal(x["choices"], y["choices"])
+    tail = _items([(12, 6, 0.05, 6, 5), (16, 4, 0.05, 3, 5)])
+    for w in tail:
+        w.traj_offset = 2
+        w.n_traj -= 2
+    c, _ = qs.qs_run_batched(tail)
+    for x, z in zip(a, c):
+        assert np.array_equal(x["choices"][2:], z["choices"])
+        assert np.array_equal(x["samples"][2:], z["samples"])
+
+
+def test_batched_rejects_non_mixtures(qs):
+    c = W.generic_grid_circuit(10, 4, p_dep=0.01, gamma=0.01, seed=1)
+    w = TrajectoryWorkload("ad", c, n_traj=1, n_samples=1)
+    with pytest.raises(qs.QsError) as e:
+        qs.qs_run_batched([w])
+    assert e.value.code == qs.QS_ERR_NOT_SUPPORTED
