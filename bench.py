@@ -97,7 +97,7 @@ def main() -> int:
                     help="trajectories timed with the conventional method (0 = skip)")
     ap.add_argument("--cpu-cycles", type=int, default=1,
                     help="cycles of trajectory 0 timed on the oracle (0 = skip)")
-    ap.add_argument("--workload", default="grid24", choices=["grid24", "batched", "serving"],
+    ap.add_argument("--workload", default="grid24", choices=["grid24", "batched", "serving", "phase_damping"],
                     help="grid24 (default): the headline line; batched / serving: the other forms")
     ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals/s (0 = ~70%% load)")
@@ -124,6 +124,8 @@ def main() -> int:
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "phase_damping":
+        return bench_phase_damping(args)
     w = W.grid24_workload(p_dep=args.p_dep)
     c = w.circuit
     n = c.n
@@ -291,6 +293,59 @@ def bench_batched(args) -> int:
                                     "sample": f"{done} trajectories of {len(sample)} circuits"},
         "speedup_vs_one_per_call": value / per_call,
     }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def phase_damped_circuit(rows: int, cols: int, lam: float, cycles: int = 20):
+    """Random grid circuit with a phase-damping channel after every gate on
+    each qubit it touches (the paper's noise benchmark shape)."""
+    import workloads as W
+
+    c = W.grid_circuit(rows, cols, cycles, seed=0)
+    ops = []
+    pd = W.phase_damp(lam)
+    for op in c.ops:
+        ops.append(op)
+        for q in op.qubits:
+            ops.append(W.Op(W.CHANNEL, (q,), pd, op.moment, "phase_damp"))
+    return W.Circuit(c.n, ops, f"grid{rows}x{cols}-pd{lam:g}")
+
+
+def bench_phase_damping(args) -> int:
+    """Trajectories/s against phase-damping strength, delayed inner products
+    vs the conventional method, at 20 and 27 qubits."""
+    import paper_2111_02396_amd as qs
+
+    rows = []
+    for (r, c_, n_traj, n_naive) in ((4, 5, 40, 4), (3, 9, 6, 1)):
+        n = r * c_
+        with qs.State(n) as st:
+            for lam in (1e-4, 1e-3, 1e-2, 1e-1):
+                circ = phase_damped_circuit(r, c_, lam)
+                mc = qs.MarshalledCircuit(circ)
+                qs.qs_run_trajectories(st.h, circ, 1, seed=0, traj_offset=99, n_samples=1,
+                                       marshalled=mc, record_choices=False)
+                t0 = time.perf_counter()
+                rd = qs.qs_run_trajectories(st.h, circ, n_traj, seed=0, n_samples=1,
+                                            marshalled=mc, record_choices=False)
+                dd = time.perf_counter() - t0
+                t1 = time.perf_counter()
+                qs.qs_run_trajectories(st.h, circ, n_naive, seed=0, n_samples=1,
+                                       mode=qs.QS_KRAUS_NAIVE, marshalled=mc, record_choices=False)
+                dn = time.perf_counter() - t1
+                row = {"qubits": n, "lambda": lam, "channels": mc.n_channels,
+                       "delayed_traj_per_s": n_traj / dd, "naive_traj_per_s": n_naive / dn,
+                       "slow_paths_per_traj": float(rd["n_slow"].mean()),
+                       "speedup": (n_traj / dd) / (n_naive / dn)}
+                log(json.dumps(row))
+                rows.append(row)
+    out = {"metric": "trajectories/s vs phase-damping strength (delayed vs conventional)",
+           "value": rows[1]["delayed_traj_per_s"], "unit": "trajectories/s", "n_gpus": 1,
+           "steps": 1, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+           "config": {"workload": "grid 4x5 and 3x9, 20 cycles, phase damping after every gate"},
+           "sweep": rows}
     print(json.dumps(out), flush=True)
     return 0
 

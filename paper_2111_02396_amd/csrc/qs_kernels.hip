@@ -287,7 +287,9 @@ __device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const f
 // tile's loads are issued into registers, the gates run on the LDS copy in
 // order, and the tile is written back: any number of gates inside the tile
 // cost one HBM read and one write.
-template <int TB, typename Idx>
+// K5: whether the launch holds a 5-qubit block (its VALU path needs ~70 more
+// VGPRs, so launches without one use a leaner instantiation).
+template <int TB, typename Idx, bool K5>
 __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, Idx n_tiles,
                                                      TileArgs a) {
     static_assert(TB >= 10, "the MFMA gates need at least 32 groups per tile");
@@ -365,7 +367,9 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
                 case 2: tile_gate_small<2>(sd, a.g[gi].mat, lt, TB); break;
                 case 3: tile_gate_mfma3(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs), lt, TB); break;
                 case 4: tile_gate_mfma4(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs), lt, TB); break;
-                default: tile_gate_valu<5>(sd, sm + a.g[gi].lofs, lt, TB); break;
+                default:
+                    if constexpr (K5) tile_gate_valu<5>(sd, sm + a.g[gi].lofs, lt, TB);
+                    break;
             }
             __syncthreads();
         }
@@ -824,12 +828,12 @@ int device_cus() {
     return cus;
 }
 
-template <int TB, typename Idx>
+template <int TB, typename Idx, bool K5>
 hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
     static bool attr_set = false;
     const size_t lds = sizeof(float2) * ((size_t(1) << TB) + size_t(a.mat_total));
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_tile<TB, Idx>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_tile<TB, Idx, K5>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            int(sizeof(float2) * ((size_t(1) << TB) + kTileMatBudget)));
         if (e != hipSuccess) return e;
@@ -842,17 +846,24 @@ hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
     if (per_cu > 8) per_cu = 8;
     uint64_t grid = uint64_t(device_cus()) * uint64_t(per_cu);
     if (grid > uint64_t(n_tiles)) grid = uint64_t(n_tiles);
-    apply_tile<TB, Idx><<<unsigned(grid), kBlock, lds, st>>>(amp, n_tiles, a);
+    apply_tile<TB, Idx, K5><<<unsigned(grid), kBlock, lds, st>>>(amp, n_tiles, a);
     return hipGetLastError();
+}
+
+template <int TB, typename Idx>
+hipError_t tile_launch_k(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
+    bool k5 = false;
+    for (int gi = 0; gi < a.n_gates; ++gi) k5 |= a.g[gi].k == 5;
+    return k5 ? tile_launch<TB, Idx, true>(amp, n, a, st) : tile_launch<TB, Idx, false>(amp, n, a, st);
 }
 
 template <typename Idx>
 hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
     switch (a.tb) {
-        case 10: return tile_launch<10, Idx>(amp, n, a, st);
-        case 11: return tile_launch<11, Idx>(amp, n, a, st);
-        case 12: return tile_launch<12, Idx>(amp, n, a, st);
-        case 13: return tile_launch<13, Idx>(amp, n, a, st);
+        case 10: return tile_launch_k<10, Idx>(amp, n, a, st);
+        case 11: return tile_launch_k<11, Idx>(amp, n, a, st);
+        case 12: return tile_launch_k<12, Idx>(amp, n, a, st);
+        case 13: return tile_launch_k<13, Idx>(amp, n, a, st);
         default: return hipErrorInvalidValue;
     }
 }

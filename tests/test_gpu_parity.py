@@ -334,3 +334,55 @@ def test_grid24_full_size_classification(qs, orc):
                 assert got["paths"][t][j] == 1 or res["margin_fast"] < 1e-12
     assert slow_total == int(got["n_slow"].sum())
     assert np.all(got["samples"] < (1 << 24))
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["delayed", "naive"])
+def test_driver_decay_dephasing_and_two_qubit_noise(qs, orc, mode):
+    """Slow-path-heavy channels: the three-operator decay/dephasing channel on
+    every qubit after every moment and two-qubit depolarizing after each CZ."""
+    ops = []
+    rng = np.random.default_rng(6)
+    n = 11
+    dd = W.decay_dephase(0.05, 1.0, 0.6)
+    for layer in range(5):
+        for q in range(n):
+            ops.append(W.Op(W.GATE, (q,), [W.random_unitary(1, rng)], 2 * layer))
+            ops.append(W.Op(W.CHANNEL, (q,), dd, 2 * layer))
+        for q in range(layer % 2, n - 1, 2):
+            ops.append(W.Op(W.GATE, (q, q + 1), [W.CZ], 2 * layer + 1))
+            ops.append(W.Op(W.CHANNEL, (q + 1, q), W.depolarize2(0.05), 2 * layer + 1))
+    c = W.Circuit(n, ops)
+    m = orc.Marshalled(c)
+    ties = 0
+    for t in range(3):
+        got = _driver(qs, c, 1, mode, seed=12, traj_offset=t, n_samples=25, return_state=True)
+        ref = orc.run_trajectory(c, t, mode=mode, seed=12, n_samples=25, return_state=True,
+                                 marshalled=m)
+        _, tie = compare_choices(got["choices"][0], ref)
+        ties += tie
+        if tie:
+            continue
+        assert rel_l2(got["state"], ref["state"]) < AMP_TOL
+        mism = np.nonzero(got["samples"][0] != ref["samples"])[0]
+        assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
+    assert ties <= 1
+
+
+def test_phase_damping_slow_paths_scale_with_noise(qs):
+    """Section 3.5: with phase damping the channels needing inner products
+    grow linearly with the noise strength (sum over channels of 1 - s)."""
+    counts = {}
+    for lam in (1e-3, 1e-2, 1e-1):
+        c = W.grid_circuit(3, 4, 6, seed=2)
+        ops = []
+        for op in c.ops:
+            ops.append(op)
+            if op.kind == W.GATE:
+                for q in op.qubits:
+                    ops.append(W.Op(W.CHANNEL, (q,), W.phase_damp(lam), op.moment))
+        nc = W.Circuit(c.n, ops)
+        r = _driver(qs, nc, 40, 0, seed=1)
+        n_ch = sum(1 for o in ops if o.kind == W.CHANNEL)
+        counts[lam] = (float(r["n_slow"].mean()), n_ch * lam)
+    for lam, (got, expect) in counts.items():
+        assert abs(got - expect) < 5 * np.sqrt(expect / 40) + 0.5, (lam, got, expect)
