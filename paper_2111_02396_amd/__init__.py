@@ -317,39 +317,50 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
     return out
 
 
+class PreparedBatch:
+    """Workloads marshalled once for repeated qs_run_batched calls.  Each
+    workload carries circuit, n_traj, seed, circuit_id, n_samples, e0, e1 and
+    optionally traj_offset."""
+
+    def __init__(self, workloads, record_choices: bool = True):
+        self.keep = []
+        self.items = (QsBatchItem * max(len(workloads), 1))()
+        self.outs = []
+        self.n = len(workloads)
+        for i, w in enumerate(workloads):
+            mc = MarshalledCircuit(w.circuit)
+            e0 = None if w.e0 is None else np.ascontiguousarray(w.e0, dtype=np.float64)
+            e1 = None if w.e1 is None else np.ascontiguousarray(w.e1, dtype=np.float64)
+            bits = np.zeros(max(w.n_traj * w.n_samples, 1), dtype=np.uint64)
+            ch = np.zeros(max(w.n_traj * mc.n_channels, 1), dtype=np.int8) if record_choices else None
+            self.keep += [mc, e0, e1, bits, ch]
+            it = self.items[i]
+            it.circuit = ctypes.cast(ctypes.pointer(mc.c), ctypes.c_void_p)
+            it.n_traj = w.n_traj
+            it.traj_offset = getattr(w, "traj_offset", 0)
+            it.seed = w.seed
+            it.circuit_id = w.circuit_id
+            it.n_samples = w.n_samples
+            it.p0to1, it.p1to0 = _p(e0), _p(e1)
+            it.bitstrings = _p(bits)
+            it.kraus_choices = _p(ch)
+            self.outs.append((bits, ch, mc.n_channels, w.n_traj, w.n_samples))
+
+
 def qs_run_batched(workloads, max_fuse: int = 0, hip_stream: Optional[int] = None,
                    time_kernels: bool = False, record_choices: bool = True):
-    """Run TrajectoryWorkload-like objects (circuit, n_traj, seed, circuit_id,
-    n_samples, e0, e1, and optional traj_offset) in one persistent launch."""
-    keep = []
-    items = (QsBatchItem * max(len(workloads), 1))()
-    outs = []
-    for i, w in enumerate(workloads):
-        mc = MarshalledCircuit(w.circuit)
-        e0 = None if w.e0 is None else np.ascontiguousarray(w.e0, dtype=np.float64)
-        e1 = None if w.e1 is None else np.ascontiguousarray(w.e1, dtype=np.float64)
-        bits = np.zeros(max(w.n_traj * w.n_samples, 1), dtype=np.uint64)
-        ch = np.zeros(max(w.n_traj * mc.n_channels, 1), dtype=np.int8) if record_choices else None
-        keep += [mc, e0, e1, bits, ch]
-        it = items[i]
-        it.circuit = ctypes.cast(ctypes.pointer(mc.c), ctypes.c_void_p)
-        it.n_traj = w.n_traj
-        it.traj_offset = getattr(w, "traj_offset", 0)
-        it.seed = w.seed
-        it.circuit_id = w.circuit_id
-        it.n_samples = w.n_samples
-        it.p0to1, it.p1to0 = _p(e0), _p(e1)
-        it.bitstrings = _p(bits)
-        it.kraus_choices = _p(ch)
-        outs.append((bits, ch, mc.n_channels, w))
+    """Run workloads (or a PreparedBatch) in one persistent launch; returns
+    per-workload {"samples", "choices"} and launch statistics."""
+    pb = workloads if isinstance(workloads, PreparedBatch) else PreparedBatch(workloads,
+                                                                              record_choices)
     params = QsBatchParams(max_fuse, QS_TRAJ_TIME_KERNELS if time_kernels else 0, hip_stream)
     res = QsBatchResult()
-    _check(load().qs_run_batched(items, len(workloads), ctypes.byref(params), ctypes.byref(res)))
+    _check(load().qs_run_batched(pb.items, pb.n, ctypes.byref(params), ctypes.byref(res)))
     results = []
-    for bits, ch, nch, w in outs:
-        d = {"samples": bits[:w.n_traj * w.n_samples].reshape(w.n_traj, w.n_samples)}
+    for bits, ch, nch, n_traj, n_samples in pb.outs:
+        d = {"samples": bits[:n_traj * n_samples].reshape(n_traj, n_samples).copy()}
         if ch is not None:
-            d["choices"] = ch[:w.n_traj * nch].reshape(w.n_traj, nch)
+            d["choices"] = ch[:n_traj * nch].reshape(n_traj, nch).copy()
         results.append(d)
     stats = {"jobs": res.jobs, "resident_jobs": res.resident_jobs, "gate_blocks": res.gate_blocks,
              "host_seconds": res.host_seconds, "plan_seconds": res.plan_seconds,

@@ -65,6 +65,7 @@ struct TileArgs {
     int pos[kMaxTileBits];
     int n_gates;
     int mat_total;
+    int init_zero;  // 1: start from |0...0> written in LDS instead of reading the state
     TileGate g[kMaxTileGates];
 };
 

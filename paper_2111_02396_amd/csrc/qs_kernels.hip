@@ -322,12 +322,21 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
         }
         return base + off_tid;
     };
-    float2 v[R];
-    {
-        const Idx base = tile_base(tile);
+    // A tile's amplitudes; with init_zero the sweep starts from |0...0>
+    // (amplitude 1 at index 0) without reading the state.
+    auto fetch = [&](Idx t, float2 (&dst)[R]) {
+        const Idx base = tile_base(t);
+        if (a.init_zero) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = amp[base + off_r[r]];
-    }
+            for (int r = 0; r < R; ++r)
+                dst[r] = make_float2(base + off_r[r] == Idx(0) ? 1.f : 0.f, 0.f);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[r] = amp[base + off_r[r]];
+        }
+    };
+    float2 v[R];
+    fetch(tile, v);
     for (int gi = 0; gi < a.n_gates; ++gi) {
         const int k = a.g[gi].k;
         const float2 *src = a.g[gi].mat;
@@ -351,11 +360,7 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
         for (int r = 0; r < R; ++r) sd[threadIdx.x + (r << 8)] = v[r];
         const Idx base = tile_base(t);
         const Idx next = t + gridDim.x;
-        if (next < n_tiles) {
-            const Idx nb = tile_base(next);
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[r] = amp[nb + off_r[r]];
-        }
+        if (next < n_tiles) fetch(next, v);
         __syncthreads();
         for (int gi = 0; gi < a.n_gates; ++gi) {
             const int k = a.g[gi].k;
@@ -706,37 +711,46 @@ __global__ __launch_bounds__(kBlock) void sample_block_sums(const float2 *__rest
 }
 
 // Inclusive prefix over nb block sums: each thread scans a contiguous chunk
-// sequentially; chunk bases come from one sequential pass over the chunk
-// totals.  Writes the total to *norm.
+// sequentially; chunk totals are scanned per wavefront with a fixed shuffle
+// ladder, then across the 16 wavefronts in order.  Writes the total to *norm.
 constexpr int kScanThreads = 1024;
+__device__ __forceinline__ double wave_inclusive_scan(double x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
 __global__ __launch_bounds__(kScanThreads) void sample_scan(const double *__restrict__ sums,
                                                             int64_t nb, double *__restrict__ incl,
                                                             double *__restrict__ norm) {
-    __shared__ double part[kScanThreads];
+    __shared__ double wave_tot[kScanThreads / 64];
     const int64_t chunk = (nb + kScanThreads - 1) / kScanThreads;
     const int64_t lo = int64_t(threadIdx.x) * chunk;
     const int64_t hi = lo + chunk < nb ? lo + chunk : nb;
     double s = 0.0;
     for (int64_t b = lo; b < hi; ++b) s += sums[b];
-    part[threadIdx.x] = s;
+    const double inc = wave_inclusive_scan(s);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) wave_tot[wave] = inc;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double run = 0.0;
-        for (int i = 0; i < kScanThreads; ++i) {
-            const double v = part[i];
-            part[i] = run;
-            run += v;
-        }
-        *norm = run;
-    }
-    __syncthreads();
-    double run = part[threadIdx.x];
+    double before = 0.0;
+    for (int w = 0; w < wave; ++w) before += wave_tot[w];
+    if (threadIdx.x == kScanThreads - 1) *norm = before + inc;
+    double run = before + inc - s;  // exclusive prefix of this chunk
     for (int64_t b = lo; b < hi; ++b) {
         run += sums[b];
         incl[b] = run;
     }
 }
 
+// One wavefront per sample: find the block by binary search over the block
+// prefix, then the lanes sum 2^B/64 consecutive amplitudes each, scan those
+// partial sums in a fixed order, and the first lane whose running sum passes
+// the target rescans its own amplitudes sequentially.
 template <typename Idx>
 __global__ __launch_bounds__(kBlock) void sample_draw(const float2 *__restrict__ amp, int n, int B,
                                                       const double *__restrict__ incl, int64_t nb,
@@ -744,8 +758,9 @@ __global__ __launch_bounds__(kBlock) void sample_draw(const float2 *__restrict__
                                                       uint64_t seed, uint32_t traj, uint32_t circ,
                                                       int n_samples, ReadoutDesc ro,
                                                       uint64_t *__restrict__ out) {
-    const int s = blockIdx.x * kBlock + threadIdx.x;
-    if (s >= n_samples) return;
+    const int s = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (s >= n_samples) return;  // uniform over the wavefront
     const double N = *norm;
     const double target = philox_uniform(seed, uint32_t(s), traj, circ, kStreamMeasure) * N;
     // smallest block b with target < incl[b]
@@ -758,26 +773,48 @@ __global__ __launch_bounds__(kBlock) void sample_draw(const float2 *__restrict__
     if (lo >= nb) {
         x = (uint64_t(1) << n) - 1;
     } else {
-        double acc = lo > 0 ? incl[lo - 1] : 0.0;
+        const double base = lo > 0 ? incl[lo - 1] : 0.0;
         const Idx first = Idx(lo) << B;
         const int len = 1 << B;
+        const int per = len >= 64 ? len / 64 : 1;
+        const int lanes = len >= 64 ? 64 : len;
+        double part = 0.0;
+        if (lane < lanes)
+            for (int i = 0; i < per; ++i) {
+                const float2 v = amp[first + Idx(lane * per + i)];
+                part += fma(double(v.x), double(v.x), double(v.y) * double(v.y));
+            }
+        const double inc = base + wave_inclusive_scan(part);
+        const uint64_t passed = __ballot(lane < lanes && target < inc);
         int pick = len - 1;
-        for (int i = 0; i < len; ++i) {
-            const float2 v = amp[first + Idx(i)];
-            acc += fma(double(v.x), double(v.x), double(v.y) * double(v.y));
-            if (target < acc) { pick = i; break; }
+        if (passed) {
+            const int L = __ffsll((unsigned long long)passed) - 1;
+            // lane L rescans its amplitudes from its exclusive prefix
+            const double start = __shfl(inc - part, L, 64);
+            int idx = L * per + per - 1;
+            if (lane == L) {
+                double run = start;
+                for (int i = 0; i < per; ++i) {
+                    const float2 v = amp[first + Idx(L * per + i)];
+                    run += fma(double(v.x), double(v.x), double(v.y) * double(v.y));
+                    if (target < run) { idx = L * per + i; break; }
+                }
+            }
+            pick = __shfl(idx, L, 64);
         }
         x = uint64_t(first) + uint64_t(pick);
     }
-    if (ro.enabled) {
-        for (int q = 0; q < n; ++q) {
-            const int bit = int((x >> q) & 1u);
-            const double u = philox_uniform(seed, uint32_t(uint64_t(s) * uint64_t(n) + uint64_t(q)),
-                                            traj, circ, kStreamReadout);
-            if (u < (bit ? ro.e1[q] : ro.e0[q])) x ^= uint64_t(1) << q;
+    if (lane == 0) {
+        if (ro.enabled) {
+            for (int q = 0; q < n; ++q) {
+                const int bit = int((x >> q) & 1u);
+                const double u = philox_uniform(seed, uint32_t(uint64_t(s) * uint64_t(n) + uint64_t(q)),
+                                                traj, circ, kStreamReadout);
+                if (u < (bit ? ro.e1[q] : ro.e0[q])) x ^= uint64_t(1) << q;
+            }
         }
+        out[s] = x;
     }
-    out[s] = x;
 }
 
 // ---------------------------------------------------------------- helpers
@@ -940,6 +977,7 @@ bool tile_for_gate(int n, const GateDesc &g, TileArgs &a) {
     for (int q = 0; q < n; ++q)
         if (in_tile[q]) a.pos[i++] = q;
     a.n_gates = 1;
+    a.init_zero = 0;
     a.mat_total = tile_mat_slots(g.k);
     a.g[0].k = g.k;
     a.g[0].lofs = 0;
@@ -1041,7 +1079,7 @@ hipError_t launch_sample(const float2 *amp, int n, double *sums, double *incl, u
         sample_block_sums<uint64_t><<<unsigned(nb), kBlock, 0, st>>>(amp, B, sums);
     sample_scan<<<1, kScanThreads, 0, st>>>(sums, nb, incl, norm_dev);
     if (n_samples > 0) {
-        const unsigned grid = unsigned((n_samples + kBlock - 1) / kBlock);
+        const unsigned grid = unsigned((n_samples + kBlock / 64 - 1) / (kBlock / 64));
         if (n <= 31)
             sample_draw<uint32_t><<<grid, kBlock, 0, st>>>(amp, n, B, incl, nb, norm_dev, seed, traj,
                                                            circ, n_samples, ro, out_dev);

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -891,6 +893,7 @@ struct Runner {
     double pending_scale = 1.0;     // conventional method: 1/sqrt(p_i N) not yet applied
     KernelTimer timer;
     bool timing = false;
+    bool pending_reset = false;     // the state must become |0...0> before its next use
     float2 *static_mats = nullptr;  // default-plan matrices, uploaded once per call
 
     ~Runner() {
@@ -1004,14 +1007,25 @@ struct Runner {
         }
     }
 
+    // Launch the deferred reset, if any (before anything reads the state).
+    qs_status settle_reset() {
+        if (!pending_reset) return QS_OK;
+        pending_reset = false;
+        QS_HIP(s, qs::launch_set_basis(s->amp, s->n, 0, s->st));
+        return QS_OK;
+    }
+
     qs_status launch_unit(const Unit &u) {
         const TileLayout &L = layouts[u.sweep];
         if (!L.tiled) {
+            QS_CHECK(settle_reset());
             for (const BlockDesc *d : u.items) QS_CHECK(launch_block(*d));
             return QS_OK;
         }
         qs::TileArgs a;
         std::memset(&a, 0, sizeof(a));
+        a.init_zero = pending_reset ? 1 : 0;
+        pending_reset = false;
         a.tb = L.tb;
         for (int i = 0; i < L.tb; ++i) a.pos[i] = L.pos[i];
         int lofs = 0;
@@ -1165,7 +1179,7 @@ struct Runner {
         if (res.n_slow) res.n_slow[rel] = int32_t(slow_ops.size());
 
         QS_CHECK(restore_home(s));
-        QS_HIP(s, qs::launch_set_basis(s->amp, s->n, 0, s->st));
+        pending_reset = true;  // the first tile sweep writes |0...0> itself
         log_norm_bound = 0.0;
 
         std::vector<const cd *> mats = default_mats;
@@ -1229,6 +1243,7 @@ struct Runner {
             // steps 12-20 for the channel at seg_end
             const int c = m.channel_of_op[seg_end];
             const ChannelInfo &ci = m.channels[c];
+            QS_CHECK(settle_reset());
             QS_CHECK(device_rdm(s, ci.k, ci.ts));
             res.sweeps++;
             double pp = 0.0, N = 0.0;
@@ -1302,6 +1317,7 @@ struct Runner {
             const uint32_t traj = uint32_t(p.traj_offset + rel);
             if (p.mode == QS_KRAUS_DELAYED) QS_CHECK(run_delayed(rel, traj));
             else QS_CHECK(run_naive(rel, traj));
+            QS_CHECK(settle_reset());
             QS_CHECK(sample_trajectory(rel, traj));
         }
         QS_CHECK(flush_samples());
@@ -1455,6 +1471,29 @@ struct BatchTrajOut {
     std::vector<float2> pool;             // patched matrices
 };
 
+// Grow-only device buffers for the batched launch, one set per device; a
+// call holds the lock for its duration.
+struct BatchBuffers {
+    std::mutex lock;
+    char *prog = nullptr;
+    size_t prog_cap = 0;
+    float2 *slots = nullptr;
+    size_t slots_cap = 0;  // bytes
+    char *host = nullptr;  // pinned staging for the program
+    size_t host_cap = 0;
+};
+
+BatchBuffers &batch_buffers() {
+    static std::mutex map_lock;
+    static std::map<int, BatchBuffers *> per_device;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> g(map_lock);
+    BatchBuffers *&b = per_device[dev];
+    if (!b) b = new BatchBuffers();
+    return *b;
+}
+
 void to_float2(int D, const cd *m, float2 *out) {
     for (int i = 0; i < D * D; ++i) out[i] = make_float2(float(m[i].real()), float(m[i].imag()));
 }
@@ -1471,16 +1510,18 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
     hipStream_t st = static_cast<hipStream_t>(bp->hip_stream);
     std::memset(r, 0, sizeof(*r));
 
-    // ---- per-circuit plans
+    // ---- per-circuit plans (threads over circuits), then concatenated
     std::vector<BatchPlanCircuit> plans(n_items);
     std::vector<qs::BatchCircuit> circs(n_items);
-    std::vector<qs::BatchSweep> sweeps;
-    std::vector<qs::BatchGate> gates;
-    std::vector<float2> pool;
-    std::vector<double> readout;
-    int max_tiled_n = 0;
-    int64_t total_jobs = 0, total_samples = 0;
-    std::vector<cd> tmp(1024);
+    struct CircPieces {
+        std::vector<qs::BatchSweep> sweeps;
+        std::vector<qs::BatchGate> gates;  // mat: local offset into pool
+        std::vector<float2> pool;
+        std::vector<double> readout;
+        qs_status status = QS_OK;
+        std::string error;
+    };
+    std::vector<CircPieces> pieces(n_items);
     for (int it = 0; it < n_items; ++it) {
         const qs_batch_item &I = items[it];
         if (!I.circuit) return fail(QS_ERR_INVALID_ARGUMENT, "null circuit");
@@ -1493,18 +1534,33 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
             return fail(QS_ERR_INVALID_ARGUMENT, "n_samples outside 0..4096");
         if (I.n_samples > 0 && I.n_traj > 0 && !I.bitstrings)
             return fail(QS_ERR_INVALID_ARGUMENT, "null bitstrings");
+    }
+    auto plan_one = [&](int it) {
+        const qs_batch_item &I = items[it];
         BatchPlanCircuit &P = plans[it];
+        CircPieces &X = pieces[it];
         P.circuit_index = it;
-        QS_CHECK(build_model(I.circuit, P.m));
+        qs_status stt = build_model(I.circuit, P.m);
+        if (stt != QS_OK) {
+            X.status = stt;
+            X.error = g_last_error;
+            return;
+        }
         for (const auto &c : P.m.channels)
-            if (!c.mixture)
-                return fail(QS_ERR_NOT_SUPPORTED,
-                            "batched launch takes channels whose Kraus operators are all proportional to unitaries");
+            if (!c.mixture) {
+                X.status = QS_ERR_NOT_SUPPORTED;
+                X.error = "batched launch takes channels whose Kraus operators are all proportional to unitaries";
+                return;
+            }
         qs::ReadoutDesc ro;
-        QS_CHECK(fill_readout(P.m.n, I.p0to1, I.p1to0, ro));
+        stt = fill_readout(P.m.n, I.p0to1, I.p1to0, ro);
+        if (stt != QS_OK) {
+            X.status = stt;
+            X.error = g_last_error;
+            return;
+        }
         const int n = P.m.n;
         P.resident = n <= qs::kBatchLdsQubits;
-        if (!P.resident) max_tiled_n = std::max(max_tiled_n, n);
         const int n_ops = int(P.m.ops.size());
         P.default_mats.assign(n_ops, nullptr);
         for (int o = 0; o < n_ops; ++o) {
@@ -1515,7 +1571,6 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
             }
         }
         P.blocks = qs::fuse_greedy(n, P.m.ops, f, &P.op_block);
-        // sweeps: one for a resident state; LDS tile passes otherwise
         std::vector<qs::Sweep> sw;
         if (P.resident) {
             qs::Sweep one;
@@ -1528,16 +1583,15 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
         qs::BatchCircuit &C = circs[it];
         C.n = n;
         C.resident = P.resident ? 1 : 0;
-        C.s0 = int(sweeps.size());
         C.n_samples = I.n_samples;
         C.readout = -1;
         if (ro.enabled) {
-            C.readout = int(readout.size());
-            for (int q = 0; q < n; ++q) readout.push_back(ro.e0[q]);
-            for (int q = 0; q < n; ++q) readout.push_back(ro.e1[q]);
+            C.readout = 0;  // local; shifted when concatenated
+            for (int q = 0; q < n; ++q) X.readout.push_back(ro.e0[q]);
+            for (int q = 0; q < n; ++q) X.readout.push_back(ro.e1[q]);
         }
-        P.gate_base = int64_t(gates.size());
         P.gate_of_block.assign(P.blocks.size(), -1);
+        std::vector<cd> tmp(1024);
         for (const auto &w : sw) {
             qs::BatchSweep S;
             std::memset(&S, 0, sizeof(S));
@@ -1554,7 +1608,11 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
                         in[q] = 1;
                         ++cnt;
                     }
-                if (cnt > qs::kMaxTileBits) return fail(QS_ERR_NOT_SUPPORTED, "block too wide for a tile");
+                if (cnt > qs::kMaxTileBits) {
+                    X.status = QS_ERR_NOT_SUPPORTED;
+                    X.error = "block too wide for a tile";
+                    return;
+                }
                 S.tb = cnt;
                 int i = 0;
                 for (int q = 0; q < n; ++q)
@@ -1564,7 +1622,7 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
                         ++i;
                     }
             }
-            S.g0 = int(gates.size());
+            S.g0 = int(X.gates.size());  // local; shifted when concatenated
             for (int b : w.blocks) {
                 const qs::Block &B = P.blocks[b];
                 qs::BatchGate G;
@@ -1573,18 +1631,60 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
                 for (int j = 0; j < B.k; ++j) G.lt[j] = local[B.q[j]];
                 qs::fused_matrix(B.k, B.q, B.ops, P.m.ops, P.default_mats, tmp.data());
                 const int D = 1 << B.k;
-                G.mat = int(pool.size());
-                pool.resize(pool.size() + size_t(D) * D + (D * D) % 2);
-                to_float2(D, tmp.data(), pool.data() + G.mat);
-                P.gate_of_block[b] = int(gates.size());
-                gates.push_back(G);
+                G.mat = int(X.pool.size());
+                X.pool.resize(X.pool.size() + size_t(D) * D + (D * D) % 2);
+                to_float2(D, tmp.data(), X.pool.data() + G.mat);
+                P.gate_of_block[b] = int(X.gates.size());
+                X.gates.push_back(G);
             }
-            S.g1 = int(gates.size());
+            S.g1 = int(X.gates.size());
+            X.sweeps.push_back(S);
+        }
+    };
+    {
+        const unsigned nt = std::max(1u, std::min({16u, std::thread::hardware_concurrency(),
+                                                   unsigned(std::max(n_items, 1))}));
+        std::vector<std::thread> th;
+        for (unsigned w = 0; w < nt; ++w)
+            th.emplace_back([&, w]() {
+                for (int it = int(w); it < n_items; it += int(nt)) plan_one(it);
+            });
+        for (auto &x : th) x.join();
+    }
+    std::vector<qs::BatchSweep> sweeps;
+    std::vector<qs::BatchGate> gates;
+    std::vector<float2> pool;
+    std::vector<double> readout;
+    int max_tiled_n = 0;
+    int64_t total_jobs = 0, total_samples = 0;
+    for (int it = 0; it < n_items; ++it) {
+        CircPieces &X = pieces[it];
+        if (X.status != QS_OK) return fail(X.status, X.error);
+        BatchPlanCircuit &P = plans[it];
+        qs::BatchCircuit &C = circs[it];
+        const int gshift = int(gates.size());
+        const int pshift = int(pool.size());
+        C.s0 = int(sweeps.size());
+        for (auto S : X.sweeps) {
+            S.g0 += gshift;
+            S.g1 += gshift;
             sweeps.push_back(S);
         }
         C.s1 = int(sweeps.size());
-        total_jobs += I.n_traj;
-        total_samples += I.n_traj * int64_t(I.n_samples);
+        for (auto G : X.gates) {
+            G.mat += pshift;
+            gates.push_back(G);
+        }
+        for (auto &g : P.gate_of_block) g += gshift;
+        P.gate_base = gshift;
+        pool.insert(pool.end(), X.pool.begin(), X.pool.end());
+        if (C.readout >= 0) {
+            C.readout = int(readout.size());
+            readout.insert(readout.end(), X.readout.begin(), X.readout.end());
+        }
+        if (!P.resident) max_tiled_n = std::max(max_tiled_n, P.m.n);
+        total_jobs += items[it].n_traj;
+        total_samples += items[it].n_traj * int64_t(items[it].n_samples);
     }
     if (pool.size() > (size_t(1) << 30)) return fail(QS_ERR_OUT_OF_MEMORY, "matrix pool too large");
 
@@ -1715,16 +1815,57 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
     const int grid = qs::batched_grid();
     const size_t slot_amps = max_tiled_n > 0 ? size_t(1) << max_tiled_n : 0;
     const size_t b_slots = sizeof(float2) * slot_amps * size_t(grid);
-    size_t free_b = 0, total_b = 0;
-    hipError_t e = hipMemGetInfo(&free_b, &total_b);
-    if (e != hipSuccess) return fail(QS_ERR_DEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
-    if (free_b < total + b_slots) return fail(QS_ERR_OUT_OF_MEMORY, "batched launch does not fit in free memory");
-    char *dbuf = nullptr;
-    float2 *slots = nullptr;
-    std::vector<char> host(total, 0);
+    BatchBuffers &BB = batch_buffers();
+    std::lock_guard<std::mutex> hold(BB.lock);
+    hipError_t e = hipSuccess;
+    auto grow = [&](size_t need_prog, size_t need_slots) -> qs_status {
+        size_t free_b = 0, total_b = 0;
+        if (need_prog > BB.prog_cap || need_slots > BB.slots_cap || need_prog > BB.host_cap) {
+            if ((e = hipMemGetInfo(&free_b, &total_b)) != hipSuccess)
+                return fail(QS_ERR_DEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+        }
+        if (need_prog > BB.prog_cap) {
+            if (BB.prog) (void)hipFree(BB.prog);
+            BB.prog = nullptr;
+            BB.prog_cap = 0;
+            if (free_b < need_prog) return fail(QS_ERR_OUT_OF_MEMORY, "batched program does not fit");
+            if (hipMalloc(&BB.prog, need_prog) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(QS_ERR_OUT_OF_MEMORY, "allocating the batched program failed");
+            }
+            BB.prog_cap = need_prog;
+        }
+        if (need_prog > BB.host_cap) {
+            if (BB.host) (void)hipHostFree(BB.host);
+            BB.host = nullptr;
+            BB.host_cap = 0;
+            if (hipHostMalloc(reinterpret_cast<void **>(&BB.host), need_prog, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(QS_ERR_OUT_OF_MEMORY, "allocating pinned staging failed");
+            }
+            BB.host_cap = need_prog;
+        }
+        if (need_slots > BB.slots_cap) {
+            if (BB.slots) (void)hipFree(BB.slots);
+            BB.slots = nullptr;
+            BB.slots_cap = 0;
+            (void)hipMemGetInfo(&free_b, &total_b);
+            if (free_b < need_slots) return fail(QS_ERR_OUT_OF_MEMORY, "batched state slots do not fit");
+            if (hipMalloc(&BB.slots, need_slots) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(QS_ERR_OUT_OF_MEMORY, "allocating batched state slots failed");
+            }
+            BB.slots_cap = need_slots;
+        }
+        return QS_OK;
+    };
+    QS_CHECK(grow(total, b_slots));
+    char *dbuf = BB.prog;
+    float2 *slots = b_slots ? BB.slots : nullptr;
+    char *hostp = BB.host;
     size_t off = 0;
     auto put = [&](const void *src, size_t bytes, size_t cap) {
-        std::memcpy(host.data() + off, src, bytes);
+        if (bytes) std::memcpy(hostp + off, src, bytes);
         const size_t at = off;
         off += cap;
         return at;
@@ -1741,17 +1882,7 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<uint64_t> out(size_t(std::max<int64_t>(total_samples, 1)));
     do {
-        if ((e = hipMalloc(&dbuf, total)) != hipSuccess) {
-            status = fail(QS_ERR_OUT_OF_MEMORY, "allocating the batched program failed");
-            dbuf = nullptr;
-            break;
-        }
-        if (b_slots && (e = hipMalloc(&slots, b_slots)) != hipSuccess) {
-            status = fail(QS_ERR_OUT_OF_MEMORY, "allocating batched state slots failed");
-            slots = nullptr;
-            break;
-        }
-        if ((e = hipMemcpyAsync(dbuf, host.data(), o_out, hipMemcpyHostToDevice, st)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(dbuf, hostp, o_out, hipMemcpyHostToDevice, st)) != hipSuccess) break;
         qs::BatchArgs A;
         A.circs = reinterpret_cast<const qs::BatchCircuit *>(dbuf + o_circ);
         A.sweeps = reinterpret_cast<const qs::BatchSweep *>(dbuf + o_sweep);
@@ -1782,13 +1913,11 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
             r->kernel_ms = ms;
         }
     } while (false);
-    if (status == QS_OK && e != hipSuccess)
+    if (e != hipSuccess)
         status = fail(QS_ERR_DEVICE, std::string("batched launch: ") + hipGetErrorString(e));
     (void)hipStreamSynchronize(st);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
-    if (slots) (void)hipFree(slots);
-    if (dbuf) (void)hipFree(dbuf);
     if (status != QS_OK) return status;
     for (int it = 0; it < n_items; ++it) {
         const int64_t cnt = items[it].n_traj * int64_t(items[it].n_samples);
