@@ -172,6 +172,27 @@ hipError_t launch_sample(const float2 *amp, int n, double *sums, double *incl,
                          const ReadoutDesc &ro, uint64_t *out_dev, double *norm_dev,
                          hipStream_t st);
 
+// Device-side branch selection for a channel that needs inner products
+// (Algorithm 2, steps 13-20): from the FP64 reduced density matrix R (as
+// written by launch_rdm), e_i = Re Tr((K_i^dag K_i - pbar_i I) R) / N; the
+// residual picks i (falling back to the last i with e_i > 0); then
+// dst = cand[i] / sqrt((pbar_i + e_i) N) in complex64, where cand[i] is the
+// fused block matrix with K_i in the channel's place.  Writes the pick to
+// *choice; sets *err on a zero norm or weight.
+struct SelectArgs {
+    const double *rdm;     // 2 * D * D
+    const double *excess;  // nk * D * D complex128, ascending target order
+    const double *pbar;    // nk
+    const double *cand;    // nk * Db * Db complex128
+    float2 *dst;           // Db * Db
+    int *choice;
+    int *err;
+    double resid;
+    int nk, D, Db;
+};
+
+hipError_t launch_select(const SelectArgs &a, hipStream_t st);
+
 // One persistent launch over all jobs; `grid` workgroups, each owning slot
 // blockIdx.x of `slots` when it runs a tiled circuit.
 hipError_t launch_batched(const BatchArgs &a, int grid, hipStream_t st);

@@ -385,6 +385,66 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
     for (tile += gridDim.x; tile < n_tiles; tile += gridDim.x) run_tile(tile);
 }
 
+// ---------------------------------------------------------------- branch selection
+
+__global__ __launch_bounds__(64) void select_branch(SelectArgs a) {
+    __shared__ double scale;
+    __shared__ int pick;
+    if (threadIdx.x == 0) {
+        const int D = a.D;
+        double N = 0.0;
+        for (int j = 0; j < D; ++j) N += a.rdm[2 * (j * D + j)];
+        double r = a.resid;
+        int chosen = -1, last_pos = -1;
+        double e_chosen = 0.0;
+        for (int i = 0; i < a.nk; ++i) {
+            const double *M = a.excess + size_t(i) * D * D * 2;
+            double tr = 0.0;  // Re sum_jl M[j][l] R[l][j]
+            for (int j = 0; j < D; ++j)
+                for (int l = 0; l < D; ++l) {
+                    const double mr = M[2 * (j * D + l)], mi = M[2 * (j * D + l) + 1];
+                    const double rr = a.rdm[2 * (l * D + j)], ri = a.rdm[2 * (l * D + j) + 1];
+                    tr += mr * rr - mi * ri;
+                }
+            const double e = tr / N;
+            if (e > 0.0) last_pos = i;
+            if (r < e) {
+                chosen = i;
+                e_chosen = e;
+                break;
+            }
+            r -= e;
+        }
+        if (chosen < 0) {
+            chosen = last_pos >= 0 ? last_pos : a.nk - 1;
+            // e of the fallback pick
+            const double *M = a.excess + size_t(chosen) * D * D * 2;
+            double tr = 0.0;
+            for (int j = 0; j < D; ++j)
+                for (int l = 0; l < D; ++l) {
+                    const double mr = M[2 * (j * D + l)], mi = M[2 * (j * D + l) + 1];
+                    const double rr = a.rdm[2 * (l * D + j)], ri = a.rdm[2 * (l * D + j) + 1];
+                    tr += mr * rr - mi * ri;
+                }
+            e_chosen = tr / N;
+        }
+        const double p = a.pbar[chosen] + e_chosen;
+        if (!(N > 0.0) || !(p > 0.0) || !(N < INFINITY)) {
+            *a.err = 1;
+            scale = 0.0;
+        } else {
+            scale = 1.0 / sqrt(p * N);
+        }
+        pick = chosen;
+        *a.choice = chosen;
+    }
+    __syncthreads();
+    const int dd = a.Db * a.Db;
+    const double *c = a.cand + size_t(pick) * dd * 2;
+    for (int i = threadIdx.x; i < dd; i += 64)
+        a.dst[i] = make_float2(float(c[2 * i] * scale), float(c[2 * i + 1] * scale));
+}
+
 // ---------------------------------------------------------------- batched
 
 // One fused block on amplitudes held in LDS (a whole resident state, or a
@@ -906,6 +966,12 @@ hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st)
 }
 
 }  // namespace
+
+hipError_t launch_select(const SelectArgs &a, hipStream_t st) {
+    if (a.nk < 1 || a.D < 1 || a.Db < 1 || a.Db > 32) return hipErrorInvalidValue;
+    select_branch<<<1, 64, 0, st>>>(a);
+    return hipGetLastError();
+}
 
 int batched_grid() {
     const int per_cu = int((160u * 1024u) / (sizeof(float2) * ((1u << kBatchLdsQubits) + 1024u) +

@@ -895,12 +895,87 @@ struct Runner {
     bool timing = false;
     bool pending_reset = false;     // the state must become |0...0> before its next use
     float2 *static_mats = nullptr;  // default-plan matrices, uploaded once per call
+    // device-side branch selection (delayed mode): per-channel excess
+    // matrices and bounds, the picks written by the select kernel, an error flag
+    double *chan_buf = nullptr;
+    std::vector<const double *> chan_excess, chan_pbar;
+    int *dev_choice = nullptr;      // [kChoiceCap] picks, then [kChoiceCap] = error flag
+    int *host_choice = nullptr;     // pinned mirror
+    double *sel_rdm = nullptr;      // R of the pending channel; a renormalisation
+                                    // launched before the select cannot overwrite it
+    static constexpr int kChoiceCap = 1 << 16;
+    std::vector<std::pair<int64_t, int>> choice_owner;  // (trajectory rel, channel) per slot
+    // the pending inner-product channel whose pick decides the next block
+    struct PendingSelect {
+        bool active = false;
+        bool staged = false;
+        bool launched = false;
+        int op = -1, channel = -1;
+        double resid = 0.0;
+        qs::SelectArgs args;
+    } sel;
 
     ~Runner() {
-        if (static_mats) {
-            (void)hipStreamSynchronize(s->st);
-            (void)hipFree(static_mats);
+        if (static_mats || chan_buf || dev_choice) (void)hipStreamSynchronize(s->st);
+        if (sel_rdm) (void)hipFree(sel_rdm);
+        if (static_mats) (void)hipFree(static_mats);
+        if (chan_buf) (void)hipFree(chan_buf);
+        if (dev_choice) (void)hipFree(dev_choice);
+        if (host_choice) (void)hipHostFree(host_choice);
+    }
+
+    // Channels that can need inner products: upload K^dag K - pbar I (ascending
+    // target order, complex128) and the bounds once per call.
+    qs_status upload_channels() {
+        const size_t nch = m.channels.size();
+        chan_excess.assign(nch, nullptr);
+        chan_pbar.assign(nch, nullptr);
+        size_t total = 0;
+        for (const auto &c : m.channels)
+            if (!c.mixture) total += c.excess_sorted.size() * 2 + c.pbar.size();
+        QS_HIP(s, hipMalloc(&dev_choice, sizeof(int) * (kChoiceCap + 1)));
+        QS_HIP(s, hipMalloc(&sel_rdm, sizeof(double) * qs::kMaxReduceWidth));
+        QS_HIP(s, hipHostMalloc(&host_choice, sizeof(int) * (kChoiceCap + 1), hipHostMallocDefault));
+        QS_HIP(s, hipMemsetAsync(dev_choice + kChoiceCap, 0, sizeof(int), s->st));
+        if (total == 0) return QS_OK;
+        std::vector<double> host(total);
+        std::vector<size_t> at(nch, 0);
+        size_t pos = 0;
+        for (size_t c = 0; c < nch; ++c) {
+            const auto &ci = m.channels[c];
+            if (ci.mixture) continue;
+            at[c] = pos;
+            for (const cd &z : ci.excess_sorted) {
+                host[pos++] = z.real();
+                host[pos++] = z.imag();
+            }
+            for (double pb : ci.pbar) host[pos++] = pb;
         }
+        QS_HIP(s, hipMalloc(&chan_buf, sizeof(double) * total));
+        QS_HIP(s, hipMemcpy(chan_buf, host.data(), sizeof(double) * total, hipMemcpyHostToDevice));
+        for (size_t c = 0; c < nch; ++c) {
+            const auto &ci = m.channels[c];
+            if (ci.mixture) continue;
+            chan_excess[c] = chan_buf + at[c];
+            chan_pbar[c] = chan_buf + at[c] + ci.excess_sorted.size() * 2;
+        }
+        return QS_OK;
+    }
+
+    // Copy the picks made on the device back into the result array.
+    qs_status drain_choices() {
+        QS_HIP(s, hipMemcpyAsync(host_choice, dev_choice, sizeof(int) * (kChoiceCap + 1),
+                                 hipMemcpyDeviceToHost, s->st));
+        QS_HIP(s, hipStreamSynchronize(s->st));
+        const int nch = int(m.channels.size());
+        if (res.kraus_choices)
+            for (size_t i = 0; i < choice_owner.size(); ++i)
+                res.kraus_choices[choice_owner[i].first * nch + choice_owner[i].second] =
+                    int8_t(host_choice[i]);
+        choice_owner.clear();
+        if (host_choice[kChoiceCap] != 0)
+            return fail(QS_ERR_ZERO_NORM, "a channel needing inner products met a zero norm or weight");
+        return QS_OK;
     }
 
     // Upload the matrices of `descs` to one device buffer and point at it.
@@ -960,6 +1035,7 @@ struct Runner {
         plan_sweeps();
         std::vector<BlockDesc *> all;
         for (auto &d : block_desc) all.push_back(&d);
+        QS_CHECK(upload_channels());
         return upload_static(all);
     }
 
@@ -1012,6 +1088,19 @@ struct Runner {
         if (!pending_reset) return QS_OK;
         pending_reset = false;
         QS_HIP(s, qs::launch_set_basis(s->amp, s->n, 0, s->st));
+        return QS_OK;
+    }
+
+    // Copy staged matrices, run a pending branch selection (it writes the
+    // matrix one of the units reads), then launch the units in order.
+    qs_status flush_units(std::vector<Unit> &units) {
+        QS_CHECK(arena_commit(s));
+        if (sel.active && sel.staged && !sel.launched) {
+            QS_HIP(s, qs::launch_select(sel.args, s->st));
+            sel.launched = true;
+        }
+        for (const Unit &x : units) QS_CHECK(launch_unit(x));
+        units.clear();
         return QS_OK;
     }
 
@@ -1214,6 +1303,58 @@ struct Runner {
                     sub.assign(lo, hi);
                     dyn.emplace_back();
                     BlockDesc &bd = dyn.back();
+                    const bool holds_slow = sel.active && !sel.staged && *lo == sel.op;
+                    if (holds_slow) {
+                        // one candidate matrix per Kraus operator; the select kernel
+                        // scales the chosen one into this block's slot
+                        const ChannelInfo &ci = m.channels[sel.channel];
+                        const int Dc = 1 << ci.k;
+                        int q[5];
+                        const int kb = qs::union_qubits(sub, m.ops, q);
+                        const int Db = 1 << kb;
+                        const size_t cand_f2 = size_t(ci.nk) * Db * Db * 2;  // complex128 as float2 pairs
+                        const size_t need = cand_f2 + size_t(Db) * Db + 64;
+                        if (!arena_fits(s, need)) QS_CHECK(flush_units(units));
+                        float2 *hc = nullptr;
+                        const float2 *dc = nullptr;
+                        QS_CHECK(arena_stage(s, cand_f2, &hc, &dc));
+                        double *hcd = reinterpret_cast<double *>(hc);
+                        for (int i = 0; i < ci.nk; ++i) {
+                            mats[sel.op] = ci.kraus + size_t(i) * Dc * Dc;
+                            qs::fused_matrix(kb, q, sub, m.ops, mats, tmp.data());
+                            for (int e2 = 0; e2 < Db * Db; ++e2) {
+                                hcd[2 * (size_t(i) * Db * Db + e2)] = tmp[e2].real();
+                                hcd[2 * (size_t(i) * Db * Db + e2) + 1] = tmp[e2].imag();
+                            }
+                        }
+                        bd.g.k = kb;
+                        for (int b2 = 0; b2 < 5; ++b2) bd.g.t[b2] = b2 < kb ? q[b2] : 0;
+                        bd.identity = false;
+                        bd.log_bound = 0.0;
+                        float2 *hd = nullptr;
+                        QS_CHECK(arena_stage(s, size_t(Db) * Db, &hd, &bd.dev));
+                        std::memset(hd, 0, sizeof(float2) * Db * Db);
+                        if (int(choice_owner.size()) >= kChoiceCap) {
+                            QS_CHECK(flush_units(units));
+                            QS_CHECK(drain_choices());
+                        }
+                        qs::SelectArgs &A = sel.args;
+                        A.rdm = sel_rdm;
+                        A.excess = chan_excess[sel.channel];
+                        A.pbar = chan_pbar[sel.channel];
+                        A.cand = reinterpret_cast<const double *>(dc);
+                        A.dst = const_cast<float2 *>(bd.dev);
+                        A.choice = dev_choice + choice_owner.size();
+                        A.err = dev_choice + kChoiceCap;
+                        A.resid = sel.resid;
+                        A.nk = ci.nk;
+                        A.D = Dc;
+                        A.Db = Db;
+                        choice_owner.emplace_back(rel, sel.channel);
+                        sel.staged = true;
+                        unit.items.push_back(&bd);
+                        continue;
+                    }
                     build_block(m, sub, mats, tmp, bd);
                     if (bd.identity) continue;
                     double lb = 0.0;
@@ -1226,38 +1367,28 @@ struct Runner {
                         }
                     }
                     bd.log_bound = lb;
-                    if (!arena_fits(s, size_t(1) << (2 * bd.g.k))) {
-                        // launch what is staged before the ring can wrap onto it
-                        QS_CHECK(arena_commit(s));
-                        for (const Unit &x : units) QS_CHECK(launch_unit(x));
-                        units.clear();
-                    }
+                    if (!arena_fits(s, size_t(1) << (2 * bd.g.k))) QS_CHECK(flush_units(units));
                     QS_CHECK(stage_block(s, bd));
                     unit.items.push_back(&bd);
                 }
                 if (!unit.items.empty()) units.push_back(std::move(unit));
             }
-            QS_CHECK(arena_commit(s));
-            for (const Unit &x : units) QS_CHECK(launch_unit(x));
+            QS_CHECK(flush_units(units));
+            sel = PendingSelect();
             if (seg_end == n_ops) break;
-            // steps 12-20 for the channel at seg_end
+            // steps 12-20 for the channel at seg_end, without a host round trip:
+            // one read pass forms R on the device; the select kernel launched
+            // with the next segment picks the branch and scales its block
             const int c = m.channel_of_op[seg_end];
             const ChannelInfo &ci = m.channels[c];
             QS_CHECK(settle_reset());
-            QS_CHECK(device_rdm(s, ci.k, ci.ts));
+            QS_CHECK(ensure_reduce(s));
+            QS_HIP(s, qs::launch_rdm(s->amp, s->n, ci.k, ci.ts, s->red_partials, sel_rdm, s->st));
             res.sweeps++;
-            double pp = 0.0, N = 0.0;
-            const int pk = select_slow(ci, s->red_host, resid[c], &pp, &N);
-            if (!(N > 0.0) || !std::isfinite(N)) return fail(QS_ERR_ZERO_NORM, "state has zero norm");
-            if (!(pp > 0.0)) return fail(QS_ERR_ZERO_NORM, "chosen Kraus operator has zero weight");
-            pick[c] = pk;
-            if (choices) choices[c] = int8_t(pk);
-            const int D = 1 << ci.k;
-            slow_mats.emplace_back(size_t(D) * D);
-            const double f = 1.0 / std::sqrt(pp * N);
-            const cd *K = ci.kraus + size_t(pk) * D * D;
-            for (int e = 0; e < D * D; ++e) slow_mats.back()[e] = K[e] * f;
-            mats[seg_end] = slow_mats.back().data();
+            sel.active = true;
+            sel.op = seg_end;
+            sel.channel = c;
+            sel.resid = resid[c];
             dirty[op_block[seg_end]] = 1;
             log_norm_bound = 0.0;  // renormalised by the folded 1/sqrt(p N)
             seg_start = seg_end;
@@ -1321,6 +1452,7 @@ struct Runner {
             QS_CHECK(sample_trajectory(rel, traj));
         }
         QS_CHECK(flush_samples());
+        if (p.mode == QS_KRAUS_DELAYED && dev_choice) QS_CHECK(drain_choices());
         if (timing) {
             QS_CHECK(timer.finish(s));
             res.gate_kernel_ms = timer.total_ms;
