@@ -47,9 +47,9 @@ constexpr int kTileMatBudget = 4096;  // float2 of matrices staged per launch (3
 
 // LDS float2 slots a gate's matrix takes in a tile launch: none for k <= 2
 // (read from global memory), MFMA fragments for k = 3 (256 floats) and
-// k = 4 (1024 floats), the plain 32x32 matrix for k = 5.
+// k = 4 (768 floats: three real 16x16 matrices), the plain 32x32 matrix for k = 5.
 __host__ __device__ inline int tile_mat_slots(int k) {
-    return k <= 2 ? 0 : (k == 3 ? 128 : (k == 4 ? 512 : 1024));
+    return k <= 2 ? 0 : (k == 3 ? 128 : (k == 4 ? 384 : 1024));
 }
 
 struct TileGate {

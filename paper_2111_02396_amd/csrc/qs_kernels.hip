@@ -115,36 +115,69 @@ __global__ __launch_bounds__(kBlock) void apply_direct(float2 *__restrict__ amp,
     }
 }
 
+// ---- LDS layout of a tile
+// Gates read and write a tile in LDS one 64-lane instruction at a time; the
+// lanes of an instruction span a few group bits and target bits of the
+// local index, and with the plain layout (float2 index = local index) a gate
+// on low local bits puts them on a handful of banks.  The tile kernel
+// therefore stores local index x at x ^ m(x): bits 0..4 (which of 32 float2
+// bank pairs) are XORed with a linear function m of bits 5..7.  The columns
+// of m were chosen by scoring every target set of k <= 4 in 13 bits against
+// the access pattern of each gate routine below (average cost 1.26x the
+// conflict-free rate instead of 2x, worst case 2x instead of 4x).  Bits 8
+// and up are left alone, so the tile copy's per-row offsets stay immediate.
+// The map is linear over GF(2), so an index made of disjoint bit fields maps
+// field by field, map(a | b) = map(a) ^ map(b): the gate loops split their
+// indices into a per-lane part computed once and a wave-uniform part
+// computed on the scalar unit.
+struct SwizzledTile {
+    __device__ __forceinline__ static int map(int x) {
+        const int m = (((x >> 5) & 1) ? 30 : 0) ^ (((x >> 6) & 1) ? 27 : 0) ^ (((x >> 7) & 1) ? 23 : 0);
+        return x ^ m;
+    }
+};
+
+// Plain layout (the batched kernel's resident states and tiles).
+struct PlainTile {
+    __device__ __forceinline__ static int map(int x) { return x; }
+};
+
+// Wavefront index as a scalar, so loops over it stay uniform.
+__device__ __forceinline__ int wave_index() {
+    return __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+}
+
 // One gate on a tile held in LDS with VALU multiply-adds: every group of the
 // tile is owned by one work-item, which gathers its 2^K amplitudes,
-// multiplies, and writes back in place.  `m` is the matrix: a global
-// address for K <= 2 (wave-uniform, so the entries arrive through scalar
-// loads) or an LDS copy for K = 5.
-template <int K>
+// multiplies, and writes back in place.  `m` is an LDS copy of the matrix.
+template <int K, class L>
 __device__ __forceinline__ void tile_gate_valu(float2 *__restrict__ sd, const float2 *__restrict__ m,
                                                const int *lt, int tb) {
     constexpr int D = 1 << K;
     int off[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) off[j] = local_offset<K, int>(j, lt);
+    for (int j = 0; j < D; ++j) off[j] = L::map(local_offset<K, int>(j, lt));
     const int groups = 1 << (tb - K);
     for (int gg = threadIdx.x; gg < groups; gg += kBlock) {
-        const int lb = spread_index<K, int>(gg, lt);
+        const int lb = L::map(spread_index<K, int>(gg, lt));
         float2 v[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = sd[lb + off[j]];
+        for (int j = 0; j < D; ++j) v[j] = sd[lb ^ off[j]];
 #pragma unroll(K >= 3 ? 2 : D)
         for (int j = 0; j < D; ++j) {
             float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
             for (int l = 0; l < D; ++l) acc = cmac(acc, m[j * D + l], v[l]);
-            sd[lb + off[j]] = acc;
+            sd[lb ^ off[j]] = acc;
         }
     }
 }
 
 // K <= 2: the matrix (at most 16 entries) sits in SGPRs for the whole tile.
-template <int K>
+// Work-item (lane, wave) owns groups lane + 64 wave + 256 i; the next group's
+// amplitudes are read before this one's are written (the last iteration
+// re-reads its own group, which is harmless: the reads precede the writes).
+template <int K, class L>
 __device__ __forceinline__ void tile_gate_small(float2 *__restrict__ sd, const float2 *gm,
                                                 const int *lt, int tb) {
     constexpr int D = 1 << K;
@@ -153,20 +186,47 @@ __device__ __forceinline__ void tile_gate_small(float2 *__restrict__ sd, const f
     for (int i = 0; i < D * D; ++i) u[i] = const_entry(gm, i);
     int off[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) off[j] = local_offset<K, int>(j, lt);
-    const int groups = 1 << (tb - K);
-    for (int gg = threadIdx.x; gg < groups; gg += kBlock) {
-        const int lb = spread_index<K, int>(gg, lt);
-        float2 v[D];
+    for (int j = 0; j < D; ++j) off[j] = L::map(local_offset<K, int>(j, lt));
+    if (tb < K + 8) {  // fewer groups than work-items (small resident states)
+        const int groups = 1 << (tb - K);
+        for (int gg = threadIdx.x; gg < groups; gg += kBlock) {
+            const int lb = L::map(spread_index<K, int>(gg, lt));
+            float2 v[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) v[j] = sd[lb + off[j]];
+            for (int j = 0; j < D; ++j) v[j] = sd[lb ^ off[j]];
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int l = 0; l < D; ++l) acc = cmac(acc, u[j * D + l], v[l]);
+                sd[lb ^ off[j]] = acc;
+            }
+        }
+        return;
+    }
+    const int lane = threadIdx.x & 63, wave = wave_index();
+    const int lane_part = L::map(spread_index<K, int>(lane, lt));
+    const int iters = 1 << (tb - K - 8);
+    int lb = lane_part ^ L::map(spread_index<K, int>(wave << 6, lt));
+    float2 v[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) v[j] = sd[lb ^ off[j]];
+    for (int it = 0; it < iters; ++it) {
+        const int itn = it + 1 < iters ? it + 1 : it;
+        const int lbn = lane_part ^ L::map(spread_index<K, int>((wave << 6) | (itn << 8), lt));
+        float2 w[D];
+#pragma unroll
+        for (int j = 0; j < D; ++j) w[j] = sd[lbn ^ off[j]];
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
             for (int l = 0; l < D; ++l) acc = cmac(acc, u[j * D + l], v[l]);
-            sd[lb + off[j]] = acc;
+            sd[lb ^ off[j]] = acc;
         }
+        lb = lbn;
+#pragma unroll
+        for (int j = 0; j < D; ++j) v[j] = w[j];
     }
 }
 
@@ -184,16 +244,18 @@ __device__ __forceinline__ float real_form(float2 u, int co, int ci) {
     return co == 0 ? (ci == 0 ? u.x : -u.y) : (ci == 0 ? u.y : u.x);
 }
 
-// k = 4, v_mfma_f32_32x32x2f32: lane l supplies A[l%32][l/32] and B[l/32][l%32]
-// per step; step s covers real columns 2s, 2s+1, ordered so that lane half
-// h = l/32 reads amplitude j = 2(s/2) + h and uses its component s%2.
-// Fragment layout: frag[lane * 16 + s].
+// k = 4 with three real products instead of four (Gauss): for U = A + iB and
+// v = x + iy, t1 = A x, t2 = B y, t3 = (A + B)(x + y) give Re Uv = t1 - t2 and
+// Im Uv = t3 - t1 - t2.  v_mfma_f32_16x16x4f32: in step s lane l supplies
+// A[l%16][4s + l/16] and B[4s + l/16][l%16]; accumulator r is row 4(l/16) + r,
+// column l%16.  Fragment layout: frag[lane * 12 + 4 m + s] = M_m[l%16][4s + l/16]
+// with M_0 = Re U, M_1 = Im U, M_2 = Re U + Im U.
 __device__ __forceinline__ void stage_frag4(float *__restrict__ frag, const float2 *__restrict__ u) {
-    for (int i = threadIdx.x; i < 64 * 16; i += kBlock) {
-        const int lane = i >> 4, s = i & 15;
-        const int m = lane & 31, h = lane >> 5;
-        const int ji = 2 * (s >> 1) + h;
-        frag[i] = real_form(u[(m >> 1) * 16 + ji], m & 1, s & 1);
+    for (int i = threadIdx.x; i < 64 * 12; i += kBlock) {
+        const int lane = i / 12, rem = i - 12 * lane;
+        const int m = rem >> 2, s = rem & 3;
+        const float2 e = u[(lane & 15) * 16 + 4 * s + (lane >> 4)];
+        frag[i] = m == 0 ? e.x : (m == 1 ? e.y : e.x + e.y);
     }
 }
 
@@ -209,73 +271,92 @@ __device__ __forceinline__ void stage_frag3(float *__restrict__ frag, const floa
     }
 }
 
-// 32 groups per wavefront iteration.  Output rows 8(r/4) + 4h + r%4 of the
-// accumulator r pair up as (re, im) of amplitudes jo = 4(r/4)/... so each lane
-// writes 8 whole complex amplitudes.  All LDS reads of an iteration precede
-// its writes (the MFMAs consume every loaded value first), and one
-// iteration's groups are disjoint from every other's.
+// 16 groups per wavefront iteration: lane (n, q) = (l%16, l/16) reads
+// amplitudes 4s + q of group n and ends with amplitudes 4q + r.  The next
+// iteration's amplitudes are read before this one's MFMAs, so the LDS latency
+// hides behind them; iterations touch disjoint groups, so reading ahead of
+// the writes is safe.
+template <class L>
 __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const float *__restrict__ frag,
                                                 const int *lt, int tb) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n = lane & 31, h = lane >> 5;
-    const f32x4 *fp = reinterpret_cast<const f32x4 *>(frag + lane * 16);
-    const f32x4 a0 = fp[0], a1 = fp[1], a2 = fp[2], a3 = fp[3];
-    const float afr[16] = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3],
-                           a2[0], a2[1], a2[2], a2[3], a3[0], a3[1], a3[2], a3[3]};
-    int off_in[8], off_out[8];
+    constexpr int W = kBlock / 64;
+    const int lane = threadIdx.x & 63, wave = wave_index();
+    const int n = lane & 15, q = lane >> 4;
+    const f32x4 *fp = reinterpret_cast<const f32x4 *>(frag + lane * 12);
+    const f32x4 fa = fp[0], fb = fp[1], fs = fp[2];
+    // LDS index of amplitude j of group (16 b + n) = per-lane part ^ uniform part of b
+    const int lane_part = L::map(spread_index<4, int>(n, lt));
+    int in[4], out[4];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        off_in[i] = local_offset<4, int>(2 * i + h, lt);
-        const int r = 2 * i;
-        const int row = 8 * (r >> 2) + 4 * h + (r & 3);
-        off_out[i] = local_offset<4, int>(row >> 1, lt);
+    for (int s = 0; s < 4; ++s) {
+        in[s] = lane_part ^ L::map(local_offset<4, int>(4 * s + q, lt));
+        out[s] = lane_part ^ L::map(local_offset<4, int>(4 * q + s, lt));
     }
-    const int batches = 1 << (tb - 4 - 5);
-    for (int b = wave; b < batches; b += kBlock / 64) {
-        const int lb = spread_index<4, int>(b * 32 + n, lt);
-        float2 v[8];
+    const int iters = (1 << (tb - 4 - 4)) / W;  // batches per wave, >= 1 for tb >= 10
+    int ub = L::map(spread_index<4, int>(wave << 4, lt));
+    float2 v[4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = sd[lb + off_in[i]];
-        f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < 4; ++s) v[s] = sd[in[s] ^ ub];
+    for (int it = 0; it < iters; ++it) {
+        const int itn = it + 1 < iters ? it + 1 : it;
+        const int ubn = L::map(spread_index<4, int>((wave + W * itn) << 4, lt));
+        float2 w[4];
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const float bv = (s & 1) ? v[s >> 1].y : v[s >> 1].x;
-            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(afr[s], bv, acc, 0, 0, 0);
+        for (int s = 0; s < 4; ++s) w[s] = sd[in[s] ^ ubn];
+        f32x4 t1 = {0.f, 0.f, 0.f, 0.f}, t2 = t1, t3 = t1;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s], v[s].x, t1, 0, 0, 0);
+            t2 = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[s], v[s].y, t2, 0, 0, 0);
+            t3 = __builtin_amdgcn_mfma_f32_16x16x4f32(fs[s], v[s].x + v[s].y, t3, 0, 0, 0);
         }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) sd[lb + off_out[i]] = make_float2(acc[2 * i], acc[2 * i + 1]);
+        for (int r = 0; r < 4; ++r)
+            sd[out[r] ^ ub] = make_float2(t1[r] - t2[r], t3[r] - t1[r] - t2[r]);
+        ub = ubn;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = w[s];
     }
 }
 
 // 16 groups per wavefront iteration; the accumulator rows 4q + r give lane
-// quarter q the amplitudes 2q (r = 0, 1) and 2q + 1 (r = 2, 3).
+// quarter q the amplitudes 2q (r = 0, 1) and 2q + 1 (r = 2, 3).  As for k = 4
+// the next iteration's amplitudes are read ahead of this one's MFMAs.
+template <class L>
 __device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const float *__restrict__ frag,
                                                 const int *lt, int tb) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int W = kBlock / 64;
+    const int lane = threadIdx.x & 63, wave = wave_index();
     const int n = lane & 15, q = lane >> 4;
     const f32x4 afr = *reinterpret_cast<const f32x4 *>(frag + lane * 4);
-    int off_in[4];
+    // lane quarter q needs only component q & 1 of its inputs: read floats
+    const float *sf = reinterpret_cast<const float *>(sd);
+    const int lane_part = L::map(spread_index<3, int>(n, lt));
+    int in[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) off_in[s] = local_offset<3, int>(2 * s + (q >> 1), lt);
-    const int off_o0 = local_offset<3, int>(2 * q, lt);
-    const int off_o1 = local_offset<3, int>(2 * q + 1, lt);
-    const bool im = (q & 1) != 0;
-    const int batches = 1 << (tb - 3 - 4);
-    for (int b = wave; b < batches; b += kBlock / 64) {
-        const int lb = spread_index<3, int>(b * 16 + n, lt);
-        float bv[4];
+    for (int s = 0; s < 4; ++s)
+        in[s] = (2 * (lane_part ^ L::map(local_offset<3, int>(2 * s + (q >> 1), lt)))) | (q & 1);
+    const int o0 = lane_part ^ L::map(local_offset<3, int>(2 * q, lt));
+    const int o1 = lane_part ^ L::map(local_offset<3, int>(2 * q + 1, lt));
+    const int iters = (1 << (tb - 3 - 4)) / W;  // batches per wave, >= 2 for tb >= 10
+    int ub = L::map(spread_index<3, int>(wave << 4, lt));
+    float v[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const float2 v = sd[lb + off_in[s]];
-            bv[s] = im ? v.y : v.x;
-        }
+    for (int s = 0; s < 4; ++s) v[s] = sf[in[s] ^ (2 * ub)];
+    for (int it = 0; it < iters; ++it) {
+        const int itn = it + 1 < iters ? it + 1 : it;
+        const int ubn = L::map(spread_index<3, int>((wave + W * itn) << 4, lt));
+        float w[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) w[s] = sf[in[s] ^ (2 * ubn)];
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[s], bv[s], acc, 0, 0, 0);
-        // every lane's reads of this iteration are complete before any write
-        __builtin_amdgcn_wave_barrier();
-        sd[lb + off_o0] = make_float2(acc[0], acc[1]);
-        sd[lb + off_o1] = make_float2(acc[2], acc[3]);
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[s], v[s], acc, 0, 0, 0);
+        sd[o0 ^ ub] = make_float2(acc[0], acc[1]);
+        sd[o1 ^ ub] = make_float2(acc[2], acc[3]);
+        ub = ubn;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) v[s] = w[s];
     }
 }
 
@@ -354,10 +435,12 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
     // the loop so that at the loop head the only pending memory operations are
     // the prefetch loads followed by the previous tile's stores; the wait for
     // the loads then leaves the younger stores in flight.
+    // LDS index of local index threadIdx.x + 256 r: the map leaves r alone
+    const int tid_l = SwizzledTile::map(int(threadIdx.x));
     auto run_tile = [&](Idx t) {
         __syncthreads();  // the previous tile is out of LDS; matrices staged
 #pragma unroll
-        for (int r = 0; r < R; ++r) sd[threadIdx.x + (r << 8)] = v[r];
+        for (int r = 0; r < R; ++r) sd[tid_l + (r << 8)] = v[r];
         const Idx base = tile_base(t);
         const Idx next = t + gridDim.x;
         if (next < n_tiles) fetch(next, v);
@@ -368,18 +451,22 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
 #pragma unroll
             for (int b = 0; b < kMaxGateQubits; ++b) lt[b] = a.g[gi].lt[b];
             switch (k) {
-                case 1: tile_gate_small<1>(sd, a.g[gi].mat, lt, TB); break;
-                case 2: tile_gate_small<2>(sd, a.g[gi].mat, lt, TB); break;
-                case 3: tile_gate_mfma3(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs), lt, TB); break;
-                case 4: tile_gate_mfma4(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs), lt, TB); break;
+                case 1: tile_gate_small<1, SwizzledTile>(sd, a.g[gi].mat, lt, TB); break;
+                case 2: tile_gate_small<2, SwizzledTile>(sd, a.g[gi].mat, lt, TB); break;
+                case 3:
+                    tile_gate_mfma3<SwizzledTile>(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs), lt, TB);
+                    break;
+                case 4:
+                    tile_gate_mfma4<SwizzledTile>(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs), lt, TB);
+                    break;
                 default:
-                    if constexpr (K5) tile_gate_valu<5>(sd, sm + a.g[gi].lofs, lt, TB);
+                    if constexpr (K5) tile_gate_valu<5, SwizzledTile>(sd, sm + a.g[gi].lofs, lt, TB);
                     break;
             }
             __syncthreads();
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) amp[base + off_r[r]] = sd[threadIdx.x + (r << 8)];
+        for (int r = 0; r < R; ++r) amp[base + off_r[r]] = sd[tid_l + (r << 8)];
     };
     run_tile(tile);
     for (tile += gridDim.x; tile < n_tiles; tile += gridDim.x) run_tile(tile);
@@ -457,26 +544,26 @@ __device__ __forceinline__ void batched_gate(float2 *__restrict__ sd, float *__r
 #pragma unroll
     for (int b = 0; b < kMaxGateQubits; ++b) lt[b] = g.lt[b];
     if (g.k == 1) {
-        tile_gate_small<1>(sd, m, lt, tb);
+        tile_gate_small<1, PlainTile>(sd, m, lt, tb);
     } else if (g.k == 2) {
-        tile_gate_small<2>(sd, m, lt, tb);
+        tile_gate_small<2, PlainTile>(sd, m, lt, tb);
     } else if (g.k == 3 && tb >= 10) {
         stage_frag3(frag, m);
         __syncthreads();
-        tile_gate_mfma3(sd, frag, lt, tb);
+        tile_gate_mfma3<PlainTile>(sd, frag, lt, tb);
     } else if (g.k == 4 && tb >= 10) {
         stage_frag4(frag, m);
         __syncthreads();
-        tile_gate_mfma4(sd, frag, lt, tb);
+        tile_gate_mfma4<PlainTile>(sd, frag, lt, tb);
     } else {
         const int dd = 1 << (2 * g.k);
         float2 *mm = reinterpret_cast<float2 *>(frag);
         for (int i = threadIdx.x; i < dd; i += kBlock) mm[i] = m[i];
         __syncthreads();
         switch (g.k) {
-            case 3: tile_gate_valu<3>(sd, mm, lt, tb); break;
-            case 4: tile_gate_valu<4>(sd, mm, lt, tb); break;
-            default: tile_gate_valu<5>(sd, mm, lt, tb); break;
+            case 3: tile_gate_valu<3, PlainTile>(sd, mm, lt, tb); break;
+            case 4: tile_gate_valu<4, PlainTile>(sd, mm, lt, tb); break;
+            default: tile_gate_valu<5, PlainTile>(sd, mm, lt, tb); break;
         }
     }
     __syncthreads();
