@@ -20,6 +20,11 @@ HOST_SOURCES = ["qs_runtime.cpp", "qs_plan.cpp"]
 # float code.
 NO_PACKED_FP32 = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
+# MFMA accumulators in ordinary VGPRs: FP32 MFMA and VALU share the SIMD's
+# issue cycles on gfx950, so the accumulator-register reads of the AGPR form
+# cost matrix time.
+MFMA_VGPR = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+
 
 def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -36,9 +41,9 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     try:
         for src in DEVICE_SOURCES + HOST_SOURCES:
             obj = os.path.join(tmpdir, src + ".o")
-            lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-            cmd = [hipcc()] + common + NO_PACKED_FP32 + lang + ["-c", os.path.join(CSRC, src),
-                                                                 "-o", obj]
+            extra = MFMA_VGPR if src.endswith(".hip") else []
+            cmd = [hipcc()] + common + NO_PACKED_FP32 + extra + ["-x", "hip", "-c",
+                                                                  os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,

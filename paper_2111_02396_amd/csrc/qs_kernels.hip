@@ -115,6 +115,8 @@ __global__ __launch_bounds__(kBlock) void apply_direct(float2 *__restrict__ amp,
     }
 }
 
+__host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
 // ---- LDS layout of a tile
 // Gates read and write a tile in LDS one 64-lane instruction at a time; the
 // lanes of an instruction span a few group bits and target bits of the
@@ -142,6 +144,18 @@ struct PlainTile {
     __device__ __forceinline__ static int map(int x) { return x; }
 };
 
+// LDS accesses by byte offset: each address is one XOR of a per-lane and a
+// wave-uniform byte offset.
+__device__ __forceinline__ float2 lds_get(const float2 *sd, int byte) {
+    return *reinterpret_cast<const float2 *>(reinterpret_cast<const char *>(sd) + byte);
+}
+__device__ __forceinline__ void lds_put(float2 *sd, int byte, float2 v) {
+    *reinterpret_cast<float2 *>(reinterpret_cast<char *>(sd) + byte) = v;
+}
+__device__ __forceinline__ float lds_getf(const float2 *sd, int byte) {
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(sd) + byte);
+}
+
 // Wavefront index as a scalar, so loops over it stay uniform.
 __device__ __forceinline__ int wave_index() {
     return __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
@@ -150,7 +164,7 @@ __device__ __forceinline__ int wave_index() {
 // One gate on a tile held in LDS with VALU multiply-adds: every group of the
 // tile is owned by one work-item, which gathers its 2^K amplitudes,
 // multiplies, and writes back in place.  `m` is an LDS copy of the matrix.
-template <int K, class L>
+template <int K, class L, int NT = kBlock>
 __device__ __forceinline__ void tile_gate_valu(float2 *__restrict__ sd, const float2 *__restrict__ m,
                                                const int *lt, int tb) {
     constexpr int D = 1 << K;
@@ -158,7 +172,7 @@ __device__ __forceinline__ void tile_gate_valu(float2 *__restrict__ sd, const fl
 #pragma unroll
     for (int j = 0; j < D; ++j) off[j] = L::map(local_offset<K, int>(j, lt));
     const int groups = 1 << (tb - K);
-    for (int gg = threadIdx.x; gg < groups; gg += kBlock) {
+    for (int gg = threadIdx.x; gg < groups; gg += NT) {
         const int lb = L::map(spread_index<K, int>(gg, lt));
         float2 v[D];
 #pragma unroll
@@ -174,10 +188,10 @@ __device__ __forceinline__ void tile_gate_valu(float2 *__restrict__ sd, const fl
 }
 
 // K <= 2: the matrix (at most 16 entries) sits in SGPRs for the whole tile.
-// Work-item (lane, wave) owns groups lane + 64 wave + 256 i; the next group's
+// Work-item (lane, wave) owns groups lane + 64 wave + NT i; the next group's
 // amplitudes are read before this one's are written (the last iteration
 // re-reads its own group, which is harmless: the reads precede the writes).
-template <int K, class L>
+template <int K, class L, int NT = kBlock>
 __device__ __forceinline__ void tile_gate_small(float2 *__restrict__ sd, const float2 *gm,
                                                 const int *lt, int tb) {
     constexpr int D = 1 << K;
@@ -187,9 +201,10 @@ __device__ __forceinline__ void tile_gate_small(float2 *__restrict__ sd, const f
     int off[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) off[j] = L::map(local_offset<K, int>(j, lt));
-    if (tb < K + 8) {  // fewer groups than work-items (small resident states)
+    constexpr int NB = ilog2(NT);
+    if (tb < K + NB) {  // fewer groups than work-items (small resident states)
         const int groups = 1 << (tb - K);
-        for (int gg = threadIdx.x; gg < groups; gg += kBlock) {
+        for (int gg = threadIdx.x; gg < groups; gg += NT) {
             const int lb = L::map(spread_index<K, int>(gg, lt));
             float2 v[D];
 #pragma unroll
@@ -206,14 +221,14 @@ __device__ __forceinline__ void tile_gate_small(float2 *__restrict__ sd, const f
     }
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int lane_part = L::map(spread_index<K, int>(lane, lt));
-    const int iters = 1 << (tb - K - 8);
+    const int iters = 1 << (tb - K - NB);
     int lb = lane_part ^ L::map(spread_index<K, int>(wave << 6, lt));
     float2 v[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) v[j] = sd[lb ^ off[j]];
     for (int it = 0; it < iters; ++it) {
         const int itn = it + 1 < iters ? it + 1 : it;
-        const int lbn = lane_part ^ L::map(spread_index<K, int>((wave << 6) | (itn << 8), lt));
+        const int lbn = lane_part ^ L::map(spread_index<K, int>((wave << 6) | (itn << NB), lt));
         float2 w[D];
 #pragma unroll
         for (int j = 0; j < D; ++j) w[j] = sd[lbn ^ off[j]];
@@ -250,8 +265,9 @@ __device__ __forceinline__ float real_form(float2 u, int co, int ci) {
 // A[l%16][4s + l/16] and B[4s + l/16][l%16]; accumulator r is row 4(l/16) + r,
 // column l%16.  Fragment layout: frag[lane * 12 + 4 m + s] = M_m[l%16][4s + l/16]
 // with M_0 = Re U, M_1 = Im U, M_2 = Re U + Im U.
+template <int NT = kBlock>
 __device__ __forceinline__ void stage_frag4(float *__restrict__ frag, const float2 *__restrict__ u) {
-    for (int i = threadIdx.x; i < 64 * 12; i += kBlock) {
+    for (int i = threadIdx.x; i < 64 * 12; i += NT) {
         const int lane = i / 12, rem = i - 12 * lane;
         const int m = rem >> 2, s = rem & 3;
         const float2 e = u[(lane & 15) * 16 + 4 * s + (lane >> 4)];
@@ -262,8 +278,9 @@ __device__ __forceinline__ void stage_frag4(float *__restrict__ frag, const floa
 // k = 3, v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16] and B[l/16][l%16];
 // step s covers real columns 4s..4s+3: lane quarter q = l/16 reads amplitude
 // j = 2s + q/2 and uses component q%2.  Fragment layout: frag[lane * 4 + s].
+template <int NT = kBlock>
 __device__ __forceinline__ void stage_frag3(float *__restrict__ frag, const float2 *__restrict__ u) {
-    for (int i = threadIdx.x; i < 64 * 4; i += kBlock) {
+    for (int i = threadIdx.x; i < 64 * 4; i += NT) {
         const int lane = i >> 2, s = i & 3;
         const int m = lane & 15, q = lane >> 4;
         const int ji = 2 * s + (q >> 1);
@@ -276,33 +293,33 @@ __device__ __forceinline__ void stage_frag3(float *__restrict__ frag, const floa
 // iteration's amplitudes are read before this one's MFMAs, so the LDS latency
 // hides behind them; iterations touch disjoint groups, so reading ahead of
 // the writes is safe.
-template <class L>
+template <class L, int NT = kBlock>
 __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const float *__restrict__ frag,
                                                 const int *lt, int tb) {
-    constexpr int W = kBlock / 64;
+    constexpr int W = NT / 64;
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int n = lane & 15, q = lane >> 4;
     const f32x4 *fp = reinterpret_cast<const f32x4 *>(frag + lane * 12);
     const f32x4 fa = fp[0], fb = fp[1], fs = fp[2];
-    // LDS index of amplitude j of group (16 b + n) = per-lane part ^ uniform part of b
+    // LDS byte offset of amplitude j of group (16 b + n) = per-lane part ^ uniform part of b
     const int lane_part = L::map(spread_index<4, int>(n, lt));
     int in[4], out[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        in[s] = lane_part ^ L::map(local_offset<4, int>(4 * s + q, lt));
-        out[s] = lane_part ^ L::map(local_offset<4, int>(4 * q + s, lt));
+        in[s] = 8 * (lane_part ^ L::map(local_offset<4, int>(4 * s + q, lt)));
+        out[s] = 8 * (lane_part ^ L::map(local_offset<4, int>(4 * q + s, lt)));
     }
-    const int iters = (1 << (tb - 4 - 4)) / W;  // batches per wave, >= 1 for tb >= 10
-    int ub = L::map(spread_index<4, int>(wave << 4, lt));
+    const int iters = (1 << (tb - 4 - 4)) / W;  // batches per wave: >= 1 needs tb >= 8 + log2 W
+    int ub = 8 * L::map(spread_index<4, int>(wave << 4, lt));
     float2 v[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = sd[in[s] ^ ub];
+    for (int s = 0; s < 4; ++s) v[s] = lds_get(sd, in[s] ^ ub);
     for (int it = 0; it < iters; ++it) {
         const int itn = it + 1 < iters ? it + 1 : it;
-        const int ubn = L::map(spread_index<4, int>((wave + W * itn) << 4, lt));
+        const int ubn = 8 * L::map(spread_index<4, int>((wave + W * itn) << 4, lt));
         float2 w[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) w[s] = sd[in[s] ^ ubn];
+        for (int s = 0; s < 4; ++s) w[s] = lds_get(sd, in[s] ^ ubn);
         f32x4 t1 = {0.f, 0.f, 0.f, 0.f}, t2 = t1, t3 = t1;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -312,7 +329,7 @@ __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const f
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            sd[out[r] ^ ub] = make_float2(t1[r] - t2[r], t3[r] - t1[r] - t2[r]);
+            lds_put(sd, out[r] ^ ub, make_float2(t1[r] - t2[r], t3[r] - t1[r] - t2[r]));
         ub = ubn;
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = w[s];
@@ -322,38 +339,37 @@ __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const f
 // 16 groups per wavefront iteration; the accumulator rows 4q + r give lane
 // quarter q the amplitudes 2q (r = 0, 1) and 2q + 1 (r = 2, 3).  As for k = 4
 // the next iteration's amplitudes are read ahead of this one's MFMAs.
-template <class L>
+template <class L, int NT = kBlock>
 __device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const float *__restrict__ frag,
                                                 const int *lt, int tb) {
-    constexpr int W = kBlock / 64;
+    constexpr int W = NT / 64;
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int n = lane & 15, q = lane >> 4;
     const f32x4 afr = *reinterpret_cast<const f32x4 *>(frag + lane * 4);
     // lane quarter q needs only component q & 1 of its inputs: read floats
-    const float *sf = reinterpret_cast<const float *>(sd);
     const int lane_part = L::map(spread_index<3, int>(n, lt));
     int in[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
-        in[s] = (2 * (lane_part ^ L::map(local_offset<3, int>(2 * s + (q >> 1), lt)))) | (q & 1);
-    const int o0 = lane_part ^ L::map(local_offset<3, int>(2 * q, lt));
-    const int o1 = lane_part ^ L::map(local_offset<3, int>(2 * q + 1, lt));
-    const int iters = (1 << (tb - 3 - 4)) / W;  // batches per wave, >= 2 for tb >= 10
-    int ub = L::map(spread_index<3, int>(wave << 4, lt));
+        in[s] = (8 * (lane_part ^ L::map(local_offset<3, int>(2 * s + (q >> 1), lt)))) | (4 * (q & 1));
+    const int o0 = 8 * (lane_part ^ L::map(local_offset<3, int>(2 * q, lt)));
+    const int o1 = 8 * (lane_part ^ L::map(local_offset<3, int>(2 * q + 1, lt)));
+    const int iters = (1 << (tb - 3 - 4)) / W;  // batches per wave: >= 1 needs tb >= 7 + log2 W
+    int ub = 8 * L::map(spread_index<3, int>(wave << 4, lt));
     float v[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = sf[in[s] ^ (2 * ub)];
+    for (int s = 0; s < 4; ++s) v[s] = lds_getf(sd, in[s] ^ ub);
     for (int it = 0; it < iters; ++it) {
         const int itn = it + 1 < iters ? it + 1 : it;
-        const int ubn = L::map(spread_index<3, int>((wave + W * itn) << 4, lt));
+        const int ubn = 8 * L::map(spread_index<3, int>((wave + W * itn) << 4, lt));
         float w[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) w[s] = sf[in[s] ^ (2 * ubn)];
+        for (int s = 0; s < 4; ++s) w[s] = lds_getf(sd, in[s] ^ ubn);
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[s], v[s], acc, 0, 0, 0);
-        sd[o0 ^ ub] = make_float2(acc[0], acc[1]);
-        sd[o1 ^ ub] = make_float2(acc[2], acc[3]);
+        lds_put(sd, o0 ^ ub, make_float2(acc[0], acc[1]));
+        lds_put(sd, o1 ^ ub, make_float2(acc[2], acc[3]));
         ub = ubn;
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = w[s];
@@ -370,12 +386,14 @@ __device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const f
 // cost one HBM read and one write.
 // K5: whether the launch holds a 5-qubit block (its VALU path needs ~70 more
 // VGPRs, so launches without one use a leaner instantiation).
-template <int TB, typename Idx, bool K5>
-__global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, Idx n_tiles,
-                                                     TileArgs a) {
+template <int TB, typename Idx, bool K5, int NT>
+__global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n_tiles,
+                                                 TileArgs a) {
+    constexpr int NB = ilog2(NT);
     static_assert(TB >= 10, "the MFMA gates need at least 32 groups per tile");
+    static_assert((1 << (TB - 8)) >= NT / 64, "every wavefront needs a 4-qubit batch");
     constexpr int E = 1 << TB;
-    constexpr int R = E / kBlock;
+    constexpr int R = E / NT;
     extern __shared__ float2 smem[];
     float2 *sd = smem;
     float2 *sm = smem + E;
@@ -383,15 +401,15 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
     if (tile >= n_tiles) return;  // uniform over the workgroup
     Idx off_tid = 0;
 #pragma unroll
-    for (int b = 0; b < 8; ++b)
+    for (int b = 0; b < NB; ++b)
         if ((threadIdx.x >> b) & 1) off_tid |= Idx(1) << a.pos[b];
     Idx off_r[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         Idx o = 0;
 #pragma unroll
-        for (int b = 8; b < TB; ++b)
-            if (((r << 8) >> b) & 1) o |= Idx(1) << a.pos[b];
+        for (int b = NB; b < TB; ++b)
+            if (((r << NB) >> b) & 1) o |= Idx(1) << a.pos[b];
         off_r[r] = o;
     }
     auto tile_base = [&](Idx t) {
@@ -423,11 +441,11 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
         const float2 *src = a.g[gi].mat;
         float2 *dst = sm + a.g[gi].lofs;
         if (k == 4) {
-            stage_frag4(reinterpret_cast<float *>(dst), src);
+            stage_frag4<NT>(reinterpret_cast<float *>(dst), src);
         } else if (k == 3) {
-            stage_frag3(reinterpret_cast<float *>(dst), src);
+            stage_frag3<NT>(reinterpret_cast<float *>(dst), src);
         } else if (k == 5) {
-            for (int i = threadIdx.x; i < 1024; i += kBlock) dst[i] = src[i];
+            for (int i = threadIdx.x; i < 1024; i += NT) dst[i] = src[i];
         }
     }
     // One tile: the prefetched amplitudes go to LDS, the next tile's loads are
@@ -435,12 +453,12 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
     // the loop so that at the loop head the only pending memory operations are
     // the prefetch loads followed by the previous tile's stores; the wait for
     // the loads then leaves the younger stores in flight.
-    // LDS index of local index threadIdx.x + 256 r: the map leaves r alone
+    // LDS index of local index threadIdx.x + NT r: the map leaves r alone
     const int tid_l = SwizzledTile::map(int(threadIdx.x));
     auto run_tile = [&](Idx t) {
         __syncthreads();  // the previous tile is out of LDS; matrices staged
 #pragma unroll
-        for (int r = 0; r < R; ++r) sd[tid_l + (r << 8)] = v[r];
+        for (int r = 0; r < R; ++r) sd[tid_l + (r << NB)] = v[r];
         const Idx base = tile_base(t);
         const Idx next = t + gridDim.x;
         if (next < n_tiles) fetch(next, v);
@@ -451,22 +469,24 @@ __global__ __launch_bounds__(kBlock) void apply_tile(float2 *__restrict__ amp, I
 #pragma unroll
             for (int b = 0; b < kMaxGateQubits; ++b) lt[b] = a.g[gi].lt[b];
             switch (k) {
-                case 1: tile_gate_small<1, SwizzledTile>(sd, a.g[gi].mat, lt, TB); break;
-                case 2: tile_gate_small<2, SwizzledTile>(sd, a.g[gi].mat, lt, TB); break;
+                case 1: tile_gate_small<1, SwizzledTile, NT>(sd, a.g[gi].mat, lt, TB); break;
+                case 2: tile_gate_small<2, SwizzledTile, NT>(sd, a.g[gi].mat, lt, TB); break;
                 case 3:
-                    tile_gate_mfma3<SwizzledTile>(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs), lt, TB);
+                    tile_gate_mfma3<SwizzledTile, NT>(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs),
+                                                      lt, TB);
                     break;
                 case 4:
-                    tile_gate_mfma4<SwizzledTile>(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs), lt, TB);
+                    tile_gate_mfma4<SwizzledTile, NT>(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs),
+                                                      lt, TB);
                     break;
                 default:
-                    if constexpr (K5) tile_gate_valu<5, SwizzledTile>(sd, sm + a.g[gi].lofs, lt, TB);
+                    if constexpr (K5) tile_gate_valu<5, SwizzledTile, NT>(sd, sm + a.g[gi].lofs, lt, TB);
                     break;
             }
             __syncthreads();
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) amp[base + off_r[r]] = sd[tid_l + (r << 8)];
+        for (int r = 0; r < R; ++r) amp[base + off_r[r]] = sd[tid_l + (r << NB)];
     };
     run_tile(tile);
     for (tile += gridDim.x; tile < n_tiles; tile += gridDim.x) run_tile(tile);
@@ -1012,25 +1032,32 @@ int device_cus() {
     return cus;
 }
 
-template <int TB, typename Idx, bool K5>
+template <int TB, typename Idx, bool K5, int NT>
 hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
     static bool attr_set = false;
+    static int reg_limit = 1;  // resident workgroups per CU allowed by registers and waves
     const size_t lds = sizeof(float2) * ((size_t(1) << TB) + size_t(a.mat_total));
+    const void *fn = reinterpret_cast<const void *>(&apply_tile<TB, Idx, K5, NT>);
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&apply_tile<TB, Idx, K5>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            int(sizeof(float2) * ((size_t(1) << TB) + kTileMatBudget)));
         if (e != hipSuccess) return e;
+        // with the smallest LDS footprint the LDS is not what limits the count
+        int blocks = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, NT,
+                                                         sizeof(float2) * (size_t(1) << TB));
+        if (e != hipSuccess) return e;
+        reg_limit = blocks < 1 ? 1 : blocks;
         attr_set = true;
     }
     const Idx n_tiles = Idx(1) << (n - TB);
-    // persistent grid: as many workgroups as fit on the chip at this LDS size
+    // persistent grid: as many workgroups as are resident at once at this LDS size
     int per_cu = int((160u * 1024u) / lds);
     if (per_cu < 1) per_cu = 1;
-    if (per_cu > 8) per_cu = 8;
+    if (per_cu > reg_limit) per_cu = reg_limit;
     uint64_t grid = uint64_t(device_cus()) * uint64_t(per_cu);
     if (grid > uint64_t(n_tiles)) grid = uint64_t(n_tiles);
-    apply_tile<TB, Idx, K5><<<unsigned(grid), kBlock, lds, st>>>(amp, n_tiles, a);
+    apply_tile<TB, Idx, K5, NT><<<unsigned(grid), NT, lds, st>>>(amp, n_tiles, a);
     return hipGetLastError();
 }
 
@@ -1038,7 +1065,13 @@ template <int TB, typename Idx>
 hipError_t tile_launch_k(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
     bool k5 = false;
     for (int gi = 0; gi < a.n_gates; ++gi) k5 |= a.g[gi].k == 5;
-    return k5 ? tile_launch<TB, Idx, true>(amp, n, a, st) : tile_launch<TB, Idx, false>(amp, n, a, st);
+    // 2^13-amplitude tiles (64 KiB) leave room for two or three workgroups per
+    // CU; 512 work-items each (two wavefronts per SIMD per group) keep four or
+    // more wavefronts per SIMD to hide LDS and MFMA latency.  Smaller tiles
+    // fit more workgroups and do better with 256 (measured on the 24-qubit
+    // noisy grid).
+    constexpr int NT = TB >= 13 ? 512 : kBlock;
+    return k5 ? tile_launch<TB, Idx, true, NT>(amp, n, a, st) : tile_launch<TB, Idx, false, NT>(amp, n, a, st);
 }
 
 template <typename Idx>
