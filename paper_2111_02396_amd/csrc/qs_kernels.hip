@@ -301,25 +301,31 @@ __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const f
     const int n = lane & 15, q = lane >> 4;
     const f32x4 *fp = reinterpret_cast<const f32x4 *>(frag + lane * 12);
     const f32x4 fa = fp[0], fb = fp[1], fs = fp[2];
-    // LDS byte offset of amplitude j of group (16 b + n) = per-lane part ^ uniform part of b
+    // LDS byte offset of amplitude j of group 16 b + n.  The local index is
+    // spread(16 b + n) | offset(j); with j = 4 s + q (inputs) or 4 q + r
+    // (outputs) each part splits into a per-lane term (n, q) and a
+    // wave-uniform term (b, s or r), and the layout map is linear, so every
+    // access is one XOR of a lane register with a scalar.
     const int lane_part = L::map(spread_index<4, int>(n, lt));
-    int in[4], out[4];
+    const int lin = 8 * (lane_part ^ L::map(((q & 1) << lt[0]) | ((q >> 1) << lt[1])));
+    const int lout = 8 * (lane_part ^ L::map(((q & 1) << lt[2]) | ((q >> 1) << lt[3])));
+    int uin[4], uout[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        in[s] = 8 * (lane_part ^ L::map(local_offset<4, int>(4 * s + q, lt)));
-        out[s] = 8 * (lane_part ^ L::map(local_offset<4, int>(4 * q + s, lt)));
+        uin[s] = 8 * L::map(((s & 1) << lt[2]) | ((s >> 1) << lt[3]));
+        uout[s] = 8 * L::map(((s & 1) << lt[0]) | ((s >> 1) << lt[1]));
     }
     const int iters = (1 << (tb - 4 - 4)) / W;  // batches per wave: >= 1 needs tb >= 8 + log2 W
     int ub = 8 * L::map(spread_index<4, int>(wave << 4, lt));
     float2 v[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = lds_get(sd, in[s] ^ ub);
+    for (int s = 0; s < 4; ++s) v[s] = lds_get(sd, lin ^ (uin[s] ^ ub));
     for (int it = 0; it < iters; ++it) {
         const int itn = it + 1 < iters ? it + 1 : it;
         const int ubn = 8 * L::map(spread_index<4, int>((wave + W * itn) << 4, lt));
         float2 w[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) w[s] = lds_get(sd, in[s] ^ ubn);
+        for (int s = 0; s < 4; ++s) w[s] = lds_get(sd, lin ^ (uin[s] ^ ubn));
         f32x4 t1 = {0.f, 0.f, 0.f, 0.f}, t2 = t1, t3 = t1;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -329,7 +335,7 @@ __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const f
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            lds_put(sd, out[r] ^ ub, make_float2(t1[r] - t2[r], t3[r] - t1[r] - t2[r]));
+            lds_put(sd, lout ^ (uout[r] ^ ub), make_float2(t1[r] - t2[r], t3[r] - t1[r] - t2[r]));
         ub = ubn;
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = w[s];
@@ -346,30 +352,32 @@ __device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const f
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int n = lane & 15, q = lane >> 4;
     const f32x4 afr = *reinterpret_cast<const f32x4 *>(frag + lane * 4);
-    // lane quarter q needs only component q & 1 of its inputs: read floats
+    // Offsets split into per-lane and wave-uniform terms as for k = 4: input
+    // amplitude 2 s + (q >> 1), component q & 1 (lane quarter q needs only
+    // that float); outputs 2 q and 2 q + 1.
     const int lane_part = L::map(spread_index<3, int>(n, lt));
-    int in[4];
+    const int lin = (8 * (lane_part ^ L::map((q >> 1) << lt[0]))) | (4 * (q & 1));
+    const int lout = 8 * (lane_part ^ L::map(((q & 1) << lt[1]) | ((q >> 1) << lt[2])));
+    const int uo1 = 8 * L::map(1 << lt[0]);
+    int uin[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-        in[s] = (8 * (lane_part ^ L::map(local_offset<3, int>(2 * s + (q >> 1), lt)))) | (4 * (q & 1));
-    const int o0 = 8 * (lane_part ^ L::map(local_offset<3, int>(2 * q, lt)));
-    const int o1 = 8 * (lane_part ^ L::map(local_offset<3, int>(2 * q + 1, lt)));
+    for (int s = 0; s < 4; ++s) uin[s] = 8 * L::map(((s & 1) << lt[1]) | ((s >> 1) << lt[2]));
     const int iters = (1 << (tb - 3 - 4)) / W;  // batches per wave: >= 1 needs tb >= 7 + log2 W
     int ub = 8 * L::map(spread_index<3, int>(wave << 4, lt));
     float v[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = lds_getf(sd, in[s] ^ ub);
+    for (int s = 0; s < 4; ++s) v[s] = lds_getf(sd, lin ^ (uin[s] ^ ub));
     for (int it = 0; it < iters; ++it) {
         const int itn = it + 1 < iters ? it + 1 : it;
         const int ubn = 8 * L::map(spread_index<3, int>((wave + W * itn) << 4, lt));
         float w[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) w[s] = lds_getf(sd, in[s] ^ ubn);
+        for (int s = 0; s < 4; ++s) w[s] = lds_getf(sd, lin ^ (uin[s] ^ ubn));
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[s], v[s], acc, 0, 0, 0);
-        lds_put(sd, o0 ^ ub, make_float2(acc[0], acc[1]));
-        lds_put(sd, o1 ^ ub, make_float2(acc[2], acc[3]));
+        lds_put(sd, lout ^ ub, make_float2(acc[0], acc[1]));
+        lds_put(sd, lout ^ (uo1 ^ ub), make_float2(acc[2], acc[3]));
         ub = ubn;
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = w[s];
@@ -394,9 +402,11 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
     static_assert((1 << (TB - 8)) >= NT / 64, "every wavefront needs a 4-qubit batch");
     constexpr int E = 1 << TB;
     constexpr int R = E / NT;
-    extern __shared__ float2 smem[];
-    float2 *sd = smem;
-    float2 *sm = smem + E;
+    // The tile is a static array (its LDS address is a link-time constant
+    // that folds into the LDS instructions' offsets); the launch's matrices
+    // follow it in dynamic LDS.
+    __shared__ float2 sd[E];
+    extern __shared__ float2 sm[];
     Idx tile = blockIdx.x;
     if (tile >= n_tiles) return;  // uniform over the workgroup
     Idx off_tid = 0;
@@ -448,18 +458,26 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
             for (int i = threadIdx.x; i < 1024; i += NT) dst[i] = src[i];
         }
     }
-    // One tile: the prefetched amplitudes go to LDS, the next tile's loads are
-    // issued, the gates run, the tile is stored.  The first tile is peeled off
-    // the loop so that at the loop head the only pending memory operations are
-    // the prefetch loads followed by the previous tile's stores; the wait for
-    // the loads then leaves the younger stores in flight.
+    // One tile: the prefetched amplitudes go to LDS, the previous tile's
+    // results (held in registers since its gates finished) are stored, the
+    // next tile's loads are issued, the gates run, and the results are read
+    // out of LDS into registers.  Stores and loads therefore drain while this
+    // tile's gates run, instead of the stores going out in a burst at the end
+    // of every tile; the wait for the prefetch at the next loop head covers
+    // memory operations issued a whole gate phase earlier.
     // LDS index of local index threadIdx.x + NT r: the map leaves r alone
     const int tid_l = SwizzledTile::map(int(threadIdx.x));
-    auto run_tile = [&](Idx t) {
+    float2 o[R];
+    Idx prev_base = 0;
+    auto run_tile = [&](Idx t, bool has_prev) {
         __syncthreads();  // the previous tile is out of LDS; matrices staged
 #pragma unroll
         for (int r = 0; r < R; ++r) sd[tid_l + (r << NB)] = v[r];
         const Idx base = tile_base(t);
+        if (has_prev) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) amp[prev_base + off_r[r]] = o[r];
+        }
         const Idx next = t + gridDim.x;
         if (next < n_tiles) fetch(next, v);
         __syncthreads();
@@ -486,10 +504,13 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
             __syncthreads();
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) amp[base + off_r[r]] = sd[tid_l + (r << NB)];
+        for (int r = 0; r < R; ++r) o[r] = sd[tid_l + (r << NB)];
+        prev_base = base;
     };
-    run_tile(tile);
-    for (tile += gridDim.x; tile < n_tiles; tile += gridDim.x) run_tile(tile);
+    run_tile(tile, false);
+    for (tile += gridDim.x; tile < n_tiles; tile += gridDim.x) run_tile(tile, true);
+#pragma unroll
+    for (int r = 0; r < R; ++r) amp[prev_base + off_r[r]] = o[r];
 }
 
 // ---------------------------------------------------------------- branch selection
@@ -1036,16 +1057,17 @@ template <int TB, typename Idx, bool K5, int NT>
 hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
     static bool attr_set = false;
     static int reg_limit = 1;  // resident workgroups per CU allowed by registers and waves
-    const size_t lds = sizeof(float2) * ((size_t(1) << TB) + size_t(a.mat_total));
+    // static tile + dynamic matrices
+    const size_t dyn = sizeof(float2) * size_t(a.mat_total);
+    const size_t lds = sizeof(float2) * (size_t(1) << TB) + dyn;
     const void *fn = reinterpret_cast<const void *>(&apply_tile<TB, Idx, K5, NT>);
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           int(sizeof(float2) * ((size_t(1) << TB) + kTileMatBudget)));
+                                           int(sizeof(float2) * kTileMatBudget));
         if (e != hipSuccess) return e;
-        // with the smallest LDS footprint the LDS is not what limits the count
+        // with no matrices the LDS is not what limits the count
         int blocks = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, NT,
-                                                         sizeof(float2) * (size_t(1) << TB));
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, NT, 0);
         if (e != hipSuccess) return e;
         reg_limit = blocks < 1 ? 1 : blocks;
         attr_set = true;
@@ -1057,7 +1079,7 @@ hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
     if (per_cu > reg_limit) per_cu = reg_limit;
     uint64_t grid = uint64_t(device_cus()) * uint64_t(per_cu);
     if (grid > uint64_t(n_tiles)) grid = uint64_t(n_tiles);
-    apply_tile<TB, Idx, K5, NT><<<unsigned(grid), NT, lds, st>>>(amp, n_tiles, a);
+    apply_tile<TB, Idx, K5, NT><<<unsigned(grid), NT, dyn, st>>>(amp, n_tiles, a);
     return hipGetLastError();
 }
 
