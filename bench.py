@@ -54,6 +54,32 @@ def measured_traffic():
         return None
 
 
+def bench_copy(args) -> int:
+    """Device-to-device copy of a 2^24-amplitude complex64 state (128 MiB read,
+    128 MiB written per copy): the kernel of known traffic whose FETCH_SIZE /
+    WRITE_SIZE readings scale the counters taken on the sweep kernels."""
+    import torch
+
+    a = torch.randn(1 << 24, dtype=torch.complex64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(args.warmup):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    nbytes = 2 * a.numel() * 8
+    print(json.dumps({"metric": "device copy bandwidth (counter calibration)", "value": nbytes / dt / 1e9,
+                      "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+                      "config": {"workload": "copy of a 2^24-amplitude complex64 state",
+                                 "bytes_per_copy": nbytes}}), flush=True)
+    return 0
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -97,8 +123,11 @@ def main() -> int:
                     help="trajectories timed with the conventional method (0 = skip)")
     ap.add_argument("--cpu-cycles", type=int, default=1,
                     help="cycles of trajectory 0 timed on the oracle (0 = skip)")
-    ap.add_argument("--workload", default="grid24", choices=["grid24", "batched", "serving", "phase_damping"],
-                    help="grid24 (default): the headline line; batched / serving: the other forms")
+    ap.add_argument("--workload", default="grid24",
+                    choices=["grid24", "batched", "serving", "phase_damping", "copy"],
+                    help="grid24 (default): the headline line; batched / serving / phase_damping: "
+                         "the other forms; copy: a plain device copy of a 24-qubit state, the "
+                         "reference for calibrating HBM byte counters")
     ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="serving: arrivals/s (0 = ~70%% load)")
     ap.add_argument("--max-qubits", type=int, default=26, help="serving: largest request")
@@ -126,6 +155,8 @@ def main() -> int:
         return bench_serving(args)
     if args.workload == "phase_damping":
         return bench_phase_damping(args)
+    if args.workload == "copy":
+        return bench_copy(args)
     w = W.grid24_workload(p_dep=args.p_dep)
     c = w.circuit
     n = c.n
@@ -153,6 +184,7 @@ def main() -> int:
     t0 = time.perf_counter()
     gate_ms = 0.0
     gate_launches = 0
+    zero_start = 0
     sweeps = 0
     gate_sweeps = 0
     slow = 0
@@ -161,6 +193,7 @@ def main() -> int:
         r = step(s * args.traj, True)
         gate_ms += r["gate_kernel_ms"]
         gate_launches += r["gate_kernel_launches"]
+        zero_start += r["zero_start_sweeps"]
         sweeps += r["sweeps"]
         gate_sweeps += r["gate_sweeps"]
         slow += int(r["n_slow"].sum())
@@ -173,8 +206,13 @@ def main() -> int:
     value = total_traj / elapsed
 
     avg_gate_s = (gate_ms / 1e3) / max(gate_launches, 1)
-    bytes_per_launch = 16 * (1 << n)  # one read + one write of the complex64 state
-    achieved = bytes_per_launch / avg_gate_s / 1e9
+    # algorithmic bytes: one read + one write of the complex64 state per sweep,
+    # except a trajectory's first sweep, which starts from |0...0> written on
+    # chip and only writes
+    state_bytes = 8 * (1 << n)
+    alg_bytes = 2 * state_bytes * gate_launches - state_bytes * zero_start
+    bytes_per_launch = alg_bytes / max(gate_launches, 1)
+    achieved = alg_bytes / (gate_ms / 1e3) / 1e9 if gate_ms > 0 else 0.0
     traffic = measured_traffic()
     # complex mat-vec flops of the fused blocks applied (8 * 2^k per amplitude, Section 3.1)
     flops = sum(k_hist[k] * (8 << k) for k in range(1, 6)) * float(1 << n)
@@ -230,6 +268,8 @@ def main() -> int:
             "kernel": "fused-gate sweep (apply_tile / apply_direct): one read + one write of the state",
             "avg_launch_us": avg_gate_s * 1e6,
             "launches": gate_launches,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "zero_start_launches": zero_start,
         },
         "compute": {"achieved": flops_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": flops_tf / FP32_PEAK_TFLOPS,

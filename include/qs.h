@@ -123,6 +123,9 @@ typedef struct {
     double gate_kernel_ms;  /* out (QS_TRAJ_TIME_KERNELS): summed fused-gate kernel time */
     int64_t gate_kernel_launches; /* out (QS_TRAJ_TIME_KERNELS): launches timed */
     int64_t gate_k_launches[6];   /* out: fused-gate launches by width k = 1..5 (index k) */
+    int64_t zero_start_sweeps;    /* out: gate sweeps that began from |0...0> written on chip and
+                                     read no state (one write of the state instead of a read and
+                                     a write); counted among gate_sweeps */
 } qs_traj_result;
 
 /* ---- state lifecycle ---------------------------------------------------- */

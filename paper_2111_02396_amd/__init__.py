@@ -69,7 +69,7 @@ class QsTrajResult(ctypes.Structure):
                 ("final_state", ctypes.c_void_p), ("sweeps", ctypes.c_int64),
                 ("gate_sweeps", ctypes.c_int64), ("host_seconds", ctypes.c_double),
                 ("gate_kernel_ms", ctypes.c_double), ("gate_kernel_launches", ctypes.c_int64),
-                ("gate_k_launches", ctypes.c_int64 * 6)]
+                ("gate_k_launches", ctypes.c_int64 * 6), ("zero_start_sweeps", ctypes.c_int64)]
 
 
 class QsBatchItem(ctypes.Structure):
@@ -310,6 +310,7 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
         "gate_kernel_ms": res.gate_kernel_ms,
         "gate_kernel_launches": res.gate_kernel_launches,
         "gate_k_launches": [int(x) for x in res.gate_k_launches],
+        "zero_start_sweeps": res.zero_start_sweeps,
     }
     if record_choices:
         out["choices"] = choices[:n_traj * nch].reshape(n_traj, nch)

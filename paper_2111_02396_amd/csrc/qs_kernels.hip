@@ -915,24 +915,34 @@ __device__ __forceinline__ double wave_inclusive_scan(double x) {
 __global__ __launch_bounds__(kScanThreads) void sample_scan(const double *__restrict__ sums,
                                                             int64_t nb, double *__restrict__ incl,
                                                             double *__restrict__ norm) {
+    // Rounds of kScanThreads consecutive block sums (coalesced loads, the next
+    // round's issued before this round's scan): wavefront scan, the
+    // wavefronts' totals added in order, and a carry that every work-item
+    // updates identically.
     __shared__ double wave_tot[kScanThreads / 64];
-    const int64_t chunk = (nb + kScanThreads - 1) / kScanThreads;
-    const int64_t lo = int64_t(threadIdx.x) * chunk;
-    const int64_t hi = lo + chunk < nb ? lo + chunk : nb;
-    double s = 0.0;
-    for (int64_t b = lo; b < hi; ++b) s += sums[b];
-    const double inc = wave_inclusive_scan(s);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 63) wave_tot[wave] = inc;
-    __syncthreads();
-    double before = 0.0;
-    for (int w = 0; w < wave; ++w) before += wave_tot[w];
-    if (threadIdx.x == kScanThreads - 1) *norm = before + inc;
-    double run = before + inc - s;  // exclusive prefix of this chunk
-    for (int64_t b = lo; b < hi; ++b) {
-        run += sums[b];
-        incl[b] = run;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int64_t rounds = (nb + kScanThreads - 1) / kScanThreads;
+    double carry = 0.0;
+    double x_next = t < nb ? sums[t] : 0.0;
+    for (int64_t r = 0; r < rounds; ++r) {
+        const double x = x_next;
+        const int64_t i = r * kScanThreads + t;
+        x_next = i + kScanThreads < nb ? sums[i + kScanThreads] : 0.0;
+        const double inc = wave_inclusive_scan(x);
+        if (lane == 63) wave_tot[wave] = inc;
+        __syncthreads();
+        double before = carry, total = carry;
+#pragma unroll
+        for (int w = 0; w < kScanThreads / 64; ++w) {
+            const double v = wave_tot[w];
+            if (w < wave) before += v;
+            total += v;
+        }
+        if (i < nb) incl[i] = before + inc;
+        carry = total;
+        __syncthreads();
     }
+    if (t == 0) *norm = carry;
 }
 
 // One wavefront per sample: find the block by binary search over the block
@@ -951,11 +961,30 @@ __global__ __launch_bounds__(kBlock) void sample_draw(const float2 *__restrict__
     if (s >= n_samples) return;  // uniform over the wavefront
     const double N = *norm;
     const double target = philox_uniform(seed, uint32_t(s), traj, circ, kStreamMeasure) * N;
-    // smallest block b with target < incl[b]
+    // smallest block b with target < incl[b] (nb if none): 64-way search, the
+    // lanes probe evenly spaced entries and a ballot keeps the first passing
+    // interval.  Invariant: the answer lies in [lo, hi], and hi passes or is nb.
     int64_t lo = 0, hi = nb;
     while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (target < incl[mid]) hi = mid; else lo = mid + 1;
+        const int64_t span = hi - lo;
+        const int64_t step = span <= 64 ? 1 : (span + 63) / 64;
+        int64_t probe = lo + int64_t(lane + 1) * step - 1;
+        if (probe > hi - 1) probe = hi - 1;
+        const bool pass = target < incl[probe];
+        const uint64_t mask = __ballot(pass);
+        if (mask == 0) {  // every probe up to hi - 1 fails
+            lo = hi;
+            break;
+        }
+        const int L = __ffsll((unsigned long long)mask) - 1;
+        const int64_t pL = __shfl(probe, L, 64);
+        const int64_t pprev = L > 0 ? __shfl(probe, L - 1, 64) : lo - 1;
+        if (step == 1) {
+            lo = pL;
+            break;
+        }
+        lo = pprev + 1;
+        hi = pL;
     }
     uint64_t x;
     if (lo >= nb) {
