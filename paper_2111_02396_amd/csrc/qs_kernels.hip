@@ -117,6 +117,16 @@ __global__ __launch_bounds__(kBlock) void apply_direct(float2 *__restrict__ amp,
 
 __host__ __device__ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
+// Issue priority from the batches a wavefront still has to do in this gate:
+// the arbiter favours older wavefronts, so without this the younger ones
+// finish a gate late and the rest of the workgroup idles at the barrier.
+__device__ __forceinline__ void prio_for_remaining(int remaining) {
+    if (remaining >= 4) __builtin_amdgcn_s_setprio(3);
+    else if (remaining == 3) __builtin_amdgcn_s_setprio(2);
+    else if (remaining == 2) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 // ---- LDS layout of a tile
 // Gates read and write a tile in LDS one 64-lane instruction at a time; the
 // lanes of an instruction span a few group bits and target bits of the
@@ -227,6 +237,7 @@ __device__ __forceinline__ void tile_gate_small(float2 *__restrict__ sd, const f
 #pragma unroll
     for (int j = 0; j < D; ++j) v[j] = sd[lb ^ off[j]];
     for (int it = 0; it < iters; ++it) {
+        prio_for_remaining(iters - it);
         const int itn = it + 1 < iters ? it + 1 : it;
         const int lbn = lane_part ^ L::map(spread_index<K, int>((wave << 6) | (itn << NB), lt));
         float2 w[D];
@@ -243,6 +254,7 @@ __device__ __forceinline__ void tile_gate_small(float2 *__restrict__ sd, const f
 #pragma unroll
         for (int j = 0; j < D; ++j) v[j] = w[j];
     }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -321,6 +333,7 @@ __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const f
 #pragma unroll
     for (int s = 0; s < 4; ++s) v[s] = lds_get(sd, lin ^ (uin[s] ^ ub));
     for (int it = 0; it < iters; ++it) {
+        prio_for_remaining(iters - it);
         const int itn = it + 1 < iters ? it + 1 : it;
         const int ubn = 8 * L::map(spread_index<4, int>((wave + W * itn) << 4, lt));
         float2 w[4];
@@ -340,6 +353,7 @@ __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const f
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = w[s];
     }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 // 16 groups per wavefront iteration; the accumulator rows 4q + r give lane
@@ -368,6 +382,7 @@ __device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const f
 #pragma unroll
     for (int s = 0; s < 4; ++s) v[s] = lds_getf(sd, lin ^ (uin[s] ^ ub));
     for (int it = 0; it < iters; ++it) {
+        prio_for_remaining(iters - it);
         const int itn = it + 1 < iters ? it + 1 : it;
         const int ubn = 8 * L::map(spread_index<3, int>((wave + W * itn) << 4, lt));
         float w[4];
@@ -382,6 +397,7 @@ __device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const f
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = w[s];
     }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 // Tiled path: persistent workgroups stage every gate matrix of the launch in
