@@ -931,34 +931,40 @@ __device__ __forceinline__ double wave_inclusive_scan(double x) {
 __global__ __launch_bounds__(kScanThreads) void sample_scan(const double *__restrict__ sums,
                                                             int64_t nb, double *__restrict__ incl,
                                                             double *__restrict__ norm) {
-    // Rounds of kScanThreads consecutive block sums (coalesced loads, the next
-    // round's issued before this round's scan): wavefront scan, the
-    // wavefronts' totals added in order, and a carry that every work-item
-    // updates identically.
+    // Each work-item owns a contiguous chunk of block sums, read in groups of
+    // eight independent loads: chunk total (in index order), one workgroup
+    // scan of the totals (wavefronts in order), then the chunk's running
+    // prefix from its exclusive start.
     __shared__ double wave_tot[kScanThreads / 64];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const int64_t rounds = (nb + kScanThreads - 1) / kScanThreads;
-    double carry = 0.0;
-    double x_next = t < nb ? sums[t] : 0.0;
-    for (int64_t r = 0; r < rounds; ++r) {
-        const double x = x_next;
-        const int64_t i = r * kScanThreads + t;
-        x_next = i + kScanThreads < nb ? sums[i + kScanThreads] : 0.0;
-        const double inc = wave_inclusive_scan(x);
-        if (lane == 63) wave_tot[wave] = inc;
-        __syncthreads();
-        double before = carry, total = carry;
+    const int64_t chunk = (nb + kScanThreads - 1) / kScanThreads;
+    const int64_t lo = int64_t(t) * chunk;
+    const int64_t hi = lo + chunk < nb ? lo + chunk : nb;
+    double tot = 0.0;
+    for (int64_t b = lo; b < hi; b += 8) {
+        double v[8];
 #pragma unroll
-        for (int w = 0; w < kScanThreads / 64; ++w) {
-            const double v = wave_tot[w];
-            if (w < wave) before += v;
-            total += v;
-        }
-        if (i < nb) incl[i] = before + inc;
-        carry = total;
-        __syncthreads();
+        for (int j = 0; j < 8; ++j) v[j] = b + j < hi ? sums[b + j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) tot += v[j];
     }
-    if (t == 0) *norm = carry;
+    const double inc = wave_inclusive_scan(tot);
+    if (lane == 63) wave_tot[wave] = inc;
+    __syncthreads();
+    double before = 0.0;
+    for (int w = 0; w < wave; ++w) before += wave_tot[w];
+    if (t == kScanThreads - 1) *norm = before + inc;
+    double run = before + (inc - tot);  // exclusive prefix of this chunk
+    for (int64_t b = lo; b < hi; b += 8) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = b + j < hi ? sums[b + j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            run += v[j];
+            if (b + j < hi) incl[b + j] = run;
+        }
+    }
 }
 
 // One wavefront per sample: find the block by binary search over the block

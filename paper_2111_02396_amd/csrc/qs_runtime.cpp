@@ -816,10 +816,17 @@ void build_block(const CircuitModel &m, const std::vector<int> &members,
 
 // Event pairs around kernel launches, harvested lazily so the host never
 // waits on recent work.
+// HIP-event timing of the fused-gate sweeps.  One event pair brackets a run
+// of sweep launches issued back to back (a segment's units); the run's time is
+// divided over its launches, so the per-launch figure carries no event
+// overhead of its own.  A bracket is closed before any other kernel is
+// launched.  A ring of brackets is harvested as it wraps.
 struct KernelTimer {
     std::vector<hipEvent_t> ev;
-    std::vector<char> live;
+    std::vector<int> launches;  // per bracket: 0 = not pending
     int pos = 0;
+    bool open_now = false;
+    int cur = 0;
     double total_ms = 0.0;
     int64_t count = 0;
 
@@ -828,35 +835,45 @@ struct KernelTimer {
     }
     qs_status init(qs_state s, int cap) {
         ev.assign(size_t(2) * cap, nullptr);
-        live.assign(cap, 0);
+        launches.assign(cap, 0);
         // timing only: no system-scope fence (with one, every record writes
         // back and invalidates the L2, which costs the timed sweeps ~10 %)
         for (auto &e : ev) QS_HIP(s, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         return QS_OK;
     }
     qs_status harvest(qs_state s, int slot) {
-        if (!live[slot]) return QS_OK;
+        if (!launches[slot]) return QS_OK;
         QS_HIP(s, hipEventSynchronize(ev[2 * slot + 1]));
         float ms = 0.f;
         QS_HIP(s, hipEventElapsedTime(&ms, ev[2 * slot], ev[2 * slot + 1]));
         total_ms += ms;
-        ++count;
-        live[slot] = 0;
+        count += launches[slot];
+        launches[slot] = 0;
         return QS_OK;
     }
-    qs_status before(qs_state s) {
+    // before a sweep launch
+    qs_status open(qs_state s) {
+        if (open_now) return QS_OK;
         QS_CHECK(harvest(s, pos));
         QS_HIP(s, hipEventRecord(ev[2 * pos], s->st));
+        open_now = true;
+        cur = 0;
         return QS_OK;
     }
-    qs_status after(qs_state s) {
+    // after a sweep launch
+    void launched() { ++cur; }
+    // before any other kernel, and at the end of a run of sweeps
+    qs_status close(qs_state s) {
+        if (!open_now) return QS_OK;
         QS_HIP(s, hipEventRecord(ev[2 * pos + 1], s->st));
-        live[pos] = 1;
-        pos = (pos + 1) % int(live.size());
+        launches[pos] = cur;  // a bracket with no launches is never harvested
+        pos = (pos + 1) % int(launches.size());
+        open_now = false;
         return QS_OK;
     }
     qs_status finish(qs_state s) {
-        for (int i = 0; i < int(live.size()); ++i) QS_CHECK(harvest(s, i));
+        QS_CHECK(close(s));
+        for (int i = 0; i < int(launches.size()); ++i) QS_CHECK(harvest(s, i));
         return QS_OK;
     }
 };
@@ -1089,6 +1106,7 @@ struct Runner {
     qs_status settle_reset() {
         if (!pending_reset) return QS_OK;
         pending_reset = false;
+        if (timing) QS_CHECK(timer.close(s));
         QS_HIP(s, qs::launch_set_basis(s->amp, s->n, 0, s->st));
         return QS_OK;
     }
@@ -1102,6 +1120,7 @@ struct Runner {
             sel.launched = true;
         }
         for (const Unit &x : units) QS_CHECK(launch_unit(x));
+        if (timing) QS_CHECK(timer.close(s));
         units.clear();
         return QS_OK;
     }
@@ -1133,13 +1152,14 @@ struct Runner {
             res.gate_k_launches[d->g.k]++;
         }
         a.mat_total = lofs;
-        if (timing) QS_CHECK(timer.before(s));
+        if (timing) QS_CHECK(timer.open(s));
         QS_HIP(s, qs::launch_apply_tile(s->amp, s->n, a, s->st));
-        if (timing) QS_CHECK(timer.after(s));
+        if (timing) timer.launched();
         res.sweeps++;
         res.gate_sweeps++;
         log_norm_bound += lb;
         if (log_norm_bound < kRenormLogThreshold) {
+            if (timing) QS_CHECK(timer.close(s));
             QS_CHECK(renormalize_now(s));
             res.sweeps += 2;
             log_norm_bound = 0.0;
@@ -1206,9 +1226,12 @@ struct Runner {
             return launch_block(sc);
         }
         if (d.identity) return QS_OK;
-        if (timing) QS_CHECK(timer.before(s));
+        if (timing) QS_CHECK(timer.open(s));
         QS_HIP(s, qs::launch_apply_gate(s->amp, s->n, d.g, d.dev, s->st));
-        if (timing) QS_CHECK(timer.after(s));
+        if (timing) {
+            timer.launched();
+            QS_CHECK(timer.close(s));
+        }
         res.sweeps++;
         res.gate_sweeps++;
         res.gate_k_launches[d.g.k]++;
