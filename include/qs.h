@@ -103,7 +103,7 @@ typedef struct {
     int32_t tile_bits;     /* LDS tile sweeps: fused gates whose qubits fit a tile of this
                               many index bits (bits 0..5 always included) share one pass
                               over the state; 0 = library default (13), 1 = off (one pass
-                              per fused gate), otherwise 10..13 */
+                              per fused gate), otherwise 10..14 */
     int32_t n_samples;     /* measurement samples per trajectory (>= 0) */
     const double *p0to1;   /* per-qubit readout P(read 1 | state 0), host, or NULL */
     const double *p1to0;   /* per-qubit readout P(read 0 | state 1), host, or NULL */

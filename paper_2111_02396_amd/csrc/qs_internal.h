@@ -40,7 +40,8 @@ struct TargetArgs {
 // matrices (2^k x 2^k complex64, rows/columns in lt order) read from device
 // address `mat` (16-byte aligned) and, for k >= 3, staged in LDS at float2
 // offset `lofs` (even) of a region of mat_total entries.
-constexpr int kMaxTileBits = 13;
+constexpr int kMaxTileBits = 14;
+constexpr int kDefaultTileBits = 13;  // tile sweeps when the caller asks for the default
 constexpr int kMaxTileGates = 48;
 constexpr int kTileMinQubits = 10;
 constexpr int kTileMatBudget = 4096;  // float2 of matrices staged per launch (32 KiB)

@@ -1138,12 +1138,12 @@ template <int TB, typename Idx>
 hipError_t tile_launch_k(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
     bool k5 = false;
     for (int gi = 0; gi < a.n_gates; ++gi) k5 |= a.g[gi].k == 5;
-    // 2^13-amplitude tiles (64 KiB) leave room for two or three workgroups per
-    // CU; 512 work-items each (two wavefronts per SIMD per group) keep four or
-    // more wavefronts per SIMD to hide LDS and MFMA latency.  Smaller tiles
-    // fit more workgroups and do better with 256 (measured on the 24-qubit
-    // noisy grid).
-    constexpr int NT = TB >= 13 ? 512 : kBlock;
+    // Four wavefronts per SIMD hide the LDS and MFMA latency: a 2^14-amplitude
+    // tile (128 KiB) leaves room for one workgroup per CU, so it runs 1024
+    // work-items; 2^13 (64 KiB) for two, with 512 each.  Smaller tiles fit
+    // more workgroups and do better with 256 (measured on the 24-qubit noisy
+    // grid).
+    constexpr int NT = TB >= 14 ? 1024 : (TB >= 13 ? 512 : kBlock);
     return k5 ? tile_launch<TB, Idx, true, NT>(amp, n, a, st) : tile_launch<TB, Idx, false, NT>(amp, n, a, st);
 }
 
@@ -1154,6 +1154,7 @@ hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st)
         case 11: return tile_launch_k<11, Idx>(amp, n, a, st);
         case 12: return tile_launch_k<12, Idx>(amp, n, a, st);
         case 13: return tile_launch_k<13, Idx>(amp, n, a, st);
+        case 14: return tile_launch_k<14, Idx>(amp, n, a, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -178,11 +178,61 @@ std::vector<Block> fuse_greedy(int n_qubits, const std::vector<PlanOp> &ops, int
         std::sort(qs, qs + nq);
         b.k = nq;
         for (int i = 0; i < nq; ++i) b.q[i] = qs[i];
-        if (op_block)
-            for (int o : b.ops) (*op_block)[o] = int(blocks.size());
         blocks.push_back(std::move(b));
     }
+    merge_subset_blocks(blocks);
+    if (op_block)
+        for (size_t bi = 0; bi < blocks.size(); ++bi)
+            for (int o : blocks[bi].ops) (*op_block)[o] = int(bi);
     return blocks;
+}
+
+void merge_subset_blocks(std::vector<Block> &blocks) {
+    auto touches = [](const Block &a, const Block &b) {
+        for (int i = 0; i < a.k; ++i)
+            for (int j = 0; j < b.k; ++j)
+                if (a.q[i] == b.q[j]) return true;
+        return false;
+    };
+    auto subset = [](const Block &a, const Block &b) {  // qubits(a) within qubits(b)
+        for (int i = 0; i < a.k; ++i) {
+            bool found = false;
+            for (int j = 0; j < b.k; ++j) found |= a.q[i] == b.q[j];
+            if (!found) return false;
+        }
+        return true;
+    };
+    auto fold = [&](size_t from, size_t into) {
+        Block &dst = blocks[into];
+        dst.ops.insert(dst.ops.end(), blocks[from].ops.begin(), blocks[from].ops.end());
+        std::sort(dst.ops.begin(), dst.ops.end());
+        blocks.erase(blocks.begin() + std::ptrdiff_t(from));
+    };
+    size_t i = 0;
+    while (i < blocks.size()) {
+        bool merged = false;
+        // the next block that shares a qubit with block i
+        for (size_t j = i + 1; j < blocks.size(); ++j) {
+            if (!touches(blocks[j], blocks[i])) continue;
+            if (subset(blocks[i], blocks[j])) {
+                fold(i, j);
+                merged = true;
+            }
+            break;
+        }
+        if (!merged) {
+            // the previous block that shares a qubit with block i
+            for (size_t j = i; j-- > 0;) {
+                if (!touches(blocks[j], blocks[i])) continue;
+                if (subset(blocks[i], blocks[j])) {
+                    fold(i, j);
+                    merged = true;
+                }
+                break;
+            }
+        }
+        if (!merged) ++i;  // after a fold, index i holds the next block
+    }
 }
 
 int union_qubits(const std::vector<int> &members, const std::vector<PlanOp> &ops, int *q_out) {

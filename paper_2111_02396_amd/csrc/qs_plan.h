@@ -42,8 +42,16 @@ void kraus_bounds(int k, int n_kraus, const cd *kraus, double *pbar, bool *mixtu
 // Operations wider than max_fuse form a block of their own.  Condition (a)
 // makes "apply the blocks in creation order" equal to "apply the operations
 // in time order".
+// After the greedy pass, merge_subset_blocks folds a block into the nearest
+// later (else earlier) block that shares a qubit with it whenever its qubits
+// are a subset of that block's: no block in between touches those qubits, so
+// the union of the two blocks' operations in time order keeps every qubit's
+// order and the block order stays valid (also restricted to any range of
+// operations).  The greedy rule otherwise leaves one-qubit blocks for a
+// qubit's first operations when the gate that follows them is not yet ready.
 std::vector<Block> fuse_greedy(int n_qubits, const std::vector<PlanOp> &ops, int max_fuse,
                                std::vector<int> *op_block = nullptr);
+void merge_subset_blocks(std::vector<Block> &blocks);
 
 // Fused matrix of a subset of operations (time-ordered indices) acting on
 // the ascending qubit set q[0..k-1]: the product of the embedded operator

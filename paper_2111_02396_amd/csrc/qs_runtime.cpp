@@ -1059,7 +1059,7 @@ struct Runner {
     }
 
     void plan_sweeps() {
-        const int T = p.tile_bits == 0 ? qs::kMaxTileBits : p.tile_bits;
+        const int T = p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits;
         sweeps.clear();
         layouts.clear();
         if (T >= 10 && m.n >= qs::kTileMinQubits) {
@@ -1510,7 +1510,7 @@ qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_par
         return fail(QS_ERR_INVALID_ARGUMENT, "max_fuse outside 0..5");
     if (!(p->tile_bits == 0 || p->tile_bits == 1 ||
           (p->tile_bits >= 10 && p->tile_bits <= qs::kMaxTileBits)))
-        return fail(QS_ERR_INVALID_ARGUMENT, "tile_bits must be 0, 1 or 10..13");
+        return fail(QS_ERR_INVALID_ARGUMENT, "tile_bits must be 0, 1 or 10..14");
     if (p->n_samples < 0) return fail(QS_ERR_INVALID_ARGUMENT, "negative sample count");
     if (int64_t(p->n_samples) * int64_t(s->n) > (int64_t(1) << 32))
         return fail(QS_ERR_INVALID_ARGUMENT, "readout counter would overflow");
@@ -1568,13 +1568,13 @@ qs_status qs_sweep_plan(const qs_circuit *c, int max_fuse, int tile_bits, int32_
     if (max_fuse < 1 || max_fuse > qs::kMaxGateQubits)
         return fail(QS_ERR_INVALID_ARGUMENT, "max_fuse outside 1..5");
     if (!(tile_bits == 0 || tile_bits == 1 || (tile_bits >= 10 && tile_bits <= qs::kMaxTileBits)))
-        return fail(QS_ERR_INVALID_ARGUMENT, "tile_bits must be 0, 1 or 10..13");
+        return fail(QS_ERR_INVALID_ARGUMENT, "tile_bits must be 0, 1 or 10..14");
     if (c->n_qubits < 1 || c->n_qubits > qs::kMaxQubits)
         return fail(QS_ERR_INVALID_ARGUMENT, "n out of range");
     CircuitModel m;
     QS_CHECK(build_model(c, m));
     const auto blocks = qs::fuse_greedy(m.n, m.ops, max_fuse);
-    const int T = tile_bits == 0 ? qs::kMaxTileBits : tile_bits;
+    const int T = tile_bits == 0 ? qs::kDefaultTileBits : tile_bits;
     std::vector<qs::Sweep> sw;
     if (T >= 10 && m.n >= qs::kTileMinQubits) {
         sw = qs::group_sweeps(m.n, blocks, std::min(T, m.n), 6, qs::kMaxTileGates, qs::kTileMatBudget,
@@ -1767,7 +1767,7 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
                         in[q] = 1;
                         ++cnt;
                     }
-                if (cnt > qs::kMaxTileBits) {
+                if (cnt > qs::kBatchLdsQubits) {  // the tile must fit the LDS state area
                     X.status = QS_ERR_NOT_SUPPORTED;
                     X.error = "block too wide for a tile";
                     return;

@@ -269,7 +269,7 @@ def test_torch_buffer_and_stream(qs, orc):
     assert rel_l2(got, orc.simulate(c)) < AMP_TOL
 
 
-@pytest.mark.parametrize("tile_bits", [1, 10, 12, 13])
+@pytest.mark.parametrize("tile_bits", [1, 10, 12, 13, 14])
 @pytest.mark.parametrize("max_fuse", [2, 4])
 def test_driver_tile_sweeps_16q(qs, orc, tile_bits, max_fuse):
     """16 qubits: tiles narrower than the state, fused blocks regrouped into
@@ -294,9 +294,10 @@ def test_driver_tile_sweeps_16q(qs, orc, tile_bits, max_fuse):
     assert ties <= 1
 
 
-def test_driver_noiseless_grid_matches_oracle_20q(qs, orc):
+@pytest.mark.parametrize("tile_bits", [0, 14])
+def test_driver_noiseless_grid_matches_oracle_20q(qs, orc, tile_bits):
     c = W.grid_circuit(4, 5, 10, seed=3)
-    got = _driver(qs, c, 1, 0, n_samples=200, return_state=True)
+    got = _driver(qs, c, 1, 0, n_samples=200, return_state=True, tile_bits=tile_bits)
     ref = orc.run_trajectory(c, 0, n_samples=200, return_state=True)
     assert rel_l2(got["state"], ref["state"]) < AMP_TOL
     mism = np.nonzero(got["samples"][0] != ref["samples"])[0]

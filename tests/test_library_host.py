@@ -180,4 +180,17 @@ def test_sweep_grouping_cuts_passes(lib):
     c = W.grid24_workload().circuit.gates_only()
     ns_off, *_ = lib.qs_sweep_plan(c, 4, 1)
     ns_13, *_ = lib.qs_sweep_plan(c, 4, 13)
-    assert ns_13 * 3 < ns_off
+    assert ns_13 * 2.5 < ns_off
+
+
+def test_fusion_merges_subset_blocks(lib):
+    """No block of the default grid plan is a qubit subset of the nearest
+    block sharing a qubit with it (such blocks are folded in), and the plan
+    still multiplies out to the circuit."""
+    c = W.grid_circuit(2, 4, 6, seed=3)
+    blocks = _check_plan(lib, c, 4)
+    assert all(len(t) > 1 for t, _ in blocks)
+    for i, (ti, _) in enumerate(blocks):
+        later = [tj for tj, _ in blocks[i + 1:] if set(tj) & set(ti)]
+        if later:
+            assert not set(ti) <= set(later[0])
