@@ -181,6 +181,7 @@ std::vector<Block> fuse_greedy(int n_qubits, const std::vector<PlanOp> &ops, int
         blocks.push_back(std::move(b));
     }
     merge_subset_blocks(blocks);
+    merge_cheaper_blocks(blocks, std::max(max_fuse, 1));
     if (op_block)
         for (size_t bi = 0; bi < blocks.size(); ++bi)
             for (int o : blocks[bi].ops) (*op_block)[o] = int(bi);
@@ -393,6 +394,64 @@ std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, 
         out.push_back(std::move(sw));
     }
     return out;
+}
+
+double block_cost(int k) {
+    // relative cost of one block applied to a tile in LDS by width (measured
+    // on gfx950 with 13-bit tiles: barrier and read latency make one-qubit
+    // blocks cost about 40 % of a four-qubit one)
+    static const double c[6] = {0.0, 7.0, 8.5, 12.6, 17.6, 45.0};
+    return k >= 1 && k <= 5 ? c[k] : 1e9;
+}
+
+void merge_cheaper_blocks(std::vector<Block> &blocks, int max_fuse) {
+    constexpr size_t kWindow = 8;  // blocks looked ahead of each block
+    auto shares = [](const Block &a, const Block &b) {
+        for (int i = 0; i < a.k; ++i)
+            for (int j = 0; j < b.k; ++j)
+                if (a.q[i] == b.q[j]) return true;
+        return false;
+    };
+    auto unite = [](const Block &a, const Block &b, int *q) {
+        int nq = 0;
+        for (int i = 0; i < a.k; ++i) q[nq++] = a.q[i];
+        for (int j = 0; j < b.k; ++j) {
+            bool seen = false;
+            for (int i = 0; i < a.k; ++i) seen |= b.q[j] == a.q[i];
+            if (!seen) q[nq++] = b.q[j];
+        }
+        std::sort(q, q + nq);
+        return nq;
+    };
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        for (size_t i = 0; i < blocks.size() && !changed; ++i) {
+            for (size_t j = i + 1; j < blocks.size() && j <= i + kWindow && !changed; ++j) {
+                if (!shares(blocks[i], blocks[j])) continue;
+                int q[10];
+                const int nq = unite(blocks[i], blocks[j], q);
+                if (nq > max_fuse || nq > 5) continue;
+                if (!(block_cost(nq) < block_cost(blocks[i].k) + block_cost(blocks[j].k))) continue;
+                // blocks strictly between i and j must not touch i's qubits (the
+                // merged block takes j's place) or j's (it takes i's place)
+                bool clear_i = true, clear_j = true;
+                for (size_t z = i + 1; z < j; ++z) {
+                    clear_i = clear_i && !shares(blocks[z], blocks[i]);
+                    clear_j = clear_j && !shares(blocks[z], blocks[j]);
+                }
+                if (!clear_i && !clear_j) continue;
+                const size_t keep = clear_i ? j : i, drop = clear_i ? i : j;
+                Block &dst = blocks[keep];
+                dst.ops.insert(dst.ops.end(), blocks[drop].ops.begin(), blocks[drop].ops.end());
+                std::sort(dst.ops.begin(), dst.ops.end());
+                dst.k = nq;
+                for (int t = 0; t < 5; ++t) dst.q[t] = t < nq ? q[t] : 0;
+                blocks.erase(blocks.begin() + std::ptrdiff_t(drop));
+                changed = true;
+            }
+        }
+    }
 }
 
 }  // namespace qs

@@ -53,6 +53,14 @@ std::vector<Block> fuse_greedy(int n_qubits, const std::vector<PlanOp> &ops, int
                                std::vector<int> *op_block = nullptr);
 void merge_subset_blocks(std::vector<Block> &blocks);
 
+// Then merge_cheaper_blocks fuses two blocks that share a qubit (the later
+// within a small window) into one of at most max_fuse qubits when the wider
+// block costs less than the two (block_cost, by width) and the blocks in
+// between touch neither the earlier block's qubits (the union takes the later
+// block's place) or not the later one's (it takes the earlier one's place).
+double block_cost(int k);
+void merge_cheaper_blocks(std::vector<Block> &blocks, int max_fuse);
+
 // Fused matrix of a subset of operations (time-ordered indices) acting on
 // the ascending qubit set q[0..k-1]: the product of the embedded operator
 // matrices, latest on the left.  mats[o] = matrix of op o (its own target
