@@ -312,7 +312,7 @@ void to_ascending_order(int k, const int *t, const cd *in, cd *out, int *t_sorte
 
 std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, int max_bits,
                                 int low_bits, int max_blocks, int mat_budget,
-                                const int *slot_per_k) {
+                                const int *slot_per_k, bool search) {
     const int nb = int(blocks.size());
     // predecessor counts and successor lists from per-qubit chains
     std::vector<int> last(n_qubits, -1);
@@ -332,65 +332,110 @@ std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, 
     std::vector<int> ready;
     for (int b = 0; b < nb; ++b)
         if (npred[b] == 0) ready.push_back(b);
-    std::vector<Sweep> out;
-    int done = 0;
     const int low = std::min(low_bits, n_qubits);
-    while (done < nb) {
-        Sweep sw;
-        std::vector<char> in(n_qubits, 0);
+
+    // Fill one sweep greedily: repeatedly take the ready block that adds the
+    // fewest new bits (ties: earliest), starting with `first` (if >= 0).
+    // Works on copies of the ready list and predecessor counts; returns the
+    // blocks taken in order and their total cost.
+    struct Fill {
+        std::vector<int> taken;
+        std::vector<char> in;
+        double cost = 0.0;
+    };
+    auto fill = [&](int first, std::vector<int> rdy, std::vector<int> &np) {
+        Fill f;
+        f.in.assign(n_qubits, 0);
         int nbits = 0;
         for (int q = 0; q < low; ++q) {
-            in[q] = 1;
+            f.in[q] = 1;
             ++nbits;
         }
         int mats = 0;
-        for (;;) {
-            int best = -1, best_pos = -1, best_growth = 1 << 30;
-            for (int i = 0; i < int(ready.size()); ++i) {
-                const int b = ready[i];
-                int growth = 0;
-                for (int j = 0; j < blocks[b].k; ++j) growth += in[blocks[b].q[j]] ? 0 : 1;
-                if (nbits + growth > max_bits) continue;
-                if (mats + slot_per_k[blocks[b].k] > mat_budget) continue;
-                if (growth < best_growth || (growth == best_growth && b < best)) {
-                    best = b;
-                    best_pos = i;
-                    best_growth = growth;
-                }
-            }
-            if (best < 0 || int(sw.blocks.size()) >= max_blocks) break;
-            ready.erase(ready.begin() + best_pos);
-            sw.blocks.push_back(best);
-            mats += slot_per_k[blocks[best].k];
-            for (int j = 0; j < blocks[best].k; ++j) {
-                const int q = blocks[best].q[j];
-                if (!in[q]) {
-                    in[q] = 1;
+        auto take = [&](int pos) {
+            const int b = rdy[pos];
+            rdy.erase(rdy.begin() + pos);
+            f.taken.push_back(b);
+            f.cost += block_cost(blocks[b].k);
+            mats += slot_per_k[blocks[b].k];
+            for (int j = 0; j < blocks[b].k; ++j) {
+                const int q = blocks[b].q[j];
+                if (!f.in[q]) {
+                    f.in[q] = 1;
                     ++nbits;
                 }
             }
-            ++done;
-            for (int s : succ[best])
-                if (--npred[s] == 0) ready.push_back(s);
+            for (int s2 : succ[b])
+                if (--np[s2] == 0) rdy.push_back(s2);
+        };
+        auto fits = [&](int b, int *growth) {
+            int g = 0;
+            for (int j = 0; j < blocks[b].k; ++j) g += f.in[blocks[b].q[j]] ? 0 : 1;
+            *growth = g;
+            return nbits + g <= max_bits && mats + slot_per_k[blocks[b].k] <= mat_budget;
+        };
+        if (first >= 0) {
+            int g;
+            for (int i = 0; i < int(rdy.size()); ++i)
+                if (rdy[i] == first) {
+                    if (fits(first, &g)) take(i);
+                    break;
+                }
         }
-        if (sw.blocks.empty()) {
+        for (;;) {
+            if (int(f.taken.size()) >= max_blocks) break;
+            int best = -1, best_pos = -1, best_growth = 1 << 30;
+            for (int i = 0; i < int(rdy.size()); ++i) {
+                int g;
+                if (!fits(rdy[i], &g)) continue;
+                if (g < best_growth || (g == best_growth && rdy[i] < best)) {
+                    best = rdy[i];
+                    best_pos = i;
+                    best_growth = g;
+                }
+            }
+            if (best < 0) break;
+            take(best_pos);
+        }
+        return f;
+    };
+
+    std::vector<Sweep> out;
+    int done = 0;
+    while (done < nb) {
+        // every ready block as the first pick (plus the plain greedy); keep
+        // the fill that absorbs the most block cost
+        Fill best;
+        best.cost = -1.0;
+        std::vector<int> cand;
+        if (search) cand = ready;
+        cand.push_back(-1);
+        for (int c : cand) {
+            std::vector<int> np = npred;
+            Fill f = fill(c, ready, np);
+            if (f.cost > best.cost + 1e-9) best = std::move(f);
+        }
+        Sweep sw;
+        if (best.taken.empty()) {
             // no ready block fits even an empty tile: it gets a sweep of its own,
             // wider than max_bits (the caller applies such sweeps block by block)
-            int b = ready[0], pos = 0;
-            for (int i = 1; i < int(ready.size()); ++i)
-                if (ready[i] < b) {
-                    b = ready[i];
-                    pos = i;
-                }
-            ready.erase(ready.begin() + pos);
+            int b = ready[0];
+            for (int r : ready) b = std::min(b, r);
+            best.taken.push_back(b);
+            best.in.assign(n_qubits, 0);
+            for (int q = 0; q < low; ++q) best.in[q] = 1;
+            for (int j = 0; j < blocks[b].k; ++j) best.in[blocks[b].q[j]] = 1;
+        }
+        // commit: the taken blocks leave the ready list, their successors join
+        for (int b : best.taken) {
+            ready.erase(std::find(ready.begin(), ready.end(), b));
             sw.blocks.push_back(b);
-            for (int j = 0; j < blocks[b].k; ++j) in[blocks[b].q[j]] = 1;
             ++done;
-            for (int s : succ[b])
-                if (--npred[s] == 0) ready.push_back(s);
+            for (int s2 : succ[b])
+                if (--npred[s2] == 0) ready.push_back(s2);
         }
         for (int q = 0; q < n_qubits; ++q)
-            if (in[q]) sw.bits.push_back(q);
+            if (best.in[q]) sw.bits.push_back(q);
         out.push_back(std::move(sw));
     }
     return out;

@@ -90,11 +90,13 @@ struct Sweep {
 // waits for the previous block on each of its qubits): a sweep repeatedly
 // takes a ready block that adds the fewest new bits (earliest first), as
 // long as the bit budget, max_blocks and the matrix budget (the sum of
-// slot_per_k[k] over the sweep's blocks) allow.  The result, sweep by sweep, is again a valid application order.
-// A block that fits no tile of max_bits gets a sweep of its own whose bit
-// set is wider than max_bits.
+// slot_per_k[k] over the sweep's blocks) allow.  With search, every ready
+// block is also tried as the sweep's first pick and the fill that absorbs
+// the most block cost (block_cost) is kept.  The result, sweep by sweep, is
+// again a valid application order.  A block that fits no tile of max_bits
+// gets a sweep of its own whose bit set is wider than max_bits.
 std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, int max_bits,
                                 int low_bits, int max_blocks, int mat_budget,
-                                const int *slot_per_k);
+                                const int *slot_per_k, bool search = true);
 
 }  // namespace qs

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <array>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -900,9 +901,15 @@ struct Runner {
     std::vector<qs::Sweep> sweeps;
     std::vector<TileLayout> layouts;
     struct Unit {
-        int sweep;
+        const TileLayout *L;
         std::vector<const BlockDesc *> items;
     };
+    // one sweep of a segment: its layout and (block, op range) members in order
+    struct SegSweep {
+        const TileLayout *L;
+        std::vector<std::array<int, 3>> members;  // block, first op index, end op index
+    };
+    std::deque<TileLayout> seg_layouts;
     // naive mode: gate blocks per inter-channel segment
     std::vector<std::vector<BlockDesc>> naive_segments;
     std::vector<cd> tmp;
@@ -1073,32 +1080,86 @@ struct Runner {
             }
         }
         layouts.resize(sweeps.size());
-        for (size_t u = 0; u < sweeps.size(); ++u) {
-            TileLayout &L = layouts[u];
-            const auto &bits = sweeps[u].bits;
-            if (bits.empty() || int(bits.size()) > qs::kMaxTileBits) continue;
-            int maxk = 1;
-            for (int b : sweeps[u].blocks) maxk = std::max(maxk, blocks[b].k);
-            int tb = std::max<int>(int(bits.size()), std::min(qs::kMaxTileBits, std::max(10, maxk + 8)));
-            tb = std::min(tb, m.n);
-            std::vector<char> in(m.n, 0);
-            for (int q : bits) in[q] = 1;
-            int cnt = int(bits.size());
-            for (int q = 0; q < m.n && cnt < tb; ++q)
-                if (!in[q]) {
-                    in[q] = 1;
-                    ++cnt;
-                }
-            L.tb = tb;
-            int i = 0;
-            for (int q = 0; q < qs::kMaxQubits; ++q) L.local[q] = -1;
-            for (int q = 0; q < m.n; ++q)
-                if (in[q]) {
-                    L.pos[i] = q;
-                    L.local[q] = int8_t(i);
-                    ++i;
-                }
-            L.tiled = true;
+        for (size_t u = 0; u < sweeps.size(); ++u) layouts[u] = make_layout(sweeps[u], blocks);
+    }
+
+    // Tile layout of a sweep: its qubits plus the lowest others up to the tile
+    // width (at least 10 bits, and k + 8 for its widest block).
+    TileLayout make_layout(const qs::Sweep &sw, const std::vector<qs::Block> &bl) const {
+        TileLayout L;
+        const auto &bits = sw.bits;
+        if (bits.empty() || int(bits.size()) > qs::kMaxTileBits) return L;
+        int maxk = 1;
+        for (int b : sw.blocks) maxk = std::max(maxk, bl[b].k);
+        int tb = std::max<int>(int(bits.size()), std::min(qs::kMaxTileBits, std::max(10, maxk + 8)));
+        tb = std::min(tb, m.n);
+        std::vector<char> in(m.n, 0);
+        for (int q : bits) in[q] = 1;
+        int cnt = int(bits.size());
+        for (int q = 0; q < m.n && cnt < tb; ++q)
+            if (!in[q]) {
+                in[q] = 1;
+                ++cnt;
+            }
+        L.tb = tb;
+        int i = 0;
+        for (int q = 0; q < qs::kMaxQubits; ++q) L.local[q] = -1;
+        for (int q = 0; q < m.n; ++q)
+            if (in[q]) {
+                L.pos[i] = q;
+                L.local[q] = int8_t(i);
+                ++i;
+            }
+        L.tiled = true;
+        return L;
+    }
+
+    // The sweeps of the segment [seg_start, seg_end): the call's plan when the
+    // trajectory has no channel needing inner products; otherwise the blocks
+    // restricted to the segment, regrouped into sweeps of their own (reusing
+    // the whole-circuit sweeps would launch every sweep that straddles the
+    // split twice: ~6 extra sweeps per split on a 24-qubit grid).
+    void segment_sweeps(int seg_start, int seg_end, bool whole_plan, std::vector<SegSweep> &out) {
+        out.clear();
+        if (whole_plan) {
+            for (size_t u = 0; u < sweeps.size(); ++u) {
+                SegSweep ss{&layouts[u], {}};
+                for (int b : sweeps[u].blocks)
+                    ss.members.push_back({b, 0, int(blocks[b].ops.size())});
+                out.push_back(std::move(ss));
+            }
+            return;
+        }
+        std::vector<qs::Block> rb;
+        std::vector<std::array<int, 3>> orig;
+        for (size_t b = 0; b < blocks.size(); ++b) {
+            const auto &ops = blocks[b].ops;
+            const int lo = int(std::lower_bound(ops.begin(), ops.end(), seg_start) - ops.begin());
+            const int hi = int(std::lower_bound(ops.begin() + lo, ops.end(), seg_end) - ops.begin());
+            if (lo == hi) continue;
+            qs::Block r;
+            r.ops.assign(ops.begin() + lo, ops.begin() + hi);
+            r.k = qs::union_qubits(r.ops, m.ops, r.q);
+            rb.push_back(std::move(r));
+            orig.push_back({int(b), lo, hi});
+        }
+        const int T = p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits;
+        std::vector<qs::Sweep> sw;
+        if (T >= 10 && m.n >= qs::kTileMinQubits) {
+            sw = qs::group_sweeps(m.n, rb, std::min(T, m.n), 6, qs::kMaxTileGates, qs::kTileMatBudget,
+                                  tile_slots(), true);
+        } else {
+            for (size_t b = 0; b < rb.size(); ++b) {
+                qs::Sweep one;
+                one.blocks.push_back(int(b));
+                sw.push_back(std::move(one));
+            }
+        }
+        for (const auto &w : sw) {
+            seg_layouts.push_back(make_layout(w, rb));
+            SegSweep ss{&seg_layouts.back(), {}};
+            for (int b : w.blocks) ss.members.push_back(orig[b]);
+            out.push_back(std::move(ss));
         }
     }
 
@@ -1126,7 +1187,7 @@ struct Runner {
     }
 
     qs_status launch_unit(const Unit &u) {
-        const TileLayout &L = layouts[u.sweep];
+        const TileLayout &L = *u.L;
         if (!L.tiled) {
             QS_CHECK(settle_reset());
             for (const BlockDesc *d : u.items) QS_CHECK(launch_block(*d));
@@ -1310,16 +1371,20 @@ struct Runner {
         std::vector<int> sub;
         std::deque<BlockDesc> dyn;
         std::vector<Unit> units;
+        std::vector<SegSweep> seg;
+        seg_layouts.clear();
         for (;;) {
             const int seg_end = slow_idx < int(slow_ops.size()) ? slow_ops[slow_idx] : n_ops;
             dyn.clear();
             units.clear();
-            for (size_t u = 0; u < sweeps.size(); ++u) {
-                Unit unit{int(u), {}};
-                for (int b : sweeps[u].blocks) {
+            segment_sweeps(seg_start, seg_end, slow_ops.empty(), seg);
+            for (const SegSweep &ss : seg) {
+                Unit unit{ss.L, {}};
+                for (const auto &mem : ss.members) {
+                    const int b = mem[0];
                     const auto &ops = blocks[b].ops;
-                    auto lo = std::lower_bound(ops.begin(), ops.end(), seg_start);
-                    auto hi = std::lower_bound(lo, ops.end(), seg_end);
+                    auto lo = ops.begin() + mem[1];
+                    auto hi = ops.begin() + mem[2];
                     if (lo == hi) continue;
                     const bool whole = (lo == ops.begin() && hi == ops.end());
                     if (whole && !dirty[b]) {
