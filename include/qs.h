@@ -132,10 +132,12 @@ typedef struct {
 
 /* Create an n-qubit state set to |0...0>.
  * device_buf: NULL = the library allocates 8*2^n bytes; otherwise a device
- *   buffer of at least 8*2^n bytes (buf_bytes) that the caller keeps alive.
+ *   buffer of at least 8*2^n bytes (buf_bytes), 16-byte aligned (kernels move
+ *   amplitude pairs), that the caller keeps alive.
  * hip_stream: the hipStream_t to enqueue on, or NULL for the null stream.
- * Errors: INVALID_ARGUMENT (n outside 1..34, short buffer), OUT_OF_MEMORY
- * (allocation refused or free device memory below 8*2^n), DEVICE. */
+ * Errors: INVALID_ARGUMENT (n outside 1..34, short or misaligned buffer),
+ * OUT_OF_MEMORY (allocation refused or free device memory below 8*2^n),
+ * DEVICE. */
 qs_status qs_create_state(int n_qubits, void *device_buf, size_t buf_bytes, void *hip_stream,
                           qs_state *out);
 

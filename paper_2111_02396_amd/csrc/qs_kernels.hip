@@ -417,7 +417,11 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
     static_assert(TB >= 10, "the MFMA gates need at least 32 groups per tile");
     static_assert((1 << (TB - 8)) >= NT / 64, "every wavefront needs a 4-qubit batch");
     constexpr int E = 1 << TB;
-    constexpr int R = E / NT;
+    // Each work-item moves R amplitude pairs per tile: pair (t, r) holds local
+    // indices 2 t + NT 2 r + {0, 1}, which differ in local bit 0 = qubit 0, so
+    // the pair is one 16-byte load or store, and a wavefront covers two
+    // 512-byte rows.
+    constexpr int R = E / (2 * NT);
     // The tile is a static array (its LDS address is a link-time constant
     // that folds into the LDS instructions' offsets); the launch's matrices
     // follow it in dynamic LDS.
@@ -428,14 +432,14 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
     Idx off_tid = 0;
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-        if ((threadIdx.x >> b) & 1) off_tid |= Idx(1) << a.pos[b];
+        if ((threadIdx.x >> b) & 1) off_tid |= Idx(1) << a.pos[b + 1];
     Idx off_r[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         Idx o = 0;
 #pragma unroll
-        for (int b = NB; b < TB; ++b)
-            if (((r << NB) >> b) & 1) o |= Idx(1) << a.pos[b];
+        for (int b = NB + 1; b < TB; ++b)
+            if (((r << (NB + 1)) >> b) & 1) o |= Idx(1) << a.pos[b];
         off_r[r] = o;
     }
     auto tile_base = [&](Idx t) {
@@ -447,20 +451,20 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
         }
         return base + off_tid;
     };
-    // A tile's amplitudes; with init_zero the sweep starts from |0...0>
+    // A tile's amplitude pairs; with init_zero the sweep starts from |0...0>
     // (amplitude 1 at index 0) without reading the state.
-    auto fetch = [&](Idx t, float2 (&dst)[R]) {
+    auto fetch = [&](Idx t, float4 (&dst)[R]) {
         const Idx base = tile_base(t);
         if (a.init_zero) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                dst[r] = make_float2(base + off_r[r] == Idx(0) ? 1.f : 0.f, 0.f);
+                dst[r] = make_float4(base + off_r[r] == Idx(0) ? 1.f : 0.f, 0.f, 0.f, 0.f);
         } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[r] = amp[base + off_r[r]];
+            for (int r = 0; r < R; ++r) dst[r] = *reinterpret_cast<const float4 *>(amp + base + off_r[r]);
         }
     };
-    float2 v[R];
+    float4 v[R];
     fetch(tile, v);
     for (int gi = 0; gi < a.n_gates; ++gi) {
         const int k = a.g[gi].k;
@@ -481,18 +485,22 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
     // tile's gates run, instead of the stores going out in a burst at the end
     // of every tile; the wait for the prefetch at the next loop head covers
     // memory operations issued a whole gate phase earlier.
-    // LDS index of local index threadIdx.x + NT r: the map leaves r alone
-    const int tid_l = SwizzledTile::map(int(threadIdx.x));
-    float2 o[R];
+    // LDS index of local index 2 threadIdx.x + e + 2 NT r: the map leaves the
+    // r part alone and maps bit 0 to itself, so it is tid_l ^ e + (r << NB + 1)
+    const int tid_l = SwizzledTile::map(int(threadIdx.x) << 1);
+    float4 o[R];
     Idx prev_base = 0;
     auto run_tile = [&](Idx t, bool has_prev) {
         __syncthreads();  // the previous tile is out of LDS; matrices staged
 #pragma unroll
-        for (int r = 0; r < R; ++r) sd[tid_l + (r << NB)] = v[r];
+        for (int r = 0; r < R; ++r) {
+            sd[tid_l + (r << (NB + 1))] = make_float2(v[r].x, v[r].y);
+            sd[(tid_l ^ 1) + (r << (NB + 1))] = make_float2(v[r].z, v[r].w);
+        }
         const Idx base = tile_base(t);
         if (has_prev) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) amp[prev_base + off_r[r]] = o[r];
+            for (int r = 0; r < R; ++r) *reinterpret_cast<float4 *>(amp + prev_base + off_r[r]) = o[r];
         }
         const Idx next = t + gridDim.x;
         if (next < n_tiles) fetch(next, v);
@@ -520,13 +528,16 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
             __syncthreads();
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) o[r] = sd[tid_l + (r << NB)];
+        for (int r = 0; r < R; ++r) {
+            const float2 lo = sd[tid_l + (r << (NB + 1))], hi = sd[(tid_l ^ 1) + (r << (NB + 1))];
+            o[r] = make_float4(lo.x, lo.y, hi.x, hi.y);
+        }
         prev_base = base;
     };
     run_tile(tile, false);
     for (tile += gridDim.x; tile < n_tiles; tile += gridDim.x) run_tile(tile, true);
 #pragma unroll
-    for (int r = 0; r < R; ++r) amp[prev_base + off_r[r]] = o[r];
+    for (int r = 0; r < R; ++r) *reinterpret_cast<float4 *>(amp + prev_base + off_r[r]) = o[r];
 }
 
 // ---------------------------------------------------------------- branch selection
@@ -931,22 +942,28 @@ __device__ __forceinline__ double wave_inclusive_scan(double x) {
 __global__ __launch_bounds__(kScanThreads) void sample_scan(const double *__restrict__ sums,
                                                             int64_t nb, double *__restrict__ incl,
                                                             double *__restrict__ norm) {
-    // Each work-item owns a contiguous chunk of block sums, read in groups of
-    // eight independent loads: chunk total (in index order), one workgroup
-    // scan of the totals (wavefronts in order), then the chunk's running
-    // prefix from its exclusive start.
+    // Each work-item owns a contiguous chunk of block sums (nb is a power of
+    // two: chunks of nb / kScanThreads, or one sum for the first nb work-items
+    // of a small state): chunk total in index order, one workgroup scan of
+    // the totals (wavefronts in order), then the chunk's running prefix.
     __shared__ double wave_tot[kScanThreads / 64];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const int64_t chunk = (nb + kScanThreads - 1) / kScanThreads;
+    const int64_t chunk = nb >= kScanThreads ? nb / kScanThreads : 1;
     const int64_t lo = int64_t(t) * chunk;
-    const int64_t hi = lo + chunk < nb ? lo + chunk : nb;
+    const bool active = lo < nb;
     double tot = 0.0;
-    for (int64_t b = lo; b < hi; b += 8) {
-        double v[8];
+    if (active) {
+        if (chunk >= 8) {
+            for (int64_t b = lo; b < lo + chunk; b += 8) {
+                double v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = b + j < hi ? sums[b + j] : 0.0;
+                for (int j = 0; j < 8; ++j) v[j] = sums[b + j];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) tot += v[j];
+                for (int j = 0; j < 8; ++j) tot += v[j];
+            }
+        } else {
+            for (int64_t b = lo; b < lo + chunk; ++b) tot += sums[b];
+        }
     }
     const double inc = wave_inclusive_scan(tot);
     if (lane == 63) wave_tot[wave] = inc;
@@ -954,15 +971,23 @@ __global__ __launch_bounds__(kScanThreads) void sample_scan(const double *__rest
     double before = 0.0;
     for (int w = 0; w < wave; ++w) before += wave_tot[w];
     if (t == kScanThreads - 1) *norm = before + inc;
+    if (!active) return;
     double run = before + (inc - tot);  // exclusive prefix of this chunk
-    for (int64_t b = lo; b < hi; b += 8) {
-        double v[8];
+    if (chunk >= 8) {
+        for (int64_t b = lo; b < lo + chunk; b += 8) {
+            double v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = b + j < hi ? sums[b + j] : 0.0;
+            for (int j = 0; j < 8; ++j) v[j] = sums[b + j];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            run += v[j];
-            if (b + j < hi) incl[b + j] = run;
+            for (int j = 0; j < 8; ++j) {
+                run += v[j];
+                incl[b + j] = run;
+            }
+        }
+    } else {
+        for (int64_t b = lo; b < lo + chunk; ++b) {
+            run += sums[b];
+            incl[b] = run;
         }
     }
 }

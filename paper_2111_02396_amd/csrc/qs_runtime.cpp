@@ -490,6 +490,10 @@ qs_status qs_create_state(int n_qubits, void *device_buf, size_t buf_bytes, void
     if (n_qubits < 1 || n_qubits > qs::kMaxQubits) return fail(QS_ERR_INVALID_ARGUMENT, "n out of range");
     const size_t bytes = sizeof(float2) << n_qubits;
     if (device_buf && buf_bytes < bytes) return fail(QS_ERR_INVALID_ARGUMENT, "buffer smaller than 8*2^n bytes");
+    if (device_buf && (reinterpret_cast<uintptr_t>(device_buf) & 15u) != 0)
+        return fail(QS_ERR_INVALID_ARGUMENT, "buffer not 16-byte aligned");
+    if (device_buf && (reinterpret_cast<uintptr_t>(device_buf) & 15u) != 0)
+        return fail(QS_ERR_INVALID_ARGUMENT, "buffer not 16-byte aligned");
     auto *s = new qs_state_s();
     s->n = n_qubits;
     s->st = static_cast<hipStream_t>(hip_stream);
