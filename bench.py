@@ -119,6 +119,8 @@ def main() -> int:
     ap.add_argument("--max-fuse", type=int, default=0)
     ap.add_argument("--tile-bits", type=int, default=0,
                     help="LDS tile sweep width (0 = library default, 1 = one pass per fused gate)")
+    ap.add_argument("--inplace-traj", type=int, default=3,
+                    help="trajectories timed with the conventional rule and in-place inner products")
     ap.add_argument("--naive-traj", type=int, default=3,
                     help="trajectories timed with the conventional method (0 = skip)")
     ap.add_argument("--cpu-cycles", type=int, default=1,
@@ -228,6 +230,16 @@ def main() -> int:
                  "sweeps_per_traj": rn["sweeps"] / args.naive_traj}
         log(f"naive: {naive['value']:.3f} traj/s")
 
+    inplace = None
+    if args.inplace_traj > 0:
+        t1 = time.perf_counter()
+        ri = step(30_000_000, False, mode=qs.QS_KRAUS_CONVENTIONAL_INPLACE, n_traj=args.inplace_traj)
+        dti = time.perf_counter() - t1
+        inplace = {"value": args.inplace_traj / dti, "unit": "trajectories/s",
+                   "trajectories": args.inplace_traj,
+                   "sweeps_per_traj": ri["sweeps"] / args.inplace_traj}
+        log(f"conventional, in-place inner products: {inplace['value']:.3f} traj/s")
+
     cpu = None
     if args.cpu_cycles > 0:
         log("timing the CPU oracle sample ...")
@@ -277,6 +289,8 @@ def main() -> int:
         "cpu_baseline": cpu,
         "naive": naive,
         "speedup_vs_naive": (value / naive["value"]) if naive else None,
+        "conventional_inplace": inplace,
+        "speedup_vs_conventional_inplace": (value / inplace["value"]) if inplace else None,
         "gate_sweeps_per_traj": gate_sweeps / total_traj,
         "sweeps_per_traj": sweeps / total_traj,
         "slow_paths_per_traj": slow / total_traj,

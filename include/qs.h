@@ -60,7 +60,11 @@ typedef enum {
 /* Branch-selection scheme for channels (Section 3.5). */
 typedef enum {
     QS_KRAUS_DELAYED = 0, /* Algorithm 2: lower bounds first, inner products only when r >= s */
-    QS_KRAUS_NAIVE = 1    /* conventional: apply K_i, take its norm, for i in order */
+    QS_KRAUS_NAIVE = 1,   /* conventional: apply K_i, take its norm, for i in order */
+    QS_KRAUS_CONVENTIONAL_INPLACE = 2 /* conventional rule (r < p_i, i in order) with every p_i
+                                         from one in-place read pass per channel and the chosen
+                                         K_i folded into the next fused block: the conventional
+                                         method without its scratch state */
 } qs_kraus_mode;
 
 typedef struct qs_state_s *qs_state;
@@ -182,6 +186,8 @@ qs_status qs_apply_fused_gate(qs_state s, int k, const int *targets, const doubl
  *   in place (step 14), and the residual picks i; K_i/sqrt(p_i N) is deferred.
  * QS_KRAUS_NAIVE: for i in order, K_i psi is written to a scratch state (2x
  *   memory) with its FP64 norm in the same pass; r < p_i keeps it.
+ * QS_KRAUS_CONVENTIONAL_INPLACE: the same rule, with p_i = <psi|K_i^dag K_i|psi>/N
+ *   from one in-place read pass (Algorithm 2's second loop with every bound 0).
  * chosen_out (may be NULL) receives the chosen index; path_out (may be NULL)
  * receives 0 (picked from the bounds) or 1 (inner products were needed).
  * Errors: INVALID_ARGUMENT, NOT_SUPPORTED (k > 2), ZERO_NORM (the state or
@@ -213,7 +219,9 @@ qs_status qs_sample_measurements(qs_state s, uint64_t seed, uint32_t traj, int n
  * operator list into blocks of at most max_fuse qubits (Section 3.2) split
  * at the channels that need inner products, apply the blocks, resolve those
  * channels in place (steps 12-20), and finally sample.  QS_KRAUS_NAIVE
- * resolves every channel by the conventional method instead.
+ * resolves every channel by the conventional method instead, and
+ * QS_KRAUS_CONVENTIONAL_INPLACE by the conventional rule with in-place
+ * inner products (every channel takes the inner-product path).
  * The circuit's n_qubits must equal the state's.  Results are written to the
  * caller's host arrays in r.  Errors: INVALID_ARGUMENT, ZERO_NORM, DEVICE. */
 qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_params *p,

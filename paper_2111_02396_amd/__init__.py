@@ -28,6 +28,7 @@ QS_ERR_NOT_SUPPORTED = -5
 
 QS_KRAUS_DELAYED = 0
 QS_KRAUS_NAIVE = 1
+QS_KRAUS_CONVENTIONAL_INPLACE = 2
 QS_OP_GATE = 0
 QS_OP_CHANNEL = 1
 QS_TRAJ_RETURN_STATE = 1

@@ -332,6 +332,22 @@ void build_channel(int k, const int *t, int nk, const cd *kraus, ChannelInfo &c)
     c.default_pick = best;
 }
 
+// The conventional rule expressed as Algorithm 2: every bound 0, so no pick
+// is made from the bounds and the second loop compares the residual r with
+// the full p_i = <psi|K_i^dag K_i|psi>/N in order.
+void to_conventional(ChannelInfo &c) {
+    const int D = 1 << c.k;
+    std::vector<cd> G(size_t(D) * D);
+    for (int i = 0; i < c.nk; ++i) {
+        c.pbar[i] = 0.0;
+        c.log_pbar[i] = 0.0;
+        qs::gram(D, c.kraus + size_t(i) * D * D, G.data());
+        qs::to_ascending_order(c.k, c.t, G.data(), c.excess_sorted.data() + size_t(i) * D * D, c.ts);
+    }
+    c.mixture = false;
+    c.default_pick = 0;
+}
+
 // Matrix to apply for pick i picked from the bounds: nullptr = identity
 // (a scalar multiple of I is dropped: normalisation is lazy).
 const cd *fast_pick_matrix(const ChannelInfo &c, int i) {
@@ -618,16 +634,18 @@ qs_status qs_apply_channel(qs_state s, int k, const int *targets, int n_kraus,
         return fail(QS_ERR_NOT_SUPPORTED, "channels act on at most 2 qubits");
     QS_CHECK(check_targets(s->n, k, targets, qs::kMaxChannelQubits));
     if (n_kraus < 1 || n_kraus > 16 || !kraus) return fail(QS_ERR_INVALID_ARGUMENT, "bad Kraus list");
-    if (mode != QS_KRAUS_DELAYED && mode != QS_KRAUS_NAIVE) return fail(QS_ERR_INVALID_ARGUMENT, "bad mode");
+    if (mode != QS_KRAUS_DELAYED && mode != QS_KRAUS_NAIVE && mode != QS_KRAUS_CONVENTIONAL_INPLACE)
+        return fail(QS_ERR_INVALID_ARGUMENT, "bad mode");
     const int D = 1 << k;
     if (!finite_matrix(kraus, size_t(n_kraus) * D * D * 2))
         return fail(QS_ERR_INVALID_ARGUMENT, "non-finite Kraus entries");
     ChannelInfo c;
     build_channel(k, targets, n_kraus, reinterpret_cast<const cd *>(kraus), c);
+    if (mode == QS_KRAUS_CONVENTIONAL_INPLACE) to_conventional(c);
     const double r = qs::philox_uniform(seed, channel_draw_index(channel_index), traj, 0,
                                         qs::kStreamChannel);
     int pick = -1, path = 0;
-    if (mode == QS_KRAUS_DELAYED) {
+    if (mode == QS_KRAUS_DELAYED || mode == QS_KRAUS_CONVENTIONAL_INPLACE) {
         double residual = 0.0;
         pick = select_fast(c, r, &residual);
         if (pick >= 0) {
@@ -1537,17 +1555,20 @@ struct Runner {
         QS_CHECK(ensure_reduce(s));
         timing = (p.flags & QS_TRAJ_TIME_KERNELS) != 0;
         if (timing) QS_CHECK(timer.init(s, 4096));
-        if (p.mode == QS_KRAUS_DELAYED) QS_CHECK(plan_delayed());
+        // the in-place conventional mode runs on the delayed machinery (its
+        // channels carry zero bounds, so every one takes the inner-product path)
+        const bool delayed = p.mode != QS_KRAUS_NAIVE;
+        if (delayed) QS_CHECK(plan_delayed());
         else QS_CHECK(plan_naive());
         for (int64_t rel = 0; rel < p.n_traj; ++rel) {
             const uint32_t traj = uint32_t(p.traj_offset + rel);
-            if (p.mode == QS_KRAUS_DELAYED) QS_CHECK(run_delayed(rel, traj));
+            if (delayed) QS_CHECK(run_delayed(rel, traj));
             else QS_CHECK(run_naive(rel, traj));
             QS_CHECK(settle_reset());
             QS_CHECK(sample_trajectory(rel, traj));
         }
         QS_CHECK(flush_samples());
-        if (p.mode == QS_KRAUS_DELAYED && dev_choice) QS_CHECK(drain_choices());
+        if (delayed && dev_choice) QS_CHECK(drain_choices());
         if (timing) {
             QS_CHECK(timer.finish(s));
             res.gate_kernel_ms = timer.total_ms;
@@ -1573,7 +1594,8 @@ qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_par
     if (c->n_qubits != s->n) return fail(QS_ERR_INVALID_ARGUMENT, "circuit and state qubit counts differ");
     if (p->n_traj < 0 || p->traj_offset < 0 || p->traj_offset + p->n_traj > (int64_t(1) << 32))
         return fail(QS_ERR_INVALID_ARGUMENT, "trajectory range outside 32-bit counters");
-    if (p->mode != QS_KRAUS_DELAYED && p->mode != QS_KRAUS_NAIVE)
+    if (p->mode != QS_KRAUS_DELAYED && p->mode != QS_KRAUS_NAIVE &&
+        p->mode != QS_KRAUS_CONVENTIONAL_INPLACE)
         return fail(QS_ERR_INVALID_ARGUMENT, "bad mode");
     if (p->max_fuse < 0 || p->max_fuse > qs::kMaxGateQubits)
         return fail(QS_ERR_INVALID_ARGUMENT, "max_fuse outside 0..5");
@@ -1585,6 +1607,8 @@ qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_par
         return fail(QS_ERR_INVALID_ARGUMENT, "readout counter would overflow");
     CircuitModel m;
     QS_CHECK(build_model(c, m));
+    if (p->mode == QS_KRAUS_CONVENTIONAL_INPLACE)
+        for (auto &ci : m.channels) to_conventional(ci);
     QS_CHECK(flush_pending(s));
     r->sweeps = 0;
     r->gate_sweeps = 0;

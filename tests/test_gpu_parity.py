@@ -181,19 +181,23 @@ def _driver(qs, c, n_traj, mode, seed=0, traj_offset=0, n_samples=0, e0=None, e1
                                       circuit_id=circuit_id, tile_bits=tile_bits)
 
 
-@pytest.mark.parametrize("mode", [0, 1], ids=["delayed", "naive"])
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["delayed", "naive", "conventional_inplace"])
 @pytest.mark.parametrize("max_fuse", [2, 4, 5])
 def test_driver_parity_noisy_grid(qs, orc, mode, max_fuse):
     """A 4x3 grid with the benchmark's noise kinds (depolarizing, amplitude
-    damping, readout) at strengths that make inner products frequent."""
+    damping, readout) at strengths that make inner products frequent.  The
+    in-place conventional mode follows the conventional rule, so it is held to
+    the oracle's conventional choices, with every channel on the inner-product
+    path."""
     c = W.grid_circuit(4, 3, 8, p_dep=0.02, gamma=0.03, seed=5)
     e0, e1 = W.readout_arrays(12, 0.02, 0.05)
     m = orc.Marshalled(c)
+    oracle_mode = 0 if mode == 0 else 1
     ties = 0
     for t in range(5):
         got = _driver(qs, c, 1, mode, seed=3, traj_offset=t, n_samples=40, e0=e0, e1=e1,
                       return_state=True, max_fuse=max_fuse)
-        ref = orc.run_trajectory(c, t, mode=mode, seed=3, n_samples=40, e0=e0, e1=e1,
+        ref = orc.run_trajectory(c, t, mode=oracle_mode, seed=3, n_samples=40, e0=e0, e1=e1,
                                  return_state=True, marshalled=m)
         _, tie = compare_choices(got["choices"][0], ref)
         ties += tie
@@ -202,6 +206,9 @@ def test_driver_parity_noisy_grid(qs, orc, mode, max_fuse):
         if mode == 0:
             assert np.array_equal(got["paths"][0], ref["paths"])
             assert got["n_slow"][0] == int(np.sum(ref["paths"]))
+        if mode == 2:
+            assert np.all(got["paths"][0] == 1)
+            assert got["n_slow"][0] == len(got["paths"][0])
         assert rel_l2(got["state"], ref["state"]) < AMP_TOL
         mism = np.nonzero(got["samples"][0] != ref["samples"])[0]
         assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
