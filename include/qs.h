@@ -130,6 +130,8 @@ typedef struct {
     int64_t zero_start_sweeps;    /* out: gate sweeps that began from |0...0> written on chip and
                                      read no state (one write of the state instead of a read and
                                      a write); counted among gate_sweeps */
+    double *z_expect;             /* host [n_traj * n_qubits]: <Z_q> of each trajectory's final
+                                     state (as qs_expectation_z), or NULL to skip the pass */
 } qs_traj_result;
 
 /* ---- state lifecycle ---------------------------------------------------- */
@@ -200,6 +202,23 @@ qs_status qs_apply_channel(qs_state s, int k, const int *targets, int n_kraus,
 /* N = <psi|psi> of the stored vector, accumulated in FP64 with a fixed
  * reduction order (bit-identical run to run).  Flushes; synchronises. */
 qs_status qs_norm(qs_state s, double *norm_sq_out);
+
+/* Observable estimation on the trajectory's state (Section 3.5: an
+ * expectation is averaged over trajectories, each taken on the normalised
+ * state psi/sqrt(N)).
+ * qs_expectation_z: z_out[q] = <psi|Z_q|psi>/N for every qubit q, from one
+ * FP64 read pass (sums of |psi_x|^2 over the indices with bit q set; fixed
+ * reduction order).  z_out: host double [n_qubits].
+ * qs_expectation: <psi|O|psi>/N for a Hermitian O on k = 1..2 qubits,
+ * given as a 2^k x 2^k complex128 row-major matrix whose row/column index
+ * bit j is targets[j] (the convention of qs_apply_fused_gate), taken as
+ * Tr(O R)/Tr(R) with R the FP64 reduced density matrix of the targets.
+ * Both flush and synchronise.  Errors: INVALID_ARGUMENT (null pointer,
+ * target out of range or repeated, O not Hermitian to 1e-12 relative),
+ * NOT_SUPPORTED (k > 2), ZERO_NORM, DEVICE. */
+qs_status qs_expectation_z(qs_state s, double *z_out);
+qs_status qs_expectation(qs_state s, int k, const int *targets, const double *observable,
+                         double *value_out);
 
 /* Measure every qubit n_samples times (inverse CDF of |psi_x|^2/N in index
  * order: sample s takes the smallest x with u_s N < C(x), C the inclusive

@@ -156,6 +156,24 @@ def expectation(psi: np.ndarray, targets: Sequence[int], M: np.ndarray) -> compl
     return complex(re.value, im.value)
 
 
+def z_expectations(psi: np.ndarray) -> np.ndarray:
+    """<Z_q> = sum_x (-1)^{x_q} |psi_x|^2 / sum_x |psi_x|^2 for every qubit q:
+    the per-trajectory expectation of Section 3.5 on the normalised state,
+    written out from the definition (bit q of the index selects the sign)."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    n = int(psi.size).bit_length() - 1
+    p = psi.real ** 2 + psi.imag ** 2
+    N = p.sum()
+    x = np.arange(psi.size, dtype=np.int64)
+    return np.array([(p * (1 - 2 * ((x >> q) & 1))).sum() / N for q in range(n)])
+
+
+def observable_expectation(psi: np.ndarray, targets: Sequence[int], O: np.ndarray) -> float:
+    """<psi|O|psi> / <psi|psi> for a Hermitian O on the targets (matrix index
+    bit j = targets[j])."""
+    return float(expectation(psi, targets, O).real / norm_sq(psi))
+
+
 def select_branch(psi: np.ndarray, targets: Sequence[int], kraus: Sequence[np.ndarray],
                   mode: int, r: float, pbar=None, mixture=None) -> Dict:
     n = int(psi.size).bit_length() - 1

@@ -70,7 +70,8 @@ class QsTrajResult(ctypes.Structure):
                 ("final_state", ctypes.c_void_p), ("sweeps", ctypes.c_int64),
                 ("gate_sweeps", ctypes.c_int64), ("host_seconds", ctypes.c_double),
                 ("gate_kernel_ms", ctypes.c_double), ("gate_kernel_launches", ctypes.c_int64),
-                ("gate_k_launches", ctypes.c_int64 * 6), ("zero_start_sweeps", ctypes.c_int64)]
+                ("gate_k_launches", ctypes.c_int64 * 6), ("zero_start_sweeps", ctypes.c_int64),
+                ("z_expect", ctypes.c_void_p)]
 
 
 class QsBatchItem(ctypes.Structure):
@@ -115,6 +116,8 @@ def load():
         "qs_apply_fused_gate": [vp, i32, vp, vp],
         "qs_apply_channel": [vp, i32, vp, i32, vp, u64, u32, u32, i32, vp, vp],
         "qs_norm": [vp, vp],
+        "qs_expectation_z": [vp, vp],
+        "qs_expectation": [vp, i32, vp, vp, vp],
         "qs_sample_measurements": [vp, u64, u32, i32, vp, vp, vp],
         "qs_run_trajectories": [vp, vp, vp, vp],
         "qs_kraus_bounds": [i32, i32, vp, vp, vp],
@@ -219,6 +222,22 @@ def qs_norm(s) -> float:
     return v.value
 
 
+def qs_expectation_z(s) -> np.ndarray:
+    z = np.zeros(qs_state_qubits(s), dtype=np.float64)
+    _check(load().qs_expectation_z(s, _p(z)))
+    return z
+
+
+def qs_expectation(s, targets, observable) -> float:
+    t = np.ascontiguousarray(np.asarray(targets, dtype=np.int32))
+    o = _c128(observable)
+    if o.shape != (1 << t.size, 1 << t.size):
+        raise ValueError("observable shape does not match the number of targets")
+    v = ctypes.c_double()
+    _check(load().qs_expectation(s, int(t.size), _p(t), _p(o), ctypes.byref(v)))
+    return v.value
+
+
 def qs_sample_measurements(s, seed: int, traj: int, n_samples: int, p0to1=None, p1to0=None):
     out = np.zeros(max(n_samples, 1), dtype=np.uint64)
     e0 = None if p0to1 is None else np.ascontiguousarray(p0to1, dtype=np.float64)
@@ -282,6 +301,7 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
                         tile_bits: int = 0,
                         n_samples: int = 0, p0to1=None, p1to0=None, return_state: bool = False,
                         record_choices: bool = True, time_kernels: bool = False,
+                        z_expect: bool = False,
                         marshalled: Optional[MarshalledCircuit] = None) -> Dict:
     mc = marshalled if marshalled is not None else MarshalledCircuit(circuit)
     nch = mc.n_channels
@@ -299,6 +319,8 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
     res = QsTrajResult()
     res.bitstrings, res.kraus_choices, res.kraus_paths = _p(bits), _p(choices), _p(paths)
     res.n_slow, res.final_state = _p(nslow), _p(state)
+    zs = np.zeros((max(n_traj, 1), mc.n), dtype=np.float64) if z_expect else None
+    res.z_expect = _p(zs)
     _check(load().qs_run_trajectories(s, ctypes.byref(mc.c), ctypes.byref(params),
                                       ctypes.byref(res)))
     out = {
@@ -313,6 +335,8 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
         "gate_k_launches": [int(x) for x in res.gate_k_launches],
         "zero_start_sweeps": res.zero_start_sweeps,
     }
+    if z_expect:
+        out["z_expect"] = zs[:n_traj]
     if record_choices:
         out["choices"] = choices[:n_traj * nch].reshape(n_traj, nch)
         out["paths"] = paths[:n_traj * nch].reshape(n_traj, nch)

@@ -17,7 +17,9 @@ constexpr int kBlock = 256;
 constexpr int kMaxReduceBlocks = 2048;
 // Widest per-workgroup reduction record: the 4x4 complex two-qubit
 // reduced density matrix (32 doubles) plus two scalars.
-constexpr int kMaxReduceWidth = 34;
+constexpr int kMaxReduceWidth = 36;
+// Z-expectation record: N, then sum |psi_x|^2 over x with bit q set, q < 34
+constexpr int kZRecord = 35;
 
 // Sampling blocks hold 2^kSampleBlockBits amplitudes.
 constexpr int kSampleBlockBits = 10;
@@ -153,6 +155,12 @@ hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t 
 // norm: width 1 (sum |psi|^2).
 hipError_t launch_norm(const float2 *amp, int n, double *partials, double *out_dev,
                        hipStream_t st);
+
+// Per-qubit weights of the state in one read pass: out_dev[0] = N =
+// sum |psi_x|^2, out_dev[1 + q] = sum over x with bit q set (FP64, fixed
+// reduction order); <Z_q> = (N - 2 out[1 + q]) / N.  Width kZRecord.
+hipError_t launch_zweights(const float2 *amp, int n, double *partials, double *out_dev,
+                           hipStream_t st);
 
 // Reduced density matrix R = sum_groups v v^dag over k <= 2 ascending
 // targets: width 2*4^k doubles, R[j][l] at (2*(j*D+l), +1).

@@ -890,6 +890,50 @@ __global__ __launch_bounds__(kBlock) void apply_copy_norm(const float2 *__restri
     block_sum_write<2>(acc, partials + size_t(blockIdx.x) * 2);
 }
 
+// Per-qubit weights (see launch_zweights).  Workgroup w owns the contiguous
+// chunk [w 2^c, (w + 1) 2^c); work-item t reads x = chunk + 256 i + t, so
+// bits 0..7 of x come from t, bits 8..c-1 from the iteration i (uniform) and
+// the rest from the chunk (uniform per workgroup).  A work-item keeps its
+// total and one sum per iteration bit; the record's entries follow from
+// those (bit q < 8: the work-item's total if its bit q is set).
+constexpr int kZIterBits = 16;
+template <typename Idx>
+__global__ __launch_bounds__(kBlock) void zweight_partials(const float2 *__restrict__ amp, int n, int c,
+                                                           double *__restrict__ partials) {
+    const int t = threadIdx.x;
+    const int ibits = c > 8 ? c - 8 : 0;
+    const Idx chunk = Idx(blockIdx.x) << c;
+    const Idx iters = Idx(1) << ibits;
+    const int active = c >= 8 || t < (1 << c);
+    double tot = 0.0;
+    double per_bit[kZIterBits];
+#pragma unroll
+    for (int j = 0; j < kZIterBits; ++j) per_bit[j] = 0.0;
+    if (active) {
+        for (Idx i = 0; i < iters; ++i) {
+            const float2 v = amp[chunk + (i << 8) + Idx(t)];
+            const double p = fma(double(v.x), double(v.x), double(v.y) * double(v.y));
+            tot += p;
+#pragma unroll
+            for (int j = 0; j < kZIterBits; ++j)
+                if (j < ibits && ((i >> j) & 1)) per_bit[j] += p;
+        }
+    }
+    double vals[kZRecord];
+    vals[0] = tot;
+#pragma unroll
+    for (int q = 0; q < kZRecord - 1; ++q) {
+        double x = 0.0;
+        if (q < n) {
+            if (q < 8) x = ((t >> q) & 1) ? tot : 0.0;
+            else if (q < 8 + ibits) x = per_bit[q - 8];
+            else x = ((chunk >> q) & 1) ? tot : 0.0;
+        }
+        vals[1 + q] = x;
+    }
+    block_sum_write<kZRecord>(vals, partials + size_t(blockIdx.x) * kZRecord);
+}
+
 // Sum `count` records of `width` doubles in a fixed order (one workgroup).
 __global__ __launch_bounds__(kBlock) void reduce_records(const double *__restrict__ partials,
                                                          int count, int width,
@@ -1313,6 +1357,18 @@ hipError_t launch_norm(const float2 *amp, int n, double *partials, double *out_d
     else
         norm_partials<uint64_t><<<nb, kBlock, 0, st>>>(amp, dim, partials);
     reduce_records<<<1, kBlock, 0, st>>>(partials, nb, 1, out_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_zweights(const float2 *amp, int n, double *partials, double *out_dev, hipStream_t st) {
+    if (n < 1 || n > kZRecord - 1 || n - 8 > 11 + kZIterBits) return hipErrorInvalidValue;
+    // chunks of at least 256 amplitudes, at most kMaxReduceBlocks of them
+    const int lb = n - 8 < 11 ? (n - 8 > 0 ? n - 8 : 0) : 11;
+    const int c = n - lb;
+    const unsigned nb = 1u << lb;
+    if (n <= 31) zweight_partials<uint32_t><<<nb, kBlock, 0, st>>>(amp, n, c, partials);
+    else zweight_partials<uint64_t><<<nb, kBlock, 0, st>>>(amp, n, c, partials);
+    reduce_records<<<1, kBlock, 0, st>>>(partials, int(nb), kZRecord, out_dev);
     return hipGetLastError();
 }
 

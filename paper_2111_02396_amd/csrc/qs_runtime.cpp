@@ -57,6 +57,8 @@ struct qs_state_s {
     double *samp_norm = nullptr;
     uint64_t *samp_out = nullptr;
     size_t samp_cap = 0;
+    double *z_dev = nullptr;  // per-trajectory Z-weight records of the driver
+    size_t z_cap = 0;         // records
     // matrix staging: two halves of a pinned host buffer mirrored on the
     // device; a half is refilled only after its last copy has completed
     float2 *arena_dev = nullptr;
@@ -279,6 +281,24 @@ qs_status device_rdm(qs_state s, int k, const int *ts) {
     const int width = 2 << (2 * k);
     QS_HIP(s, hipMemcpyAsync(s->red_host, s->red_out, sizeof(double) * width, hipMemcpyDeviceToHost, s->st));
     QS_HIP(s, hipStreamSynchronize(s->st));
+    return QS_OK;
+}
+
+qs_status ensure_zrecords(qs_state s, size_t records) {
+    if (records <= s->z_cap) return QS_OK;
+    if (s->z_dev) QS_HIP(s, hipFree(s->z_dev));
+    s->z_dev = nullptr;
+    s->z_cap = 0;
+    QS_HIP(s, hipMalloc(&s->z_dev, sizeof(double) * qs::kZRecord * records));
+    s->z_cap = records;
+    return QS_OK;
+}
+
+// <Z_q> = (N - 2 P1[q]) / N from a Z-weight record {N, P1[0..n-1]}.
+qs_status z_from_record(int n, const double *rec, double *z) {
+    const double N = rec[0];
+    if (!(N > 0.0) || !std::isfinite(N)) return fail(QS_ERR_ZERO_NORM, "state has zero norm");
+    for (int q = 0; q < n; ++q) z[q] = (N - 2.0 * rec[1 + q]) / N;
     return QS_OK;
 }
 
@@ -559,6 +579,7 @@ qs_status qs_destroy_state(qs_state s) {
     if (s->samp_incl) (void)hipFree(s->samp_incl);
     if (s->samp_norm) (void)hipFree(s->samp_norm);
     if (s->samp_out) (void)hipFree(s->samp_out);
+    if (s->z_dev) (void)hipFree(s->z_dev);
     if (s->arena_dev) {
         (void)hipFree(s->arena_dev);
         (void)hipHostFree(s->arena_host);
@@ -696,6 +717,61 @@ qs_status qs_norm(qs_state s, double *norm_sq_out) {
     if (!norm_sq_out) return fail(QS_ERR_INVALID_ARGUMENT, "null output");
     QS_CHECK(flush_pending(s));
     return device_norm(s, norm_sq_out);
+}
+
+qs_status qs_expectation_z(qs_state s, double *z_out) {
+    QS_CHECK(check_handle(s));
+    if (!z_out) return fail(QS_ERR_INVALID_ARGUMENT, "null output");
+    QS_CHECK(flush_pending(s));
+    QS_CHECK(ensure_reduce(s));
+    QS_HIP(s, qs::launch_zweights(s->amp, s->n, s->red_partials, s->red_out, s->st));
+    QS_HIP(s, hipMemcpyAsync(s->red_host, s->red_out, sizeof(double) * (1 + s->n),
+                             hipMemcpyDeviceToHost, s->st));
+    QS_HIP(s, hipStreamSynchronize(s->st));
+    return z_from_record(s->n, s->red_host, z_out);
+}
+
+qs_status qs_expectation(qs_state s, int k, const int *targets, const double *observable,
+                         double *value_out) {
+    QS_CHECK(check_handle(s));
+    if (!targets || !observable || !value_out) return fail(QS_ERR_INVALID_ARGUMENT, "null argument");
+    if (k < 1 || k > qs::kMaxChannelQubits)
+        return fail(QS_ERR_NOT_SUPPORTED, "observables act on one or two qubits");
+    for (int a = 0; a < k; ++a) {
+        if (targets[a] < 0 || targets[a] >= s->n) return fail(QS_ERR_INVALID_ARGUMENT, "target out of range");
+        for (int b = 0; b < a; ++b)
+            if (targets[a] == targets[b]) return fail(QS_ERR_INVALID_ARGUMENT, "repeated target");
+    }
+    const int D = 1 << k;
+    const cd *O = reinterpret_cast<const cd *>(observable);
+    double scale = 0.0;
+    for (int i = 0; i < D * D; ++i) {
+        if (!std::isfinite(O[i].real()) || !std::isfinite(O[i].imag()))
+            return fail(QS_ERR_INVALID_ARGUMENT, "observable has a non-finite entry");
+        scale = std::max(scale, std::abs(O[i]));
+    }
+    for (int i = 0; i < D; ++i)
+        for (int j = 0; j < D; ++j)
+            if (std::abs(O[i * D + j] - std::conj(O[j * D + i])) > 1e-12 * std::max(scale, 1.0))
+                return fail(QS_ERR_INVALID_ARGUMENT, "observable is not Hermitian");
+    std::vector<cd> Os(size_t(D) * D);
+    int ts[qs::kMaxChannelQubits];
+    qs::to_ascending_order(k, targets, O, Os.data(), ts);
+    QS_CHECK(flush_pending(s));
+    QS_CHECK(device_rdm(s, k, ts));
+    // <psi|O|psi> = sum_{j,l} O[j][l] R[l][j] with R[l][j] = v_l conj(v_j) summed over groups
+    const double *R = s->red_host;
+    double N = 0.0, acc = 0.0;
+    for (int j = 0; j < D; ++j) {
+        N += R[2 * (j * D + j)];
+        for (int l = 0; l < D; ++l) {
+            const cd r(R[2 * (l * D + j)], R[2 * (l * D + j) + 1]);
+            acc += (Os[size_t(j) * D + l] * r).real();
+        }
+    }
+    if (!(N > 0.0) || !std::isfinite(N)) return fail(QS_ERR_ZERO_NORM, "state has zero norm");
+    *value_out = acc / N;
+    return QS_OK;
 }
 
 namespace {
@@ -1052,6 +1128,9 @@ struct Runner {
     }
     int64_t sample_fill = 0;        // samples buffered on the device
     int64_t sample_first_traj = 0;  // trajectory index (relative) of the first buffered sample
+    int64_t z_fill = 0;             // Z-weight records buffered on the device
+    int64_t z_first_traj = 0;
+    std::vector<double> z_host;
 
     Runner(qs_state s_, const CircuitModel &m_, const qs_traj_params &p_, qs_traj_result &r_)
         : s(s_), m(m_), p(p_), res(r_) {
@@ -1349,6 +1428,32 @@ struct Runner {
         return QS_OK;
     }
 
+    // <Z_q> of the trajectory's final state: one read pass into a device
+    // record, copied back in batches (no synchronisation per trajectory)
+    qs_status flush_z() {
+        if (z_fill == 0) return QS_OK;
+        z_host.resize(size_t(z_fill) * qs::kZRecord);
+        QS_HIP(s, hipMemcpyAsync(z_host.data(), s->z_dev, sizeof(double) * z_host.size(),
+                                 hipMemcpyDeviceToHost, s->st));
+        QS_HIP(s, hipStreamSynchronize(s->st));
+        for (int64_t i = 0; i < z_fill; ++i)
+            QS_CHECK(z_from_record(s->n, z_host.data() + size_t(i) * qs::kZRecord,
+                                   res.z_expect + (z_first_traj + i) * s->n));
+        z_fill = 0;
+        return QS_OK;
+    }
+
+    qs_status z_trajectory(int64_t rel) {
+        if (!res.z_expect) return QS_OK;
+        if (z_fill == int64_t(s->z_cap)) QS_CHECK(flush_z());
+        if (z_fill == 0) z_first_traj = rel;
+        QS_HIP(s, qs::launch_zweights(s->amp, s->n, s->red_partials,
+                                      s->z_dev + size_t(z_fill) * qs::kZRecord, s->st));
+        res.sweeps += 1;
+        z_fill += 1;
+        return QS_OK;
+    }
+
     qs_status run_delayed(int64_t rel, uint32_t traj) {
         const int nch = int(m.channels.size());
         // steps 1-11 of Algorithm 2 for every channel: state-independent
@@ -1553,6 +1658,8 @@ struct Runner {
             QS_CHECK(ensure_sampling(s, size_t(cap)));
         }
         QS_CHECK(ensure_reduce(s));
+        if (res.z_expect && p.n_traj > 0)
+            QS_CHECK(ensure_zrecords(s, size_t(std::min<int64_t>(p.n_traj, 4096))));
         timing = (p.flags & QS_TRAJ_TIME_KERNELS) != 0;
         if (timing) QS_CHECK(timer.init(s, 4096));
         // the in-place conventional mode runs on the delayed machinery (its
@@ -1566,8 +1673,10 @@ struct Runner {
             else QS_CHECK(run_naive(rel, traj));
             QS_CHECK(settle_reset());
             QS_CHECK(sample_trajectory(rel, traj));
+            QS_CHECK(z_trajectory(rel));
         }
         QS_CHECK(flush_samples());
+        QS_CHECK(flush_z());
         if (delayed && dev_choice) QS_CHECK(drain_choices());
         if (timing) {
             QS_CHECK(timer.finish(s));

@@ -394,3 +394,32 @@ def test_phase_damping_slow_paths_scale_with_noise(qs):
         counts[lam] = (float(r["n_slow"].mean()), n_ch * lam)
     for lam, (got, expect) in counts.items():
         assert abs(got - expect) < 5 * np.sqrt(expect / 40) + 0.5, (lam, got, expect)
+
+
+@pytest.mark.parametrize("shape,cycles,n_traj", [((3, 4), 6, 4), ((4, 5), 4, 1)])
+@pytest.mark.parametrize("mode", [0, 1], ids=["delayed", "naive"])
+def test_driver_approx_noise_model(qs, orc, mode, shape, cycles, n_traj):
+    """Section 5.2's approximate noise model: sqrt(iSWAP) dressed with fSim
+    and Z-phase coherent errors and U_ZZ (unitaries the planner fuses with
+    the gates), 2-qubit depolarizing on every pair and decay/dephasing on
+    every qubit after every moment."""
+    c = W.approx_noise_grid_circuit(*shape, cycles, seed=4, zeta=2e6, p_dep2=0.02,
+                                    step_time=0.5)
+    m = orc.Marshalled(c)
+    e0, e1 = W.readout_arrays(c.n, 0.02, 0.05)
+    ties = 0
+    for t in range(n_traj):
+        got = _driver(qs, c, 1, mode, seed=21, traj_offset=t, n_samples=30, e0=e0, e1=e1,
+                      return_state=True, max_fuse=4)
+        ref = orc.run_trajectory(c, t, mode=mode, seed=21, n_samples=30, e0=e0, e1=e1,
+                                 return_state=True, marshalled=m)
+        _, tie = compare_choices(got["choices"][0], ref)
+        ties += tie
+        if tie:
+            continue
+        if mode == 0:
+            assert np.array_equal(got["paths"][0], ref["paths"])
+        assert rel_l2(got["state"], ref["state"]) < AMP_TOL
+        mism = np.nonzero(got["samples"][0] != ref["samples"])[0]
+        assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
+    assert ties <= 1

@@ -60,3 +60,38 @@ def test_batched_and_serving_shapes():
     assert all(b > a for a, b in zip(ts, ts[1:]))
     assert all(10 <= r.workload.circuit.n <= 32 for r in reqs)
     assert all(1 <= r.workload.n_traj <= 1000 for r in reqs)
+
+
+def test_coherent_error_gates_closed_forms():
+    """fSim special cases (Section 5.2.2): theta = 0, phi = pi is CZ;
+    theta = -pi/2, phi = 0 is iSWAP (i on the swapped pair); two sqrt(iSWAP)
+    make iSWAP; fSim angles add under products; U_ZZ at zeta T = 1/2 is CZ;
+    exp(i varphi Z) is the matrix exponential of i varphi Z."""
+    import math
+    from scipy.linalg import expm
+    assert np.allclose(W.fsim(0.0, math.pi), W.CZ, atol=1e-15)
+    iswap = np.array([[1, 0, 0, 0], [0, 0, 1j, 0], [0, 1j, 0, 0], [0, 0, 0, 1]])
+    assert np.allclose(W.fsim(-math.pi / 2, 0.0), iswap, atol=1e-15)
+    assert np.allclose(W.SQRT_ISWAP @ W.SQRT_ISWAP, iswap, atol=1e-15)
+    a, b, c, d = 0.3, -0.7, 1.1, 0.25
+    assert np.allclose(W.fsim(a, b) @ W.fsim(c, d), W.fsim(a + c, b + d), atol=1e-14)
+    for U in (W.fsim(a, b), W.u_zz(3e6, 10e-9), W.z_phase(0.4)):
+        assert np.allclose(U.conj().T @ U, np.eye(U.shape[0]), atol=1e-14)
+    assert np.allclose(W.u_zz(0.5 / 10e-9, 10e-9), W.CZ, atol=1e-12)
+    assert np.allclose(W.z_phase(0.4), expm(1j * 0.4 * W.PAULI_Z), atol=1e-14)
+
+
+def test_approx_noise_grid_structure():
+    c = W.approx_noise_grid_circuit(3, 4, 4, seed=2, zeta=1e6)
+    names = [o.name for o in c.ops]
+    pairs = names.count("sqrt_iswap")
+    assert pairs > 0
+    assert names.count("fsim_error") == pairs and names.count("u_zz") == pairs
+    assert names.count("z_phase") == 4 * pairs and names.count("depolarize2") == pairs
+    assert names.count("decay_dephase") == 2 * 4 * 12
+    # each dressed gate reads: z, z, sqrt_iswap, fsim_error, u_zz, z, z, depolarize2
+    i = names.index("sqrt_iswap")
+    assert names[i - 2:i + 6] == ["z_phase", "z_phase", "sqrt_iswap", "fsim_error", "u_zz",
+                                  "z_phase", "z_phase", "depolarize2"]
+    again = W.approx_noise_grid_circuit(3, 4, 4, seed=2, zeta=1e6)
+    assert all(np.array_equal(x.mats[0], y.mats[0]) for x, y in zip(c.ops, again.ops))

@@ -26,6 +26,11 @@ from .circuits import (  # noqa: F401
     phase_damp,
     bit_flip,
     decay_dephase,
+    fsim,
+    SQRT_ISWAP,
+    z_phase,
+    u_zz,
+    approx_noise_grid_circuit,
     chain_circuit,
     grid_circuit,
     generic_grid_circuit,

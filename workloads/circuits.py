@@ -152,6 +152,94 @@ def decay_dephase(t: float, t1: float, tphi: float) -> List[np.ndarray]:
 
 
 # --------------------------------------------------------------------------
+# Coherent (unitary) errors.
+# --------------------------------------------------------------------------
+
+
+def fsim(theta: float, phi: float) -> np.ndarray:
+    """fSim(theta, phi) of Section 5.2.2: a rotation by theta between |01>
+    and |10> (off-diagonal -i sin theta) and the phase e^{-i phi} on |11>.
+    Symmetric under exchanging the two qubits, so the target order does not
+    matter."""
+    c, s = math.cos(theta), math.sin(theta)
+    return np.array([[1, 0, 0, 0],
+                     [0, c, -1j * s, 0],
+                     [0, -1j * s, c, 0],
+                     [0, 0, 0, np.exp(-1j * phi)]], dtype=np.complex128)
+
+
+SQRT_ISWAP = fsim(-math.pi / 4, 0.0)  # fSim at theta = -pi/4: the square root of iSWAP
+
+
+def z_phase(varphi: float) -> np.ndarray:
+    """Single-qubit Z phase error exp(i varphi Z) (Section 5.2.2)."""
+    return np.diag([np.exp(1j * varphi), np.exp(-1j * varphi)]).astype(np.complex128)
+
+
+def u_zz(zeta: float, gate_time: float) -> np.ndarray:
+    """Control error of Section 4: exp(-i 2 pi zeta T |11><11|), a phase on
+    |11> only."""
+    return np.diag([1, 1, 1, np.exp(-2j * math.pi * zeta * gate_time)]).astype(np.complex128)
+
+
+def approx_noise_grid_circuit(rows: int, cols: int, cycles: int, seed: int = 0,
+                              dtheta: float = 0.01, dphi: float = 0.05,
+                              zphase_sigma: float = 0.01, zeta: float = 0.0,
+                              gate_time: float = 10e-9, p_dep1: float = 1e-3,
+                              p_dep2: float = 5e-3, step_time: float = 0.025,
+                              t1: float = 15.0, tphi: float = 30.0) -> Circuit:
+    """Section 5.2's approximate noise model on a rows x cols grid.
+
+    Per cycle: a random 1-qubit layer, each gate followed by 1-qubit
+    depolarizing; then one coupler pattern of sqrt(iSWAP) gates, each
+    dressed with its coherent errors -- exp(i varphi Z) on both qubits before
+    and after, fSim(dtheta, dphi) right after the gate, and (zeta > 0) the
+    U_ZZ control error -- then 2-qubit depolarizing on the pair.  Every
+    moment ends with the decay/dephasing channel on every qubit (times in
+    microseconds: step_time per moment, T1, T_phi).
+
+    The Z phase angles are drawn once per gate instance from a normal
+    distribution of width zphase_sigma (a calibrated, static error: the
+    same in every trajectory), from the circuit's seed.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = rows * cols
+    pats = [p for p in grid_coupler_patterns(rows, cols) if p]
+    dep1 = depolarize(p_dep1)
+    dep2 = depolarize2(p_dep2)
+    dd = decay_dephase(step_time, t1, tphi)
+    err = fsim(dtheta, dphi)
+    zz = u_zz(zeta, gate_time) if zeta else None
+    ops: List[Op] = []
+    moment = 0
+    for cyc in range(cycles):
+        layer = _one_qubit_layer(n, rng)
+        for q in range(n):
+            nm, u = layer[q]
+            ops.append(Op(GATE, (q,), [u], moment, nm))
+            ops.append(Op(CHANNEL, (q,), dep1, moment, "depolarize"))
+        for q in range(n):
+            ops.append(Op(CHANNEL, (q,), dd, moment, "decay_dephase"))
+        moment += 1
+        for a, b in pats[cyc % len(pats)]:
+            for q in (a, b):
+                ops.append(Op(GATE, (q,), [z_phase(rng.normal(0.0, zphase_sigma))], moment,
+                              "z_phase"))
+            ops.append(Op(GATE, (a, b), [SQRT_ISWAP], moment, "sqrt_iswap"))
+            ops.append(Op(GATE, (a, b), [err], moment, "fsim_error"))
+            if zz is not None:
+                ops.append(Op(GATE, (a, b), [zz], moment, "u_zz"))
+            for q in (a, b):
+                ops.append(Op(GATE, (q,), [z_phase(rng.normal(0.0, zphase_sigma))], moment,
+                              "z_phase"))
+            ops.append(Op(CHANNEL, (a, b), dep2, moment, "depolarize2"))
+        for q in range(n):
+            ops.append(Op(CHANNEL, (q,), dd, moment, "decay_dephase"))
+        moment += 1
+    return Circuit(n, ops, f"approx_noise{rows}x{cols}")
+
+
+# --------------------------------------------------------------------------
 # Random matrices for tests.
 # --------------------------------------------------------------------------
 
