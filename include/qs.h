@@ -105,7 +105,7 @@ typedef struct {
     int32_t mode;          /* qs_kraus_mode */
     int32_t max_fuse;      /* largest fused gate (Section 3.2); 0 = library default (4) */
     int32_t tile_bits;     /* LDS tile sweeps: fused gates whose qubits fit a tile of this
-                              many index bits (bits 0..5 always included) share one pass
+                              many index bits (bits 0..3 always included) share one pass
                               over the state; 0 = library default (13), 1 = off (one pass
                               per fused gate), otherwise 10..14 */
     int32_t n_samples;     /* measurement samples per trajectory (>= 0) */
@@ -318,7 +318,7 @@ qs_status qs_fusion_plan(const qs_circuit *c, int max_fuse, int32_t *n_blocks_ou
  * order in which the trajectory driver applies them, one pass over the state
  * per sweep.  Outputs (capacity n_ops): n_sweeps_out; order_out[i] = block
  * applied i-th; sweep_of_order[i] = its sweep; sweep_bits[s] = bit mask of
- * the index bits staged in LDS by sweep s (bits 0..5 always included).
+ * the index bits staged in LDS by sweep s (bits 0..3 always included).
  * tile_bits as in qs_traj_params (0 = 13).  Host only. */
 qs_status qs_sweep_plan(const qs_circuit *c, int max_fuse, int tile_bits, int32_t *n_sweeps_out,
                         int32_t *order_out, int32_t *sweep_of_order, uint64_t *sweep_bits);

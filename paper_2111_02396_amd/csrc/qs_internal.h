@@ -37,12 +37,18 @@ struct TargetArgs {
 };
 
 // Tiled sweeps: a tile is 2^tb amplitudes whose index bits are pos[0..tb-1]
-// (ascending, always starting with bits 0..5); the gates g[0..n_gates-1]
+// (ascending, always starting with bits 0..kTileLowBits-1); the gates g[0..n_gates-1]
 // act in order on tile-local bit positions lt[] (ascending), with their
 // matrices (2^k x 2^k complex64, rows/columns in lt order) read from device
 // address `mat` (16-byte aligned) and, for k >= 3, staged in LDS at float2
 // offset `lofs` (even) of a region of mat_total entries.
 constexpr int kMaxTileBits = 14;
+// Index bits every tile holds: a work-item moves an amplitude pair (bit 0)
+// and eight consecutive lanes cover bits 1..3, so each group of eight lanes
+// reads or writes one whole 128-byte line wherever the tile's other bits
+// lie.  Requiring only these four (rather than a 512-byte row) leaves nine
+// of a 13-bit tile's bits to the sweep's gates.
+constexpr int kTileLowBits = 4;
 constexpr int kDefaultTileBits = 13;  // tile sweeps when the caller asks for the default
 constexpr int kMaxTileGates = 48;
 constexpr int kTileMinQubits = 10;

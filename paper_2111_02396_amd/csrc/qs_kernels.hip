@@ -403,8 +403,8 @@ __device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const f
 // Tiled path: persistent workgroups stage every gate matrix of the launch in
 // LDS once (as MFMA fragments for k = 3, 4; plain for k = 5; k <= 2 matrices
 // stay in global memory and arrive through scalar loads), then loop over
-// tiles of 2^TB amplitudes -- the index bits in a.pos, bits 0..5 first, so
-// each wavefront load is a 512 B row.  A tile is written to LDS, the next
+// tiles of 2^TB amplitudes -- the index bits in a.pos, bits 0..3 first, so
+// every eight lanes of a wavefront load one whole 128-byte line.  A tile is written to LDS, the next
 // tile's loads are issued into registers, the gates run on the LDS copy in
 // order, and the tile is written back: any number of gates inside the tile
 // cost one HBM read and one write.
@@ -419,8 +419,8 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
     constexpr int E = 1 << TB;
     // Each work-item moves R amplitude pairs per tile: pair (t, r) holds local
     // indices 2 t + NT 2 r + {0, 1}, which differ in local bit 0 = qubit 0, so
-    // the pair is one 16-byte load or store, and a wavefront covers two
-    // 512-byte rows.
+    // the pair is one 16-byte load or store, and each eight lanes cover one
+    // 128-byte line (local bits 0..3 are global bits 0..3).
     constexpr int R = E / (2 * NT);
     // The tile is a static array (its LDS address is a link-time constant
     // that folds into the LDS instructions' offsets); the launch's matrices
@@ -1335,6 +1335,12 @@ hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t 
     if (a.tb < 10 || a.tb > kMaxTileBits || a.tb > n || a.n_gates < 0 ||
         a.n_gates > kMaxTileGates || a.mat_total < 0 || a.mat_total > kTileMatBudget)
         return hipErrorInvalidValue;
+    // tile bits: ascending global positions below n, the first kTileLowBits
+    // of them bits 0.. (the pair loads need local bit 0 = global bit 0)
+    for (int b = 0; b < a.tb; ++b)
+        if (a.pos[b] < 0 || a.pos[b] >= n || (b > 0 && a.pos[b] <= a.pos[b - 1]) ||
+            (b < kTileLowBits && a.pos[b] != b))
+            return hipErrorInvalidValue;
     for (int gi = 0; gi < a.n_gates; ++gi) {
         const TileGate &g = a.g[gi];
         if (g.k < 1 || g.k > kMaxGateQubits || g.k > a.tb || !g.mat || g.lofs < 0 ||

@@ -172,7 +172,7 @@ def test_sweep_grouping_keeps_order(lib, tile_bits, f):
         for i, b in enumerate(order):
             mask = int(bits[sweep_of[i]])
             assert all((mask >> q) & 1 for q in blocks[b][0])
-            assert mask & 0x3F == 0x3F
+            assert mask & 0xF == 0xF
             assert bin(mask).count("1") <= tile_bits
 
 
