@@ -119,6 +119,9 @@ def main() -> int:
     ap.add_argument("--max-fuse", type=int, default=0)
     ap.add_argument("--tile-bits", type=int, default=0,
                     help="LDS tile sweep width (0 = library default, 1 = one pass per fused gate)")
+    ap.add_argument("--concurrent-streams", type=int, default=2,
+                    help="also time one step with the trajectories split over this many states "
+                         "on their own streams, run at once (0 or 1 = skip)")
     ap.add_argument("--inplace-traj", type=int, default=3,
                     help="trajectories timed with the conventional rule and in-place inner products")
     ap.add_argument("--naive-traj", type=int, default=3,
@@ -220,6 +223,33 @@ def main() -> int:
     flops = sum(k_hist[k] * (8 << k) for k in range(1, 6)) * float(1 << n)
     flops_tf = flops / (gate_ms / 1e3) / 1e12 if gate_ms > 0 else 0.0
 
+    # The sweep's binding roofline: the longer of its algorithmic bytes at the
+    # HBM peak and its algorithmic flops at the FP32 MFMA peak.
+    hbm_side = {"achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS,
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "roofline_us_per_launch": bytes_per_launch / (HBM_PEAK_GBPS * 1e3)}
+    flops_per_launch = flops / max(gate_launches, 1)
+    mfma_us = flops_per_launch / (FP32_PEAK_TFLOPS * 1e6)
+    common = {
+        "traffic": (traffic / 1e9) if traffic else None,
+        "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "kernel": "fused-gate sweep (apply_tile / apply_direct): one read + one write of the state, "
+                  "the sweep's fused blocks applied in LDS",
+        "avg_launch_us": avg_gate_s * 1e6,
+        "launches": gate_launches,
+        "zero_start_launches": zero_start,
+    }
+    if mfma_us > hbm_side["roofline_us_per_launch"]:
+        roofline = {"bound": "mfma", "achieved": flops_tf, "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": flops_tf / FP32_PEAK_TFLOPS,
+                    "algorithmic_flops_per_launch": flops_per_launch,
+                    "roofline_us_per_launch": mfma_us,
+                    "basis": "8*2^k flops per amplitude per fused k-qubit block (complex mat-vec)",
+                    **common}
+    else:
+        roofline = {"bound": "hbm", **{k: v for k, v in hbm_side.items()}, **common}
+
     naive = None
     if args.naive_traj > 0:
         t1 = time.perf_counter()
@@ -239,6 +269,35 @@ def main() -> int:
                    "trajectories": args.inplace_traj,
                    "sweeps_per_traj": ri["sweeps"] / args.inplace_traj}
         log(f"conventional, in-place inner products: {inplace['value']:.3f} traj/s")
+
+    concurrent = None
+    if args.concurrent_streams > 1:
+        # the same step with the range split over several states run at once
+        extra = []
+        for _ in range(args.concurrent_streams - 1):
+            sx = torch.cuda.Stream()
+            bx = torch.zeros(1 << n, dtype=torch.complex64, device="cuda")
+            extra.append((qs.State(n, bx.data_ptr(), bx.numel() * 8, sx.cuda_stream), bx, sx))
+        handles = [st.h] + [e[0].h for e in extra]
+
+        def cstep(offset: int):
+            return qs.qs_run_trajectories(
+                handles, c, args.traj, seed=w.seed, traj_offset=offset, max_fuse=args.max_fuse,
+                tile_bits=args.tile_bits, n_samples=w.n_samples, p0to1=w.e0, p1to0=w.e1,
+                record_choices=False, marshalled=mc)
+        cstep(40_000_000)  # warm the extra states
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for s_ in range(args.steps):
+            cstep(50_000_000 + s_ * args.traj)
+        torch.cuda.synchronize()
+        dtc = time.perf_counter() - t1
+        concurrent = {"streams": args.concurrent_streams,
+                      "value": args.steps * args.traj / dtc, "unit": "trajectories/s",
+                      "ms_per_step": 1e3 * dtc / args.steps}
+        log(f"{args.concurrent_streams} concurrent states: {concurrent['value']:.1f} traj/s")
+        for e in extra:
+            e[0].close()
 
     cpu = None
     if args.cpu_cycles > 0:
@@ -269,24 +328,10 @@ def main() -> int:
             "tile_bits": args.tile_bits or 13,
             "parallelism": "none (1 GPU)",
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBPS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBPS,
-            "traffic": (traffic / 1e9) if traffic else None,
-            "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": "fused-gate sweep (apply_tile / apply_direct): one read + one write of the state",
-            "avg_launch_us": avg_gate_s * 1e6,
-            "launches": gate_launches,
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "zero_start_launches": zero_start,
-        },
-        "compute": {"achieved": flops_tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": flops_tf / FP32_PEAK_TFLOPS,
-                    "basis": "8*2^k flops per amplitude per fused k-qubit block, summed per sweep"},
+        "roofline": roofline,
+        "hbm": hbm_side,
         "cpu_baseline": cpu,
+        "concurrent": concurrent,
         "naive": naive,
         "speedup_vs_naive": (value / naive["value"]) if naive else None,
         "conventional_inplace": inplace,

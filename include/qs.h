@@ -246,6 +246,23 @@ qs_status qs_sample_measurements(qs_state s, uint64_t seed, uint32_t traj, int n
 qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_params *p,
                               qs_traj_result *r);
 
+/* The trajectory range of p split over several states that run at once
+ * (Section 3.5: trajectories are independent).  The range is cut into
+ * n_states contiguous chunks (the first n_traj mod n_states chunks one
+ * trajectory longer); chunk j runs as qs_run_trajectories on states[j], from
+ * a host thread of its own, so the chunks' kernels overlap on the device
+ * when the states use different streams (one sweep's load and store ramps
+ * are then filled by another's work).  Every trajectory's draws depend only
+ * on (seed, trajectory index, circuit id), so all outputs equal those of
+ * one qs_run_trajectories call over the same range.  Results go to r's
+ * arrays at each trajectory's position; final_state (QS_TRAJ_RETURN_STATE)
+ * is the range's last trajectory; the counters are sums over the chunks
+ * (gate_kernel_ms sums the streams' kernel time, which overlaps).
+ * states: 1..16 distinct handles, each with n_qubits equal to the
+ * circuit's.  Errors: as qs_run_trajectories (the first failing chunk's). */
+qs_status qs_run_trajectories_concurrent(qs_state *states, int n_states, const qs_circuit *c,
+                                         const qs_traj_params *p, qs_traj_result *r);
+
 /* ---- batched persistent launch ------------------------------------------ */
 
 /* One circuit of a batched launch and where its results go. */

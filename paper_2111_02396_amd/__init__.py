@@ -120,6 +120,7 @@ def load():
         "qs_expectation": [vp, i32, vp, vp, vp],
         "qs_sample_measurements": [vp, u64, u32, i32, vp, vp, vp],
         "qs_run_trajectories": [vp, vp, vp, vp],
+        "qs_run_trajectories_concurrent": [vp, i32, vp, vp, vp],
         "qs_kraus_bounds": [i32, i32, vp, vp, vp],
         "qs_fusion_plan": [vp, i32, vp, vp, vp, vp, vp],
         "qs_philox4x32_10": [vp, vp, vp],
@@ -303,6 +304,9 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
                         record_choices: bool = True, time_kernels: bool = False,
                         z_expect: bool = False,
                         marshalled: Optional[MarshalledCircuit] = None) -> Dict:
+    """Run trajectories traj_offset .. traj_offset + n_traj - 1 (qs_run_trajectories).
+    `s` may also be a list of state handles: the range is then split over them
+    and run at once (qs_run_trajectories_concurrent); the outputs are the same."""
     mc = marshalled if marshalled is not None else MarshalledCircuit(circuit)
     nch = mc.n_channels
     e0 = None if p0to1 is None else np.ascontiguousarray(p0to1, dtype=np.float64)
@@ -321,8 +325,15 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
     res.n_slow, res.final_state = _p(nslow), _p(state)
     zs = np.zeros((max(n_traj, 1), mc.n), dtype=np.float64) if z_expect else None
     res.z_expect = _p(zs)
-    _check(load().qs_run_trajectories(s, ctypes.byref(mc.c), ctypes.byref(params),
-                                      ctypes.byref(res)))
+    if isinstance(s, (list, tuple)):
+        # several states at once (qs_run_trajectories_concurrent)
+        hs = (ctypes.c_void_p * len(s))(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                          for h in s])
+        _check(load().qs_run_trajectories_concurrent(hs, len(s), ctypes.byref(mc.c),
+                                                     ctypes.byref(params), ctypes.byref(res)))
+    else:
+        _check(load().qs_run_trajectories(s, ctypes.byref(mc.c), ctypes.byref(params),
+                                          ctypes.byref(res)))
     out = {
         "samples": bits[:n_traj * n_samples].reshape(n_traj, n_samples),
         "n_slow": nslow[:n_traj],

@@ -271,19 +271,23 @@ __device__ __forceinline__ float real_form(float2 u, int co, int ci) {
     return co == 0 ? (ci == 0 ? u.x : -u.y) : (ci == 0 ? u.y : u.x);
 }
 
-// k = 4 with three real products instead of four (Gauss): for U = A + iB and
-// v = x + iy, t1 = A x, t2 = B y, t3 = (A + B)(x + y) give Re Uv = t1 - t2 and
-// Im Uv = t3 - t1 - t2.  v_mfma_f32_16x16x4f32: in step s lane l supplies
-// A[l%16][4s + l/16] and B[4s + l/16][l%16]; accumulator r is row 4(l/16) + r,
-// column l%16.  Fragment layout: frag[lane * 12 + 4 m + s] = M_m[l%16][4s + l/16]
-// with M_0 = Re U, M_1 = Im U, M_2 = Re U + Im U.
+// k = 4 with three real products instead of four (Gauss), arranged so that
+// the MFMA accumulators do the combining: for U = A + iB and v = x + iy,
+// with k1 = A (x + y),
+//   Re Uv = A x - B y = k1 - (A + B) y,   Im Uv = B x + A y = k1 + (B - A) x,
+// so one chain forms k1 and two chains seeded with it add (-(A + B)) y and
+// (B - A) x.  The only per-amplitude vector work left is x + y.
+// v_mfma_f32_16x16x4f32: in step s lane l supplies A[l%16][4s + l/16] and
+// B[4s + l/16][l%16]; accumulator r is row 4(l/16) + r, column l%16.
+// Fragment layout: frag[lane * 12 + 4 m + s] = M_m[l%16][4s + l/16] with
+// M_0 = Re U, M_1 = -(Re U + Im U), M_2 = Im U - Re U.
 template <int NT = kBlock>
 __device__ __forceinline__ void stage_frag4(float *__restrict__ frag, const float2 *__restrict__ u) {
     for (int i = threadIdx.x; i < 64 * 12; i += NT) {
         const int lane = i / 12, rem = i - 12 * lane;
         const int m = rem >> 2, s = rem & 3;
         const float2 e = u[(lane & 15) * 16 + 4 * s + (lane >> 4)];
-        frag[i] = m == 0 ? e.x : (m == 1 ? e.y : e.x + e.y);
+        frag[i] = m == 0 ? e.x : (m == 1 ? -(e.x + e.y) : e.y - e.x);
     }
 }
 
@@ -315,40 +319,45 @@ __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const f
     const f32x4 fa = fp[0], fb = fp[1], fs = fp[2];
     // LDS byte offset of amplitude j of group 16 b + n.  The local index is
     // spread(16 b + n) | offset(j); with j = 4 s + q (inputs) or 4 q + r
-    // (outputs) each part splits into a per-lane term (n, q) and a
-    // wave-uniform term (b, s or r), and the layout map is linear, so every
-    // access is one XOR of a lane register with a scalar.
+    // (outputs) each part splits into a per-lane term (n, q, and s or r,
+    // which are unrolled) and a wave-uniform term (b), and the layout map is
+    // linear, so every access is one XOR of a lane register with a scalar.
     const int lane_part = L::map(spread_index<4, int>(n, lt));
     const int lin = 8 * (lane_part ^ L::map(((q & 1) << lt[0]) | ((q >> 1) << lt[1])));
     const int lout = 8 * (lane_part ^ L::map(((q & 1) << lt[2]) | ((q >> 1) << lt[3])));
-    int uin[4], uout[4];
+    int ain[4], aout[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        uin[s] = 8 * L::map(((s & 1) << lt[2]) | ((s >> 1) << lt[3]));
-        uout[s] = 8 * L::map(((s & 1) << lt[0]) | ((s >> 1) << lt[1]));
+        ain[s] = lin ^ (8 * L::map(((s & 1) << lt[2]) | ((s >> 1) << lt[3])));
+        aout[s] = lout ^ (8 * L::map(((s & 1) << lt[0]) | ((s >> 1) << lt[1])));
     }
     const int iters = (1 << (tb - 4 - 4)) / W;  // batches per wave: >= 1 needs tb >= 8 + log2 W
     int ub = 8 * L::map(spread_index<4, int>(wave << 4, lt));
     float2 v[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = lds_get(sd, lin ^ (uin[s] ^ ub));
+    for (int s = 0; s < 4; ++s) v[s] = lds_get(sd, ain[s] ^ ub);
     for (int it = 0; it < iters; ++it) {
         prio_for_remaining(iters - it);
         const int itn = it + 1 < iters ? it + 1 : it;
         const int ubn = 8 * L::map(spread_index<4, int>((wave + W * itn) << 4, lt));
         float2 w[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) w[s] = lds_get(sd, lin ^ (uin[s] ^ ubn));
-        f32x4 t1 = {0.f, 0.f, 0.f, 0.f}, t2 = t1, t3 = t1;
+        for (int s = 0; s < 4; ++s) w[s] = lds_get(sd, ain[s] ^ ubn);
+        f32x4 k1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) k1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s], v[s].x + v[s].y, k1, 0, 0, 0);
+        f32x4 re = k1, im = k1;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s], v[s].x, t1, 0, 0, 0);
-            t2 = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[s], v[s].y, t2, 0, 0, 0);
-            t3 = __builtin_amdgcn_mfma_f32_16x16x4f32(fs[s], v[s].x + v[s].y, t3, 0, 0, 0);
+            re = __builtin_amdgcn_mfma_f32_16x16x4f32(fb[s], v[s].y, re, 0, 0, 0);
+            im = __builtin_amdgcn_mfma_f32_16x16x4f32(fs[s], v[s].x, im, 0, 0, 0);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            lds_put(sd, lout ^ (uout[r] ^ ub), make_float2(t1[r] - t2[r], t3[r] - t1[r] - t2[r]));
+        for (int r = 0; r < 4; ++r) {
+            char *dst = reinterpret_cast<char *>(sd) + (aout[r] ^ ub);
+            reinterpret_cast<float *>(dst)[0] = re[r];
+            reinterpret_cast<float *>(dst)[1] = im[r];
+        }
         ub = ubn;
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = w[s];
@@ -372,27 +381,27 @@ __device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const f
     const int lane_part = L::map(spread_index<3, int>(n, lt));
     const int lin = (8 * (lane_part ^ L::map((q >> 1) << lt[0]))) | (4 * (q & 1));
     const int lout = 8 * (lane_part ^ L::map(((q & 1) << lt[1]) | ((q >> 1) << lt[2])));
-    const int uo1 = 8 * L::map(1 << lt[0]);
-    int uin[4];
+    const int lout1 = lout ^ (8 * L::map(1 << lt[0]));
+    int ain[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) uin[s] = 8 * L::map(((s & 1) << lt[1]) | ((s >> 1) << lt[2]));
+    for (int s = 0; s < 4; ++s) ain[s] = lin ^ (8 * L::map(((s & 1) << lt[1]) | ((s >> 1) << lt[2])));
     const int iters = (1 << (tb - 3 - 4)) / W;  // batches per wave: >= 1 needs tb >= 7 + log2 W
     int ub = 8 * L::map(spread_index<3, int>(wave << 4, lt));
     float v[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = lds_getf(sd, lin ^ (uin[s] ^ ub));
+    for (int s = 0; s < 4; ++s) v[s] = lds_getf(sd, ain[s] ^ ub);
     for (int it = 0; it < iters; ++it) {
         prio_for_remaining(iters - it);
         const int itn = it + 1 < iters ? it + 1 : it;
         const int ubn = 8 * L::map(spread_index<3, int>((wave + W * itn) << 4, lt));
         float w[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) w[s] = lds_getf(sd, lin ^ (uin[s] ^ ubn));
+        for (int s = 0; s < 4; ++s) w[s] = lds_getf(sd, ain[s] ^ ubn);
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[s], v[s], acc, 0, 0, 0);
         lds_put(sd, lout ^ ub, make_float2(acc[0], acc[1]));
-        lds_put(sd, lout ^ (uo1 ^ ub), make_float2(acc[2], acc[3]));
+        lds_put(sd, lout1 ^ ub, make_float2(acc[2], acc[3]));
         ub = ubn;
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = w[s];
@@ -1162,36 +1171,35 @@ hipError_t apply_direct_idx(float2 *amp, int n, const GateDesc &g, const float2 
 }
 
 int device_cus() {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
+    // initialised once, thread-safely (several host threads may launch at once)
+    static const int cus = [] {
+        int dev = 0, c = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
-            cus = 256;
-    }
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            c = 256;
+        return c;
+    }();
     return cus;
 }
 
 template <int TB, typename Idx, bool K5, int NT>
 hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
-    static bool attr_set = false;
-    static int reg_limit = 1;  // resident workgroups per CU allowed by registers and waves
     // static tile + dynamic matrices
     const size_t dyn = sizeof(float2) * size_t(a.mat_total);
     const size_t lds = sizeof(float2) * (size_t(1) << TB) + dyn;
     const void *fn = reinterpret_cast<const void *>(&apply_tile<TB, Idx, K5, NT>);
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           int(sizeof(float2) * kTileMatBudget));
-        if (e != hipSuccess) return e;
-        // with no matrices the LDS is not what limits the count
+    // once per instantiation, thread-safely: allow the matrix region, and read
+    // how many workgroups per CU registers and waves allow (with no matrices
+    // the LDS is not what limits the count); a negative value is an error
+    static const int reg_limit = [fn] {
+        if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(sizeof(float2) * kTileMatBudget)) != hipSuccess)
+            return -1;
         int blocks = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, NT, 0);
-        if (e != hipSuccess) return e;
-        reg_limit = blocks < 1 ? 1 : blocks;
-        attr_set = true;
-    }
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, NT, 0) != hipSuccess) return -1;
+        return blocks < 1 ? 1 : blocks;
+    }();
+    if (reg_limit < 0) return hipErrorInvalidDeviceFunction;
     const Idx n_tiles = Idx(1) << (n - TB);
     // persistent grid: as many workgroups as are resident at once at this LDS size
     int per_cu = int((160u * 1024u) / lds);
@@ -1243,14 +1251,11 @@ int batched_grid() {
 }
 
 hipError_t launch_batched(const BatchArgs &a, int grid, hipStream_t st) {
-    static bool attr_set = false;
     const size_t lds = sizeof(float2) * ((size_t(1) << kBatchLdsQubits) + 1024);
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&run_batched),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&run_batched),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       int(lds));
+    if (attr != hipSuccess) return attr;
     if (grid < 1) return hipErrorInvalidValue;
     run_batched<<<unsigned(grid), kBlock, lds, st>>>(a);
     return hipGetLastError();

@@ -1731,6 +1731,72 @@ qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_par
     return st;
 }
 
+qs_status qs_run_trajectories_concurrent(qs_state *states, int n_states, const qs_circuit *c,
+                                         const qs_traj_params *p, qs_traj_result *r) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!states || !c || !p || !r) return fail(QS_ERR_INVALID_ARGUMENT, "null argument");
+    if (n_states < 1 || n_states > 16) return fail(QS_ERR_INVALID_ARGUMENT, "n_states outside 1..16");
+    for (int j = 0; j < n_states; ++j) {
+        QS_CHECK(check_handle(states[j]));
+        for (int i = 0; i < j; ++i)
+            if (states[i] == states[j]) return fail(QS_ERR_INVALID_ARGUMENT, "a state appears twice");
+    }
+    if (p->n_traj < 0) return fail(QS_ERR_INVALID_ARGUMENT, "negative trajectory count");
+    const int nch = [&] {
+        int k = 0;
+        if (c->ops)
+            for (int o = 0; o < c->n_ops; ++o) k += c->ops[o].kind == QS_OP_CHANNEL ? 1 : 0;
+        return k;
+    }();
+    const int n = c->n_qubits;
+    // contiguous chunks, the first (n_traj mod n_states) one trajectory longer
+    std::vector<qs_traj_params> sp(n_states, *p);
+    std::vector<qs_traj_result> sr(n_states);
+    int64_t start = 0;
+    for (int j = 0; j < n_states; ++j) {
+        const int64_t cnt = p->n_traj / n_states + (j < p->n_traj % n_states ? 1 : 0);
+        sp[j].traj_offset = p->traj_offset + start;
+        sp[j].n_traj = cnt;
+        qs_traj_result &x = sr[j];
+        std::memset(&x, 0, sizeof(x));
+        x.bitstrings = r->bitstrings ? r->bitstrings + start * p->n_samples : nullptr;
+        x.kraus_choices = r->kraus_choices ? r->kraus_choices + start * nch : nullptr;
+        x.kraus_paths = r->kraus_paths ? r->kraus_paths + start * nch : nullptr;
+        x.n_slow = r->n_slow ? r->n_slow + start : nullptr;
+        x.z_expect = r->z_expect ? r->z_expect + start * n : nullptr;
+        // the final state is the last trajectory's: the last non-empty chunk returns it
+        const bool last = start + cnt == p->n_traj && cnt > 0;
+        x.final_state = last ? r->final_state : nullptr;
+        if (!last) sp[j].flags &= ~uint32_t(QS_TRAJ_RETURN_STATE);
+        start += cnt;
+    }
+    std::vector<qs_status> status(n_states, QS_OK);
+    std::vector<std::string> message(n_states);
+    auto work = [&](int j) {
+        status[j] = qs_run_trajectories(states[j], c, &sp[j], &sr[j]);
+        if (status[j] != QS_OK) message[j] = g_last_error;
+    };
+    std::vector<std::thread> pool;
+    for (int j = 1; j < n_states; ++j) pool.emplace_back(work, j);
+    work(0);
+    for (auto &t : pool) t.join();
+    r->sweeps = r->gate_sweeps = r->gate_kernel_launches = r->zero_start_sweeps = 0;
+    r->gate_kernel_ms = 0.0;
+    for (int i = 0; i < 6; ++i) r->gate_k_launches[i] = 0;
+    for (int j = 0; j < n_states; ++j) {
+        r->sweeps += sr[j].sweeps;
+        r->gate_sweeps += sr[j].gate_sweeps;
+        r->gate_kernel_ms += sr[j].gate_kernel_ms;
+        r->gate_kernel_launches += sr[j].gate_kernel_launches;
+        r->zero_start_sweeps += sr[j].zero_start_sweeps;
+        for (int i = 0; i < 6; ++i) r->gate_k_launches[i] += sr[j].gate_k_launches[i];
+    }
+    r->host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int j = 0; j < n_states; ++j)
+        if (status[j] != QS_OK) return fail(status[j], message[j].c_str());
+    return QS_OK;
+}
+
 qs_status qs_fusion_plan(const qs_circuit *c, int max_fuse, int32_t *n_blocks_out,
                          int32_t *block_k, int32_t *block_targets, double *block_mats,
                          int32_t *op_block) {

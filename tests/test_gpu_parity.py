@@ -423,3 +423,34 @@ def test_driver_approx_noise_model(qs, orc, mode, shape, cycles, n_traj):
         mism = np.nonzero(got["samples"][0] != ref["samples"])[0]
         assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
     assert ties <= 1
+
+
+@pytest.mark.parametrize("n_states,n_traj", [(2, 9), (3, 2), (4, 13)])
+def test_driver_concurrent_states_match_one_state(qs, n_states, n_traj):
+    """qs_run_trajectories_concurrent splits the range over states running at
+    once; every output equals the single-state run of the same range."""
+    import torch
+    c = W.grid_circuit(4, 3, 8, p_dep=0.02, gamma=0.03, seed=5)
+    e0, e1 = W.readout_arrays(12, 0.02, 0.05)
+    kw = dict(seed=4, traj_offset=3, n_samples=7, p0to1=e0, p1to0=e1, return_state=True,
+              z_expect=True)
+    with qs.State(c.n) as one:
+        ref = qs.qs_run_trajectories(one.h, c, n_traj, **kw)
+    streams = [torch.cuda.Stream() for _ in range(n_states)]
+    states = [qs.State(c.n, hip_stream=st.cuda_stream) for st in streams]
+    try:
+        got = qs.qs_run_trajectories([st.h for st in states], c, n_traj, **kw)
+    finally:
+        for st in states:
+            st.close()
+    for key in ("samples", "choices", "paths", "n_slow", "z_expect"):
+        assert np.array_equal(got[key], ref[key]), key
+    assert np.array_equal(got["state"], ref["state"])
+    assert got["gate_sweeps"] == ref["gate_sweeps"]
+
+
+def test_driver_concurrent_rejects_repeated_state(qs):
+    c = W.grid_circuit(3, 4, 2, p_dep=0.01, seed=1)
+    with qs.State(c.n) as st:
+        with pytest.raises(qs.QsError):
+            qs.qs_run_trajectories([st.h, st.h], c, 4, seed=1)
