@@ -50,7 +50,7 @@ constexpr int kMaxTileBits = 14;
 // of a 13-bit tile's bits to the sweep's gates.
 constexpr int kTileLowBits = 4;
 constexpr int kDefaultTileBits = 13;  // tile sweeps when the caller asks for the default
-constexpr int kMaxTileGates = 48;
+constexpr int kMaxTileGates = 28;  // keeps TileArgs (a kernel argument) under 4 KiB
 constexpr int kTileMinQubits = 10;
 constexpr int kTileMatBudget = 4096;  // float2 of matrices staged per launch (32 KiB)
 
@@ -67,6 +67,7 @@ struct TileGate {
     int lofs;
     int pad;
     const float2 *mat;
+    int tab[kMaxTileBits];  // LDS byte offset per logical bit, filled by launch_apply_tile
 };
 
 struct TileArgs {

@@ -143,7 +143,7 @@ __device__ __forceinline__ void prio_for_remaining(int remaining) {
 // indices into a per-lane part computed once and a wave-uniform part
 // computed on the scalar unit.
 struct SwizzledTile {
-    __device__ __forceinline__ static int map(int x) {
+    __host__ __device__ __forceinline__ static int map(int x) {
         const int m = (((x >> 5) & 1) ? 30 : 0) ^ (((x >> 6) & 1) ? 27 : 0) ^ (((x >> 7) & 1) ? 23 : 0);
         return x ^ m;
     }
@@ -151,8 +151,41 @@ struct SwizzledTile {
 
 // Plain layout (the batched kernel's resident states and tiles).
 struct PlainTile {
-    __device__ __forceinline__ static int map(int x) { return x; }
+    __host__ __device__ __forceinline__ static int map(int x) { return x; }
 };
+
+// Address table of a K-qubit gate on a tile.  Logical bit b of an index in
+// the gate's frame is target b for b < K and, for b >= K, the (b - K)-th
+// non-target local bit in ascending order (the group-index bits).
+// tab[b] = 8 * map(1 << local position of logical bit b): the LDS byte offset
+// that bit contributes.  The layout map is linear over GF(2), so the byte
+// offset of any amplitude is the XOR of tab[] over its logical bits, and the
+// gate loops only XOR table entries.  lt must be ascending; entries beyond the
+// tile's width are unused.  Built on the host for the tile kernel's launches
+// and on the device by the batched kernel.
+template <int K, class L>
+__host__ __device__ inline void gate_tables(const int *lt, int *tab) {
+#pragma unroll
+    for (int b = 0; b < K; ++b) tab[b] = 8 * L::map(1 << lt[b]);
+#pragma unroll
+    for (int j = 0; j + K < kMaxTileBits; ++j) {
+        int p = j;  // the j-th free position: j plus the targets at or below it
+#pragma unroll
+        for (int b = 0; b < K; ++b)
+            if (lt[b] <= p) ++p;
+        tab[K + j] = 8 * L::map(1 << p);
+    }
+}
+
+// XOR of tab[first + j] over the set bits j < NBITS of x.
+template <int NBITS>
+__device__ __forceinline__ int tab_xor(const int *tab, int first, int x) {
+    int r = 0;
+#pragma unroll
+    for (int j = 0; j < NBITS; ++j)
+        if ((x >> j) & 1) r ^= tab[first + j];
+    return r;
+}
 
 // LDS accesses by byte offset: each address is one XOR of a per-lane and a
 // wave-uniform byte offset.
@@ -203,7 +236,7 @@ __device__ __forceinline__ void tile_gate_valu(float2 *__restrict__ sd, const fl
 // re-reads its own group, which is harmless: the reads precede the writes).
 template <int K, class L, int NT = kBlock>
 __device__ __forceinline__ void tile_gate_small(float2 *__restrict__ sd, const float2 *gm,
-                                                const int *lt, int tb) {
+                                                const int *lt, const int *tab, int tb) {
     constexpr int D = 1 << K;
     float2 u[D * D];
 #pragma unroll
@@ -229,28 +262,33 @@ __device__ __forceinline__ void tile_gate_small(float2 *__restrict__ sd, const f
         }
         return;
     }
+    // group index lane + 64 wave + NT it: logical bits K.. of the frame
     const int lane = threadIdx.x & 63, wave = wave_index();
-    const int lane_part = L::map(spread_index<K, int>(lane, lt));
+    int ab[D];  // byte offset of amplitude j of the lane's group, without the batch part
+    const int lane_part = tab_xor<6>(tab, K, lane);
+#pragma unroll
+    for (int j = 0; j < D; ++j) ab[j] = lane_part ^ tab_xor<K>(tab, 0, j);
     const int iters = 1 << (tb - K - NB);
-    int lb = lane_part ^ L::map(spread_index<K, int>(wave << 6, lt));
+    const int uw = tab_xor<NB - 6>(tab, K + 6, wave);
+    int ub = uw;
     float2 v[D];
 #pragma unroll
-    for (int j = 0; j < D; ++j) v[j] = sd[lb ^ off[j]];
+    for (int j = 0; j < D; ++j) v[j] = lds_get(sd, ab[j] ^ ub);
     for (int it = 0; it < iters; ++it) {
         prio_for_remaining(iters - it);
         const int itn = it + 1 < iters ? it + 1 : it;
-        const int lbn = lane_part ^ L::map(spread_index<K, int>((wave << 6) | (itn << NB), lt));
+        const int ubn = uw ^ tab_xor<kMaxTileBits - K - NB>(tab, K + NB, itn);
         float2 w[D];
 #pragma unroll
-        for (int j = 0; j < D; ++j) w[j] = sd[lbn ^ off[j]];
+        for (int j = 0; j < D; ++j) w[j] = lds_get(sd, ab[j] ^ ubn);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
             for (int l = 0; l < D; ++l) acc = cmac(acc, u[j * D + l], v[l]);
-            sd[lb ^ off[j]] = acc;
+            lds_put(sd, ab[j] ^ ub, acc);
         }
-        lb = lbn;
+        ub = ubn;
 #pragma unroll
         for (int j = 0; j < D; ++j) v[j] = w[j];
     }
@@ -311,35 +349,37 @@ __device__ __forceinline__ void stage_frag3(float *__restrict__ frag, const floa
 // the writes is safe.
 template <class L, int NT = kBlock>
 __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const float *__restrict__ frag,
-                                                const int *lt, int tb) {
+                                                const int *tab, int tb) {
     constexpr int W = NT / 64;
+    constexpr int LW = ilog2(W);
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int n = lane & 15, q = lane >> 4;
     const f32x4 *fp = reinterpret_cast<const f32x4 *>(frag + lane * 12);
     const f32x4 fa = fp[0], fb = fp[1], fs = fp[2];
-    // LDS byte offset of amplitude j of group 16 b + n.  The local index is
-    // spread(16 b + n) | offset(j); with j = 4 s + q (inputs) or 4 q + r
-    // (outputs) each part splits into a per-lane term (n, q, and s or r,
-    // which are unrolled) and a wave-uniform term (b), and the layout map is
-    // linear, so every access is one XOR of a lane register with a scalar.
-    const int lane_part = L::map(spread_index<4, int>(n, lt));
-    const int lin = 8 * (lane_part ^ L::map(((q & 1) << lt[0]) | ((q >> 1) << lt[1])));
-    const int lout = 8 * (lane_part ^ L::map(((q & 1) << lt[2]) | ((q >> 1) << lt[3])));
+    // LDS byte offset of amplitude j of group 16 b + n: the group index is
+    // logical bits 4.. of the gate's frame (n its low four), j its targets;
+    // with j = 4 s + q (inputs) or 4 q + r (outputs) the offset is a per-lane
+    // part (n, q, and the unrolled s or r) XOR a wave-uniform part (b).
+    const int lane_part = tab_xor<4>(tab, 4, n);
+    const int lin = lane_part ^ tab_xor<2>(tab, 0, q);
+    const int lout = lane_part ^ tab_xor<2>(tab, 2, q);
     int ain[4], aout[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        ain[s] = lin ^ (8 * L::map(((s & 1) << lt[2]) | ((s >> 1) << lt[3])));
-        aout[s] = lout ^ (8 * L::map(((s & 1) << lt[0]) | ((s >> 1) << lt[1])));
+        ain[s] = lin ^ tab_xor<2>(tab, 2, s);
+        aout[s] = lout ^ tab_xor<2>(tab, 0, s);
     }
     const int iters = (1 << (tb - 4 - 4)) / W;  // batches per wave: >= 1 needs tb >= 8 + log2 W
-    int ub = 8 * L::map(spread_index<4, int>(wave << 4, lt));
+    // batch b = wave + W it: its bits are logical bits 8.. (wave) and 8 + LW.. (it)
+    const int uw = tab_xor<LW>(tab, 8, wave);
+    int ub = uw;
     float2 v[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) v[s] = lds_get(sd, ain[s] ^ ub);
     for (int it = 0; it < iters; ++it) {
         prio_for_remaining(iters - it);
         const int itn = it + 1 < iters ? it + 1 : it;
-        const int ubn = 8 * L::map(spread_index<4, int>((wave + W * itn) << 4, lt));
+        const int ubn = uw ^ tab_xor<kMaxTileBits - 8 - LW>(tab, 8 + LW, itn);
         float2 w[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) w[s] = lds_get(sd, ain[s] ^ ubn);
@@ -370,30 +410,32 @@ __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const f
 // the next iteration's amplitudes are read ahead of this one's MFMAs.
 template <class L, int NT = kBlock>
 __device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const float *__restrict__ frag,
-                                                const int *lt, int tb) {
+                                                const int *tab, int tb) {
     constexpr int W = NT / 64;
+    constexpr int LW = ilog2(W);
     const int lane = threadIdx.x & 63, wave = wave_index();
     const int n = lane & 15, q = lane >> 4;
     const f32x4 afr = *reinterpret_cast<const f32x4 *>(frag + lane * 4);
-    // Offsets split into per-lane and wave-uniform terms as for k = 4: input
-    // amplitude 2 s + (q >> 1), component q & 1 (lane quarter q needs only
-    // that float); outputs 2 q and 2 q + 1.
-    const int lane_part = L::map(spread_index<3, int>(n, lt));
-    const int lin = (8 * (lane_part ^ L::map((q >> 1) << lt[0]))) | (4 * (q & 1));
-    const int lout = 8 * (lane_part ^ L::map(((q & 1) << lt[1]) | ((q >> 1) << lt[2])));
-    const int lout1 = lout ^ (8 * L::map(1 << lt[0]));
+    // Offsets split into per-lane and wave-uniform parts as for k = 4 (group
+    // bits are logical bits 3..): input amplitude 2 s + (q >> 1), component
+    // q & 1 (lane quarter q needs only that float); outputs 2 q and 2 q + 1.
+    const int lane_part = tab_xor<4>(tab, 3, n);
+    const int lin = (lane_part ^ ((q >> 1) ? tab[0] : 0)) | (4 * (q & 1));
+    const int lout = lane_part ^ tab_xor<2>(tab, 1, q);
+    const int lout1 = lout ^ tab[0];
     int ain[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) ain[s] = lin ^ (8 * L::map(((s & 1) << lt[1]) | ((s >> 1) << lt[2])));
+    for (int s = 0; s < 4; ++s) ain[s] = lin ^ tab_xor<2>(tab, 1, s);
     const int iters = (1 << (tb - 3 - 4)) / W;  // batches per wave: >= 1 needs tb >= 7 + log2 W
-    int ub = 8 * L::map(spread_index<3, int>(wave << 4, lt));
+    const int uw = tab_xor<LW>(tab, 7, wave);
+    int ub = uw;
     float v[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) v[s] = lds_getf(sd, ain[s] ^ ub);
     for (int it = 0; it < iters; ++it) {
         prio_for_remaining(iters - it);
         const int itn = it + 1 < iters ? it + 1 : it;
-        const int ubn = 8 * L::map(spread_index<3, int>((wave + W * itn) << 4, lt));
+        const int ubn = uw ^ tab_xor<kMaxTileBits - 7 - LW>(tab, 7 + LW, itn);
         float w[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) w[s] = lds_getf(sd, ain[s] ^ ubn);
@@ -516,19 +558,21 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
         __syncthreads();
         for (int gi = 0; gi < a.n_gates; ++gi) {
             const int k = a.g[gi].k;
-            int lt[kMaxGateQubits];
+            int lt[kMaxGateQubits], tab[kMaxTileBits];
 #pragma unroll
             for (int b = 0; b < kMaxGateQubits; ++b) lt[b] = a.g[gi].lt[b];
+#pragma unroll
+            for (int b = 0; b < kMaxTileBits; ++b) tab[b] = a.g[gi].tab[b];
             switch (k) {
-                case 1: tile_gate_small<1, SwizzledTile, NT>(sd, a.g[gi].mat, lt, TB); break;
-                case 2: tile_gate_small<2, SwizzledTile, NT>(sd, a.g[gi].mat, lt, TB); break;
+                case 1: tile_gate_small<1, SwizzledTile, NT>(sd, a.g[gi].mat, lt, tab, TB); break;
+                case 2: tile_gate_small<2, SwizzledTile, NT>(sd, a.g[gi].mat, lt, tab, TB); break;
                 case 3:
                     tile_gate_mfma3<SwizzledTile, NT>(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs),
-                                                      lt, TB);
+                                                      tab, TB);
                     break;
                 case 4:
                     tile_gate_mfma4<SwizzledTile, NT>(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs),
-                                                      lt, TB);
+                                                      tab, TB);
                     break;
                 default:
                     if constexpr (K5) tile_gate_valu<5, SwizzledTile, NT>(sd, sm + a.g[gi].lofs, lt, TB);
@@ -617,21 +661,25 @@ __global__ __launch_bounds__(64) void select_branch(SelectArgs a) {
 __device__ __forceinline__ void batched_gate(float2 *__restrict__ sd, float *__restrict__ frag,
                                              const BatchGate &g, const float2 *__restrict__ m,
                                              int tb) {
-    int lt[kMaxGateQubits];
+    int lt[kMaxGateQubits], tab[kMaxTileBits];
 #pragma unroll
     for (int b = 0; b < kMaxGateQubits; ++b) lt[b] = g.lt[b];
     if (g.k == 1) {
-        tile_gate_small<1, PlainTile>(sd, m, lt, tb);
+        gate_tables<1, PlainTile>(lt, tab);
+        tile_gate_small<1, PlainTile>(sd, m, lt, tab, tb);
     } else if (g.k == 2) {
-        tile_gate_small<2, PlainTile>(sd, m, lt, tb);
+        gate_tables<2, PlainTile>(lt, tab);
+        tile_gate_small<2, PlainTile>(sd, m, lt, tab, tb);
     } else if (g.k == 3 && tb >= 10) {
+        gate_tables<3, PlainTile>(lt, tab);
         stage_frag3(frag, m);
         __syncthreads();
-        tile_gate_mfma3<PlainTile>(sd, frag, lt, tb);
+        tile_gate_mfma3<PlainTile>(sd, frag, tab, tb);
     } else if (g.k == 4 && tb >= 10) {
+        gate_tables<4, PlainTile>(lt, tab);
         stage_frag4(frag, m);
         __syncthreads();
-        tile_gate_mfma4<PlainTile>(sd, frag, lt, tb);
+        tile_gate_mfma4<PlainTile>(sd, frag, tab, tb);
     } else {
         const int dd = 1 << (2 * g.k);
         float2 *mm = reinterpret_cast<float2 *>(frag);
@@ -1355,8 +1403,20 @@ hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t 
             if (g.lt[b] < 0 || g.lt[b] >= a.tb || (b > 0 && g.lt[b] <= g.lt[b - 1]))
                 return hipErrorInvalidValue;
     }
-    if (n <= 31) return apply_tile_idx<uint32_t>(amp, n, a, st);
-    return apply_tile_idx<uint64_t>(amp, n, a, st);
+    // each gate's address table for the swizzled tile layout
+    TileArgs b = a;
+    for (int gi = 0; gi < b.n_gates; ++gi) {
+        TileGate &g = b.g[gi];
+        switch (g.k) {
+            case 1: gate_tables<1, SwizzledTile>(g.lt, g.tab); break;
+            case 2: gate_tables<2, SwizzledTile>(g.lt, g.tab); break;
+            case 3: gate_tables<3, SwizzledTile>(g.lt, g.tab); break;
+            case 4: gate_tables<4, SwizzledTile>(g.lt, g.tab); break;
+            default: gate_tables<5, SwizzledTile>(g.lt, g.tab); break;
+        }
+    }
+    if (n <= 31) return apply_tile_idx<uint32_t>(amp, n, b, st);
+    return apply_tile_idx<uint64_t>(amp, n, b, st);
 }
 
 hipError_t launch_norm(const float2 *amp, int n, double *partials, double *out_dev,
