@@ -8,12 +8,17 @@ every qubit after every moment, readout flips 2e-2; complex64 state, FP64
 norms, one shot per trajectory, delayed inner-product branch selection.
 A step is one batch of trajectories (default 1000) through the whole path:
 per-trajectory draws and classification, fused gate sweeps, in-place inner
-products where needed, and sampling with readout error.
+products where needed, and sampling with readout error.  The step's
+trajectories are split over --streams states (default 2), each on its own
+stream and host thread, run at once (qs_run_trajectories_concurrent): one
+state's sweep ramps are filled by the other's gate work.
 
-Prints one JSON line with the throughput, the fused-gate kernel's achieved
-bandwidth against the HBM peak (timed with HIP events on the state's stream
-inside the timed region), the conventional (naive) method's throughput on a
-few trajectories, and the CPU oracle's rate on a bounded sample.
+Prints one JSON line with the throughput, the fused-gate sweep's achieved
+rate against its binding roofline (the sweep time is the span during which
+at least one sweep ran, from HIP-event brackets on the states' streams inside
+the timed region), the same step on one state, the conventional (naive)
+method's throughput on a few trajectories, and the CPU oracle's rate on a
+bounded sample.
 """
 
 from __future__ import annotations
@@ -128,9 +133,9 @@ def main() -> int:
     ap.add_argument("--max-fuse", type=int, default=0)
     ap.add_argument("--tile-bits", type=int, default=0,
                     help="LDS tile sweep width (0 = library default, 1 = one pass per fused gate)")
-    ap.add_argument("--concurrent-streams", type=int, default=2,
-                    help="also time one step with the trajectories split over this many states "
-                         "on their own streams, run at once (0 or 1 = skip)")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="states (each on its own stream, driven by its own host thread) that a "
+                         "step's trajectories are split over and run on at once")
     ap.add_argument("--inplace-traj", type=int, default=3,
                     help="trajectories timed with the conventional rule and in-place inner products")
     ap.add_argument("--naive-traj", type=int, default=3,
@@ -175,13 +180,18 @@ def main() -> int:
     c = w.circuit
     n = c.n
     mc = qs.MarshalledCircuit(c)
-    stream = torch.cuda.Stream()
-    buf = torch.zeros(1 << n, dtype=torch.complex64, device="cuda")
-    st = qs.State(n, buf.data_ptr(), buf.numel() * 8, stream.cuda_stream)
+    n_streams = max(1, args.streams)
+    streams = [torch.cuda.Stream() for _ in range(n_streams)]
+    bufs = [torch.zeros(1 << n, dtype=torch.complex64, device="cuda") for _ in range(n_streams)]
+    states = [qs.State(n, b.data_ptr(), b.numel() * 8, sx.cuda_stream) for b, sx in zip(bufs, streams)]
+    st, stream = states[0], streams[0]
+    handles = [x.h for x in states]
 
-    def step(offset: int, timed: bool, mode=qs.QS_KRAUS_DELAYED, n_traj=None):
+    def step(offset: int, timed: bool, mode=qs.QS_KRAUS_DELAYED, n_traj=None, all_states=True):
+        # a step: the trajectories split over every state, run at once
+        hs = handles if (all_states and n_streams > 1) else st.h
         return qs.qs_run_trajectories(
-            st.h, c, n_traj or args.traj, seed=w.seed, traj_offset=offset, mode=mode,
+            hs, c, n_traj or args.traj, seed=w.seed, traj_offset=offset, mode=mode,
             max_fuse=args.max_fuse, tile_bits=args.tile_bits, n_samples=w.n_samples,
             p0to1=w.e0, p1to0=w.e1,
             record_choices=False, time_kernels=timed, marshalled=mc)
@@ -195,7 +205,8 @@ def main() -> int:
 
     trace_marker(qs, st)  # the timed region begins
     torch.cuda.synchronize()
-    stream.synchronize()
+    for sx in streams:
+        sx.synchronize()
     t0 = time.perf_counter()
     gate_ms = 0.0
     gate_launches = 0
@@ -214,7 +225,8 @@ def main() -> int:
         slow += int(r["n_slow"].sum())
         k_hist = [a + b for a, b in zip(k_hist, r["gate_k_launches"])]
         log(f"step {s}: {r['host_seconds']:.3f} s")
-    stream.synchronize()
+    for sx in streams:
+        sx.synchronize()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     trace_marker(qs, st)  # the timed region has ended
@@ -248,6 +260,9 @@ def main() -> int:
         "kernel": "fused-gate sweep (apply_tile / apply_direct): one read + one write of the state, "
                   "the sweep's fused blocks applied in LDS",
         "avg_launch_us": avg_gate_s * 1e6,
+        "avg_launch_basis": ("time during which at least one sweep ran (union of the streams' "
+                             "HIP-event brackets) / launches" if n_streams > 1 else
+                             "HIP-event brackets of back-to-back sweeps / launches"),
         "launches": gate_launches,
         "zero_start_launches": zero_start,
     }
@@ -264,7 +279,7 @@ def main() -> int:
     naive = None
     if args.naive_traj > 0:
         t1 = time.perf_counter()
-        rn = step(20_000_000, False, mode=qs.QS_KRAUS_NAIVE, n_traj=args.naive_traj)
+        rn = step(20_000_000, False, mode=qs.QS_KRAUS_NAIVE, n_traj=args.naive_traj, all_states=False)
         dtn = time.perf_counter() - t1
         naive = {"value": args.naive_traj / dtn, "unit": "trajectories/s",
                  "trajectories": args.naive_traj,
@@ -274,49 +289,32 @@ def main() -> int:
     inplace = None
     if args.inplace_traj > 0:
         t1 = time.perf_counter()
-        ri = step(30_000_000, False, mode=qs.QS_KRAUS_CONVENTIONAL_INPLACE, n_traj=args.inplace_traj)
+        ri = step(30_000_000, False, mode=qs.QS_KRAUS_CONVENTIONAL_INPLACE, n_traj=args.inplace_traj,
+                  all_states=False)
         dti = time.perf_counter() - t1
         inplace = {"value": args.inplace_traj / dti, "unit": "trajectories/s",
                    "trajectories": args.inplace_traj,
                    "sweeps_per_traj": ri["sweeps"] / args.inplace_traj}
         log(f"conventional, in-place inner products: {inplace['value']:.3f} traj/s")
 
-    concurrent = None
-    if args.concurrent_streams > 1:
-        # the same step with the range split over several states run at once
-        extra = []
-        for _ in range(args.concurrent_streams - 1):
-            sx = torch.cuda.Stream()
-            bx = torch.zeros(1 << n, dtype=torch.complex64, device="cuda")
-            extra.append((qs.State(n, bx.data_ptr(), bx.numel() * 8, sx.cuda_stream), bx, sx))
-        handles = [st.h] + [e[0].h for e in extra]
-
-        def cstep(offset: int):
-            return qs.qs_run_trajectories(
-                handles, c, args.traj, seed=w.seed, traj_offset=offset, max_fuse=args.max_fuse,
-                tile_bits=args.tile_bits, n_samples=w.n_samples, p0to1=w.e0, p1to0=w.e1,
-                record_choices=False, marshalled=mc)
-        trace_marker(qs, st)  # concurrent launches begin
-        cstep(40_000_000)  # warm the extra states
+    single = None
+    if n_streams > 1:
+        # the same step on one state, for comparison (kernels untimed)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        for s_ in range(args.steps):
-            cstep(50_000_000 + s_ * args.traj)
-        torch.cuda.synchronize()
-        dtc = time.perf_counter() - t1
-        concurrent = {"streams": args.concurrent_streams,
-                      "value": args.steps * args.traj / dtc, "unit": "trajectories/s",
-                      "ms_per_step": 1e3 * dtc / args.steps}
-        log(f"{args.concurrent_streams} concurrent states: {concurrent['value']:.1f} traj/s")
-        for e in extra:
-            e[0].close()
+        step(60_000_000, False, all_states=False)
+        stream.synchronize()
+        dts = time.perf_counter() - t1
+        single = {"value": args.traj / dts, "unit": "trajectories/s", "steps": 1}
+        log(f"one state: {single['value']:.1f} traj/s")
 
     cpu = None
     if args.cpu_cycles > 0:
         log("timing the CPU oracle sample ...")
         cpu = cpu_baseline(w, args.cpu_cycles)
 
-    st.close()
+    for x in states:
+        x.close()
     out = {
         "metric": "trajectories/s at 24q depth-20 noisy (HBM GB/s %peak); served p50/p99 latency",
         "value": value,
@@ -338,12 +336,12 @@ def main() -> int:
             "mode": "delayed",
             "max_fuse": args.max_fuse or 4,
             "tile_bits": args.tile_bits or 13,
-            "parallelism": "none (1 GPU)",
+            "parallelism": f"none (1 GPU); {n_streams} trajectory streams",
         },
         "roofline": roofline,
         "hbm": hbm_side,
         "cpu_baseline": cpu,
-        "concurrent": concurrent,
+        "one_stream": single,
         "naive": naive,
         "speedup_vs_naive": (value / naive["value"]) if naive else None,
         "conventional_inplace": inplace,

@@ -124,7 +124,9 @@ typedef struct {
     int64_t sweeps;         /* out: kernel passes over the state (gate blocks + reductions) */
     int64_t gate_sweeps;    /* out: fused-gate passes only */
     double host_seconds;    /* out: wall time of the call */
-    double gate_kernel_ms;  /* out (QS_TRAJ_TIME_KERNELS): summed fused-gate kernel time */
+    double gate_kernel_ms;  /* out (QS_TRAJ_TIME_KERNELS): time during which the call's fused-gate
+                               sweeps ran (HIP events bracketing each run of back-to-back
+                               sweeps; with several streams, the union of their brackets) */
     int64_t gate_kernel_launches; /* out (QS_TRAJ_TIME_KERNELS): launches timed */
     int64_t gate_k_launches[6];   /* out: fused-gate launches by width k = 1..5 (index k) */
     int64_t zero_start_sweeps;    /* out: gate sweeps that began from |0...0> written on chip and
@@ -257,7 +259,8 @@ qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_par
  * one qs_run_trajectories call over the same range.  Results go to r's
  * arrays at each trajectory's position; final_state (QS_TRAJ_RETURN_STATE)
  * is the range's last trajectory; the counters are sums over the chunks
- * (gate_kernel_ms sums the streams' kernel time, which overlaps).
+ * (gate_kernel_ms is the union over the streams: time during which at
+ * least one of the call's sweeps was running).
  * states: 1..16 distinct handles, each with n_qubits equal to the
  * circuit's.  Errors: as qs_run_trajectories (the first failing chunk's). */
 qs_status qs_run_trajectories_concurrent(qs_state *states, int n_states, const qs_circuit *c,

@@ -928,6 +928,10 @@ struct KernelTimer {
     int cur = 0;
     double total_ms = 0.0;
     int64_t count = 0;
+    // optional: every bracket as (start, end) in ms after `ref` (a completed
+    // event), so that brackets of several streams can be merged
+    hipEvent_t ref = nullptr;
+    std::vector<std::pair<double, double>> *intervals = nullptr;
 
     ~KernelTimer() {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -946,6 +950,11 @@ struct KernelTimer {
         float ms = 0.f;
         QS_HIP(s, hipEventElapsedTime(&ms, ev[2 * slot], ev[2 * slot + 1]));
         total_ms += ms;
+        if (ref && intervals) {
+            float t0 = 0.f;
+            QS_HIP(s, hipEventElapsedTime(&t0, ref, ev[2 * slot]));
+            intervals->emplace_back(double(t0), double(t0) + double(ms));
+        }
         count += launches[slot];
         launches[slot] = 0;
         return QS_OK;
@@ -1132,9 +1141,12 @@ struct Runner {
     int64_t z_first_traj = 0;
     std::vector<double> z_host;
 
-    Runner(qs_state s_, const CircuitModel &m_, const qs_traj_params &p_, qs_traj_result &r_)
+    Runner(qs_state s_, const CircuitModel &m_, const qs_traj_params &p_, qs_traj_result &r_,
+           hipEvent_t ref = nullptr, std::vector<std::pair<double, double>> *intervals = nullptr)
         : s(s_), m(m_), p(p_), res(r_) {
         max_fuse = p.max_fuse > 0 ? p.max_fuse : kDefaultFuse;
+        timer.ref = ref;
+        timer.intervals = intervals;
     }
 
     qs_status plan_delayed() {
@@ -1695,8 +1707,13 @@ struct Runner {
 
 }  // namespace
 
-qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_params *p,
-                              qs_traj_result *r) {
+namespace {
+
+// qs_run_trajectories, optionally reporting every timed bracket of sweeps as
+// an interval after the completed event `ref`.
+qs_status run_trajectories_impl(qs_state s, const qs_circuit *c, const qs_traj_params *p,
+                                qs_traj_result *r, hipEvent_t ref,
+                                std::vector<std::pair<double, double>> *intervals) {
     const auto t0 = std::chrono::steady_clock::now();
     QS_CHECK(check_handle(s));
     if (!c || !p || !r) return fail(QS_ERR_INVALID_ARGUMENT, "null argument");
@@ -1725,10 +1742,36 @@ qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_par
     r->gate_kernel_launches = 0;
     for (int i = 0; i < 6; ++i) r->gate_k_launches[i] = 0;
     r->zero_start_sweeps = 0;
-    Runner run(s, m, *p, *r);
+    Runner run(s, m, *p, *r, ref, intervals);
     const qs_status st = run.run();
     r->host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return st;
+}
+
+// Total length of the union of intervals.
+double union_length(std::vector<std::pair<double, double>> iv) {
+    std::sort(iv.begin(), iv.end());
+    double total = 0.0, a = 0.0, b = 0.0;
+    bool open = false;
+    for (const auto &x : iv) {
+        if (!open || x.first > b) {
+            if (open) total += b - a;
+            a = x.first;
+            b = x.second;
+            open = true;
+        } else if (x.second > b) {
+            b = x.second;
+        }
+    }
+    if (open) total += b - a;
+    return total;
+}
+
+}  // namespace
+
+qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_params *p,
+                              qs_traj_result *r) {
+    return run_trajectories_impl(s, c, p, r, nullptr, nullptr);
 }
 
 qs_status qs_run_trajectories_concurrent(qs_state *states, int n_states, const qs_circuit *c,
@@ -1772,8 +1815,18 @@ qs_status qs_run_trajectories_concurrent(qs_state *states, int n_states, const q
     }
     std::vector<qs_status> status(n_states, QS_OK);
     std::vector<std::string> message(n_states);
+    // with kernel timing, every stream's sweep brackets are placed on one
+    // time axis (a reference event, completed before any of them starts)
+    const bool timing = (p->flags & QS_TRAJ_TIME_KERNELS) != 0;
+    hipEvent_t ref = nullptr;
+    std::vector<std::vector<std::pair<double, double>>> iv(n_states);
+    if (timing) {
+        QS_HIP(states[0], hipEventCreate(&ref));
+        QS_HIP(states[0], hipEventRecord(ref, states[0]->st));
+        QS_HIP(states[0], hipEventSynchronize(ref));
+    }
     auto work = [&](int j) {
-        status[j] = qs_run_trajectories(states[j], c, &sp[j], &sr[j]);
+        status[j] = run_trajectories_impl(states[j], c, &sp[j], &sr[j], ref, timing ? &iv[j] : nullptr);
         if (status[j] != QS_OK) message[j] = g_last_error;
     };
     std::vector<std::thread> pool;
@@ -1790,6 +1843,13 @@ qs_status qs_run_trajectories_concurrent(qs_state *states, int n_states, const q
         r->gate_kernel_launches += sr[j].gate_kernel_launches;
         r->zero_start_sweeps += sr[j].zero_start_sweeps;
         for (int i = 0; i < 6; ++i) r->gate_k_launches[i] += sr[j].gate_k_launches[i];
+    }
+    if (timing) {
+        // time during which at least one of the call's sweeps was running
+        std::vector<std::pair<double, double>> all;
+        for (const auto &v : iv) all.insert(all.end(), v.begin(), v.end());
+        r->gate_kernel_ms = union_length(std::move(all));
+        (void)hipEventDestroy(ref);
     }
     r->host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     for (int j = 0; j < n_states; ++j)

@@ -454,3 +454,22 @@ def test_driver_concurrent_rejects_repeated_state(qs):
     with qs.State(c.n) as st:
         with pytest.raises(qs.QsError):
             qs.qs_run_trajectories([st.h, st.h], c, 4, seed=1)
+
+
+def test_driver_concurrent_kernel_timing(qs):
+    """With kernel timing, a concurrent call reports the span during which
+    its sweeps ran: positive, within the call's wall time, and no more than
+    the single-state call's sweep time on the same range by a wide margin."""
+    import torch
+    c = W.grid_circuit(4, 4, 10, p_dep=0.01, gamma=0.01, seed=2)
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    states = [qs.State(c.n, hip_stream=st.cuda_stream) for st in streams]
+    try:
+        r = qs.qs_run_trajectories([s_.h for s_ in states], c, 12, seed=3, time_kernels=True)
+        one = qs.qs_run_trajectories(states[0].h, c, 12, seed=3, time_kernels=True)
+    finally:
+        for s_ in states:
+            s_.close()
+    assert r["gate_kernel_launches"] == one["gate_kernel_launches"] > 0
+    assert 0.0 < r["gate_kernel_ms"] <= 1e3 * r["host_seconds"]
+    assert r["gate_kernel_ms"] < 2.0 * one["gate_kernel_ms"]
