@@ -1040,57 +1040,62 @@ __device__ __forceinline__ double wave_inclusive_scan(double x) {
     return x;
 }
 
+// Inclusive prefix of the block sums in index order, tile by tile: a tile
+// of kScanThreads * kScanPer sums is loaded coalesced into LDS (one pad slot
+// per kScanPer, so that each work-item's run of kScanPer consecutive sums
+// sits on distinct banks), each work-item adds its run, one workgroup scan
+// of the run totals (wavefronts in order) gives every run's offset, the runs'
+// prefixes go back to LDS and out coalesced, and the tile total carries into
+// the next tile.  Fixed order throughout.
+constexpr int kScanPer = 8;
+__device__ __forceinline__ int scan_slot(int i) { return i + i / kScanPer; }
+
 __global__ __launch_bounds__(kScanThreads) void sample_scan(const double *__restrict__ sums,
                                                             int64_t nb, double *__restrict__ incl,
                                                             double *__restrict__ norm) {
-    // Each work-item owns a contiguous chunk of block sums (nb is a power of
-    // two: chunks of nb / kScanThreads, or one sum for the first nb work-items
-    // of a small state): chunk total in index order, one workgroup scan of
-    // the totals (wavefronts in order), then the chunk's running prefix.
+    constexpr int kTile = kScanThreads * kScanPer;
+    __shared__ double tile[kTile + kTile / kScanPer];
     __shared__ double wave_tot[kScanThreads / 64];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const int64_t chunk = nb >= kScanThreads ? nb / kScanThreads : 1;
-    const int64_t lo = int64_t(t) * chunk;
-    const bool active = lo < nb;
-    double tot = 0.0;
-    if (active) {
-        if (chunk >= 8) {
-            for (int64_t b = lo; b < lo + chunk; b += 8) {
-                double v[8];
+    double carry = 0.0;
+    for (int64_t base = 0; base < nb; base += kTile) {
+        const int len = nb - base < kTile ? int(nb - base) : kTile;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = sums[b + j];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) tot += v[j];
-            }
-        } else {
-            for (int64_t b = lo; b < lo + chunk; ++b) tot += sums[b];
+        for (int j = 0; j < kScanPer; ++j) {
+            const int i = j * kScanThreads + t;
+            tile[scan_slot(i)] = i < len ? sums[base + i] : 0.0;
         }
+        __syncthreads();
+        double v[kScanPer], tot = 0.0;
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) {
+            v[j] = tile[scan_slot(t * kScanPer + j)];
+            tot += v[j];
+        }
+        const double inc = wave_inclusive_scan(tot);
+        if (lane == 63) wave_tot[wave] = inc;
+        __syncthreads();
+        double before = 0.0, all = 0.0;
+        for (int w = 0; w < kScanThreads / 64; ++w) {
+            if (w < wave) before += wave_tot[w];
+            all += wave_tot[w];
+        }
+        double run = carry + before + (inc - tot);
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) {
+            run += v[j];
+            tile[scan_slot(t * kScanPer + j)] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kScanPer; ++j) {
+            const int i = j * kScanThreads + t;
+            if (i < len) incl[base + i] = tile[scan_slot(i)];
+        }
+        carry += all;
+        __syncthreads();  // the tile and wave totals are reused
     }
-    const double inc = wave_inclusive_scan(tot);
-    if (lane == 63) wave_tot[wave] = inc;
-    __syncthreads();
-    double before = 0.0;
-    for (int w = 0; w < wave; ++w) before += wave_tot[w];
-    if (t == kScanThreads - 1) *norm = before + inc;
-    if (!active) return;
-    double run = before + (inc - tot);  // exclusive prefix of this chunk
-    if (chunk >= 8) {
-        for (int64_t b = lo; b < lo + chunk; b += 8) {
-            double v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = sums[b + j];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                run += v[j];
-                incl[b + j] = run;
-            }
-        }
-    } else {
-        for (int64_t b = lo; b < lo + chunk; ++b) {
-            run += sums[b];
-            incl[b] = run;
-        }
-    }
+    if (t == 0) *norm = carry;
 }
 
 // One wavefront per sample: find the block by binary search over the block
