@@ -130,6 +130,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--traj", type=int, default=1000, help="trajectories per step")
     ap.add_argument("--p-dep", type=float, default=1e-3)
+    ap.add_argument("--rows", type=int, default=4, help="grid rows (the headline workload is 4 x 6)")
+    ap.add_argument("--cols", type=int, default=6, help="grid columns")
     ap.add_argument("--max-fuse", type=int, default=0)
     ap.add_argument("--tile-bits", type=int, default=0,
                     help="LDS tile sweep width (0 = library default, 1 = one pass per fused gate)")
@@ -176,7 +178,7 @@ def main() -> int:
         return bench_phase_damping(args)
     if args.workload == "copy":
         return bench_copy(args)
-    w = W.grid24_workload(p_dep=args.p_dep)
+    w = W.grid24_workload(p_dep=args.p_dep, rows=args.rows, cols=args.cols)
     c = w.circuit
     n = c.n
     mc = qs.MarshalledCircuit(c)
@@ -241,7 +243,7 @@ def main() -> int:
     alg_bytes = 2 * state_bytes * gate_launches - state_bytes * zero_start
     bytes_per_launch = alg_bytes / max(gate_launches, 1)
     achieved = alg_bytes / (gate_ms / 1e3) / 1e9 if gate_ms > 0 else 0.0
-    traffic = measured_traffic()
+    traffic = measured_traffic() if (args.rows, args.cols) == (4, 6) else None  # profiled at 4 x 6
     # complex mat-vec flops of the fused blocks applied (8 * 2^k per amplitude, Section 3.1)
     flops = sum(k_hist[k] * (8 << k) for k in range(1, 6)) * float(1 << n)
     flops_tf = flops / (gate_ms / 1e3) / 1e12 if gate_ms > 0 else 0.0
