@@ -537,7 +537,10 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
     // of every tile; the wait for the prefetch at the next loop head covers
     // memory operations issued a whole gate phase earlier.
     // LDS index of local index 2 threadIdx.x + e + 2 NT r: the map leaves the
-    // r part alone and maps bit 0 to itself, so it is tid_l ^ e + (r << NB + 1)
+    // r part alone and flipping bit 0 of an index flips bit 0 of its image,
+    // so it is tid_l ^ e + (r << NB + 1).  tid_l itself may be odd (columns 27
+    // and 23 of the map set bit 0), so a pair is adjacent but not always in
+    // order: it is not one 16-byte LDS access.
     const int tid_l = SwizzledTile::map(int(threadIdx.x) << 1);
     float4 o[R];
     Idx prev_base = 0;
