@@ -39,13 +39,24 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_2111_02396_amd", "csrc", "qs_kernels.h
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "apply_tile_grid24_counters.md")
 
 
+def kernel_source_digest() -> str:
+    """SHA-256 prefix of the kernel source with comments and whitespace
+    removed (a comment edit leaves the kernels, and their counters, as they were)."""
+    import hashlib
+    import re
+
+    src = open(KERNEL_SOURCE, encoding="utf-8").read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = " ".join(src.split())
+    return hashlib.sha256(src.encode()).hexdigest()[:16]
+
+
 def measured_traffic():
     """HBM bytes per sweep launch from the committed counter summary, only if
     it was taken on the kernel source that is built now (else None)."""
-    import hashlib
-
     try:
-        digest = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+        digest = kernel_source_digest()
         text = open(COUNTER_SUMMARY).read()
     except OSError:
         return None
