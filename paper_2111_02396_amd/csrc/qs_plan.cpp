@@ -442,10 +442,10 @@ std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, 
 }
 
 double block_cost(int k) {
-    // relative cost of one block applied to a tile in LDS by width (measured
-    // on gfx950 with 13-bit tiles: barrier and read latency make one-qubit
-    // blocks cost about 40 % of a four-qubit one)
-    static const double c[6] = {0.0, 7.0, 8.5, 12.6, 17.6, 45.0};
+    // relative cost of one block applied to a tile in LDS by width: µs per
+    // 2^24 amplitudes, measured on gfx950 with 13-bit tiles (barrier and read
+    // latency make one-qubit blocks cost about 40 % of a four-qubit one)
+    static const double c[6] = {0.0, 5.8, 9.1, 10.7, 14.5, 45.0};
     return k >= 1 && k <= 5 ? c[k] : 1e9;
 }
 
