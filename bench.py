@@ -166,8 +166,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU; multi-GPU runs are not part of this build "
-              "(trajectories shard by index range across GPUs; see the design notes)",
+        print("bench.py runs on one GPU only (--gpus 1): the library has no multi-GPU path; "
+              "trajectories would shard by index range, one range per GPU",
               file=sys.stderr)
         return 2
 
