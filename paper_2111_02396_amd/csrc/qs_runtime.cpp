@@ -44,6 +44,7 @@ struct PendingOp {
 
 struct qs_state_s {
     int n = 0;
+    int device = 0;             // the HIP device current when the state was created
     float2 *amp = nullptr;      // where the amplitudes are now
     float2 *home = nullptr;     // where they live between calls
     bool owns_home = false;
@@ -532,6 +533,7 @@ qs_status qs_create_state(int n_qubits, void *device_buf, size_t buf_bytes, void
         return fail(QS_ERR_INVALID_ARGUMENT, "buffer not 16-byte aligned");
     auto *s = new qs_state_s();
     s->n = n_qubits;
+    if (hipGetDevice(&s->device) != hipSuccess) s->device = 0;
     s->st = static_cast<hipStream_t>(hip_stream);
     if (device_buf) {
         s->home = static_cast<float2 *>(device_buf);
@@ -1826,12 +1828,24 @@ qs_status qs_run_trajectories_concurrent(qs_state *states, int n_states, const q
         QS_HIP(states[0], hipEventSynchronize(ref));
     }
     auto work = [&](int j) {
+        // a new host thread starts on device 0: work on the state's device
+        if (hipSetDevice(states[j]->device) != hipSuccess) {
+            status[j] = QS_ERR_DEVICE;
+            message[j] = "cannot select the state's device";
+            return;
+        }
         status[j] = run_trajectories_impl(states[j], c, &sp[j], &sr[j], ref, timing ? &iv[j] : nullptr);
         if (status[j] != QS_OK) message[j] = g_last_error;
     };
     std::vector<std::thread> pool;
     for (int j = 1; j < n_states; ++j) pool.emplace_back(work, j);
-    work(0);
+    {
+        // chunk 0 runs on the calling thread, whose current device is restored
+        int prev = 0;
+        const bool had = hipGetDevice(&prev) == hipSuccess;
+        work(0);
+        if (had) (void)hipSetDevice(prev);
+    }
     for (auto &t : pool) t.join();
     r->sweeps = r->gate_sweeps = r->gate_kernel_launches = r->zero_start_sweeps = 0;
     r->gate_kernel_ms = 0.0;
