@@ -156,7 +156,8 @@ def main() -> int:
     ap.add_argument("--cpu-cycles", type=int, default=1,
                     help="cycles of trajectory 0 timed on the oracle (0 = skip)")
     ap.add_argument("--workload", default="grid24",
-                    choices=["grid24", "batched", "serving", "phase_damping", "copy"],
+                    choices=["grid24", "chain12", "grid28", "batched", "serving", "phase_damping",
+                             "copy"],
                     help="grid24 (default): the headline line; batched / serving / phase_damping: "
                          "the other forms; copy: a plain device copy of a 24-qubit state, the "
                          "reference for calibrating HBM byte counters")
@@ -183,6 +184,10 @@ def main() -> int:
     torch.cuda.set_device(0)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "chain12":
+        return bench_chain12(args)
+    if args.workload == "grid28":
+        return bench_grid28(args)
     if args.workload == "serving":
         return bench_serving(args)
     if args.workload == "phase_damping":
@@ -363,6 +368,111 @@ def main() -> int:
         "sweeps_per_traj": sweeps / total_traj,
         "slow_paths_per_traj": slow / total_traj,
         "gate_width_histogram": k_hist[1:],
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_chain12(args) -> int:
+    """The 12-qubit chain (depth 20, depolarizing 1e-3 after every gate): 100
+    trajectories x 1000 samples.  The 32 KiB state lives in LDS, so the run is
+    latency bound: one persistent launch (qs_run_batched) for the whole step,
+    and the same trajectories one qs_run_trajectories call each beside it."""
+    import torch
+
+    import paper_2111_02396_amd as qs
+    import workloads as W
+
+    w = W.chain12_workload()
+    prepared = qs.PreparedBatch([w], record_choices=False)
+    for _ in range(args.warmup):
+        qs.qs_run_batched(prepared)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(args.steps):
+        _, stats = qs.qs_run_batched(prepared, time_kernels=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = args.steps * w.n_traj / dt
+    mc = qs.MarshalledCircuit(w.circuit)
+    with qs.State(w.circuit.n) as st:
+        qs.qs_run_trajectories(st.h, w.circuit, 4, seed=w.seed, n_samples=w.n_samples,
+                               max_fuse=w.max_fuse, record_choices=False, marshalled=mc)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        qs.qs_run_trajectories(st.h, w.circuit, w.n_traj, seed=w.seed, n_samples=w.n_samples,
+                               max_fuse=w.max_fuse, record_choices=False, marshalled=mc)
+        dt1 = time.perf_counter() - t1
+    out = {
+        "metric": "trajectories/s, 12-qubit chain depth 20, 1000 samples each",
+        "value": value, "unit": "trajectories/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": w.name, "trajectories_per_step": w.n_traj,
+                   "samples_per_trajectory": w.n_samples, "max_fuse": w.max_fuse},
+        "us_per_trajectory": 1e6 * dt / (args.steps * w.n_traj),
+        "samples_per_s": value * w.n_samples,
+        "kernel_ms": stats["kernel_ms"],
+        "one_call_per_range": {"value": w.n_traj / dt1, "unit": "trajectories/s",
+                               "form": "qs_run_trajectories over the 100 trajectories"},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_grid28(args) -> int:
+    """The 28-qubit noiseless 4 x 7 grid (depth 20, blocks of <= 4 qubits): one
+    2 GiB state evolved from |0...0>, then 10^5 samples; sweep time and rate
+    against the rooflines."""
+    import torch
+
+    import paper_2111_02396_amd as qs
+    import workloads as W
+
+    w = W.grid28_workload()
+    c = w.circuit
+    n = c.n
+    mc = qs.MarshalledCircuit(c)
+    with qs.State(n) as st:
+        def run(timed):
+            return qs.qs_run_trajectories(st.h, c, 1, seed=w.seed, n_samples=w.n_samples,
+                                          max_fuse=w.max_fuse, record_choices=False,
+                                          time_kernels=timed, marshalled=mc)
+        for _ in range(args.warmup):
+            run(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ms = 0.0
+        launches = 0
+        k_hist = [0] * 6
+        zero = 0
+        for _ in range(args.steps):
+            r = run(True)
+            ms += r["gate_kernel_ms"]
+            launches += r["gate_kernel_launches"]
+            zero += r["zero_start_sweeps"]
+            k_hist = [a + b for a, b in zip(k_hist, r["gate_k_launches"])]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    state_bytes = 8 * (1 << n)
+    alg_bytes = 2 * state_bytes * launches - state_bytes * zero
+    flops = sum(k_hist[k] * (8 << k) for k in range(1, 6)) * float(1 << n)
+    sweep_s = ms / 1e3
+    out = {
+        "metric": "28-qubit noiseless grid: evolved states/s (with 1e5 samples each)",
+        "value": args.steps / dt, "unit": "states/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": w.name, "qubits": n, "samples": w.n_samples,
+                   "max_fuse": w.max_fuse},
+        "sweeps_per_state": launches / args.steps,
+        "avg_sweep_us": 1e6 * sweep_s / max(launches, 1),
+        "sweep_hbm": {"achieved_GBps": alg_bytes / sweep_s / 1e9 if sweep_s > 0 else None,
+                      "peak_GBps": HBM_PEAK_GBPS},
+        "sweep_mfma": {"achieved_TFLOPs": flops / sweep_s / 1e12 if sweep_s > 0 else None,
+                       "peak_TFLOPs": FP32_PEAK_TFLOPS},
+        "non_sweep_ms_per_state": 1e3 * (dt - sweep_s) / args.steps,
     }
     print(json.dumps(out), flush=True)
     return 0
