@@ -473,3 +473,24 @@ def test_driver_concurrent_kernel_timing(qs):
     assert r["gate_kernel_launches"] == one["gate_kernel_launches"] > 0
     assert 0.0 < r["gate_kernel_ms"] <= 1e3 * r["host_seconds"]
     assert r["gate_kernel_ms"] < 2.0 * one["gate_kernel_ms"]
+
+
+def test_grid24_full_size_delayed_equals_conventional(qs):
+    """The benchmark workload at full size: the delayed path (tile sweeps,
+    device-side selection) and the conventional one (one scratch-state pass per
+    Kraus trial) are separate code; away from threshold ties they pick the same
+    Kraus operators, draw the same bitstring and end in the same state."""
+    w = W.grid24_workload()
+    c = w.circuit
+    compared = 0
+    for t in (0, 1, 2):
+        kw = dict(seed=w.seed, traj_offset=t, n_samples=1, e0=w.e0, e1=w.e1, return_state=True,
+                  max_fuse=w.max_fuse)
+        a = _driver(qs, c, 1, 0, **kw)
+        b = _driver(qs, c, 1, 1, **kw)
+        if not np.array_equal(a["choices"][0], b["choices"][0]):
+            continue  # a threshold tie between the two roundings
+        compared += 1
+        assert rel_l2(a["state"], b["state"]) < 2 * AMP_TOL
+        assert np.array_equal(a["samples"], b["samples"])
+    assert compared >= 2
