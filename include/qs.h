@@ -244,7 +244,9 @@ qs_status qs_sample_measurements(qs_state s, uint64_t seed, uint32_t traj, int n
  * QS_KRAUS_CONVENTIONAL_INPLACE by the conventional rule with in-place
  * inner products (every channel takes the inner-product path).
  * The circuit's n_qubits must equal the state's.  Results are written to the
- * caller's host arrays in r.  Errors: INVALID_ARGUMENT, ZERO_NORM, DEVICE. */
+ * caller's host arrays in r.  On return the state holds the last trajectory's
+ * final vector (lazily normalised; what QS_TRAJ_RETURN_STATE copies out), or
+ * is unchanged when n_traj is 0.  Errors: INVALID_ARGUMENT, ZERO_NORM, DEVICE. */
 qs_status qs_run_trajectories(qs_state s, const qs_circuit *c, const qs_traj_params *p,
                               qs_traj_result *r);
 

@@ -93,3 +93,18 @@ def test_tile_edges(qs, orc, n):
             continue
         assert rel_l2(got["state"], ref["state"]) < AMP_TOL
     assert ties <= 1
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["delayed", "naive", "conventional_inplace"])
+def test_state_after_run_is_last_trajectory(qs, mode):
+    """After qs_run_trajectories the state holds the last trajectory's final
+    vector (the one QS_TRAJ_RETURN_STATE copies out), whichever buffer the
+    conventional method ended in."""
+    c = W.grid_circuit(3, 4, 6, p_dep=0.05, gamma=0.1, seed=3)
+    with qs.State(c.n) as st:
+        r = qs.qs_run_trajectories(st.h, c, 5, seed=4, mode=mode, return_state=True)
+        after = qs.qs_copy_state_to_host(st.h)
+        assert np.array_equal(after, r["state"])
+        # and with no trajectories the state is left as it was
+        r0 = qs.qs_run_trajectories(st.h, c, 0, seed=4, mode=mode)
+        assert np.array_equal(qs.qs_copy_state_to_host(st.h), after)
