@@ -28,7 +28,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-from . import (QsError, State, load, qs_run_batched, qs_run_trajectories)
+from . import (QsError, State, load, qs_kraus_bounds, qs_run_batched, qs_run_trajectories)
 
 BATCH_MAX_QUBITS = 18
 
@@ -38,15 +38,20 @@ def footprint_bytes(n: int) -> int:
 
 
 def batchable(circuit) -> bool:
+    """At most 18 qubits and every channel a mixture of unitaries (each
+    K_i^dag K_i a multiple of I, as qs_kraus_bounds reports): Algorithm 2
+    then picks every Kraus operator from the bounds, which the persistent
+    launch requires."""
     if circuit.n > BATCH_MAX_QUBITS:
         return False
+    seen = {}
     for op in circuit.ops:
         if op.kind != 0:
-            for K in op.mats:
-                G = K.conj().T @ K
-                c = np.real(np.trace(G)) / G.shape[0]
-                if np.max(np.abs(G - c * np.eye(G.shape[0]))) > 1e-12:
-                    return False
+            key = id(op.mats)
+            if key not in seen:
+                seen[key] = qs_kraus_bounds(op.mats)[1]
+            if not seen[key]:
+                return False
     return True
 
 

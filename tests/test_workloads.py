@@ -48,8 +48,9 @@ def test_generators_deterministic():
     a = W.grid24_workload().circuit
     b = W.grid24_workload().circuit
     assert [o.name for o in a.ops] == [o.name for o in b.ops]
-    c = W.chain_circuit(12, 20, seed=1)
-    assert [o.name for o in a.ops[:24]] != [o.name for o in c.ops[:24]] or True
+    # another seed draws another 1-qubit layer
+    c = W.grid_circuit(4, 6, 20, p_dep=1e-3, gamma=1e-3, seed=1)
+    assert [o.name for o in a.ops[:24]] != [o.name for o in c.ops[:24]]
 
 
 def test_batched_and_serving_shapes():

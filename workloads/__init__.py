@@ -45,6 +45,7 @@ from .configs import (  # noqa: F401
     chain12_workload,
     grid28_workload,
     grid24_workload,
+    noisy_grid_workload,
     batched_workload,
     serving_requests,
 )

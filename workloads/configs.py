@@ -56,6 +56,17 @@ def grid24_workload(p_dep: float = 1e-3, gamma: float = 1e-3, readout: float = 2
                               max_fuse=4)
 
 
+def noisy_grid_workload(n: int, p_dep: float = 1e-3, gamma: float = 1e-3, readout: float = 2e-2,
+                        n_traj: int = 100) -> TrajectoryWorkload:
+    """The grid24 noise model on an n-qubit generic grid (R = floor(sqrt(n))
+    rows, last row partial), depth 20: for sizes whose state no longer fits
+    the device's last-level cache (26 and 28 qubits)."""
+    c = generic_grid_circuit(n, 20, p_dep=p_dep, gamma=gamma, seed=0)
+    e0, e1 = readout_arrays(n, readout, readout)
+    return TrajectoryWorkload(f"ggrid{n}-depth20-dep{p_dep:g}-ad{gamma:g}-ro{readout:g}", c,
+                              n_traj=n_traj, seed=0, n_samples=1, e0=e0, e1=e1, max_fuse=4)
+
+
 def batched_workload(n_circuits: int = 256, traj_per_circuit: int = 16, seed: int = 0,
                      n_lo: int = 12, n_hi: int = 18, d_lo: int = 10, d_hi: int = 40,
                      p_dep: float = 1e-3) -> List[TrajectoryWorkload]:
