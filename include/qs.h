@@ -93,8 +93,10 @@ typedef struct {
 
 enum {
     QS_TRAJ_RETURN_STATE = 1u, /* copy the last trajectory's final amplitudes to final_state */
-    QS_TRAJ_TIME_KERNELS = 2u  /* bracket every fused-gate launch with HIP events on the
+    QS_TRAJ_TIME_KERNELS = 2u, /* bracket every fused-gate launch with HIP events on the
                                   state's stream and report their summed durations */
+    QS_TRAJ_NO_GRAPH = 4u      /* launch every sweep directly: no HIP-graph replay of the
+                                  default plan (see qs_run_trajectories) */
 };
 
 typedef struct {
@@ -103,11 +105,17 @@ typedef struct {
     uint64_t seed;         /* Philox key */
     uint32_t circuit_id;   /* Philox counter word 2 */
     int32_t mode;          /* qs_kraus_mode */
-    int32_t max_fuse;      /* largest fused gate (Section 3.2); 0 = library default (4) */
+    int32_t max_fuse;      /* largest fused gate (Section 3.2), 1..5; 0 = autotuned: the
+                              delayed-mode driver times the circuit's default plan (every
+                              channel at its most likely pick) on the device for each
+                              candidate width (2..5 below 16 qubits, else 3..5) and keeps
+                              the fastest, cached per circuit and state size for the life
+                              of the process (the conventional modes use 4) */
     int32_t tile_bits;     /* LDS tile sweeps: fused gates whose qubits fit a tile of this
                               many index bits (bits 0..3 always included) share one pass
-                              over the state; 0 = library default (13), 1 = off (one pass
-                              per fused gate), otherwise 10..14 */
+                              over the state; 0 = library default (13), or, when max_fuse
+                              is 0, autotuned with it over 12..14; 1 = off (one pass per
+                              fused gate), otherwise 10..14 */
     int32_t n_samples;     /* measurement samples per trajectory (>= 0) */
     const double *p0to1;   /* per-qubit readout P(read 1 | state 0), host, or NULL */
     const double *p1to0;   /* per-qubit readout P(read 0 | state 1), host, or NULL */
@@ -134,6 +142,11 @@ typedef struct {
                                      a write); counted among gate_sweeps */
     double *z_expect;             /* host [n_traj * n_qubits]: <Z_q> of each trajectory's final
                                      state (as qs_expectation_z), or NULL to skip the pass */
+    int32_t max_fuse_used;        /* out: the fusion width the call ran with */
+    int32_t tile_bits_used;       /* out: the tile width the call ran with (1 = no tiles) */
+    double tune_ms;               /* out: wall time this call spent autotuning (0 on a cached
+                                     or fixed choice) */
+    int64_t graph_replays;        /* out: trajectories whose sweeps ran as a HIP-graph replay */
 } qs_traj_result;
 
 /* ---- state lifecycle ---------------------------------------------------- */
@@ -243,6 +256,15 @@ qs_status qs_sample_measurements(qs_state s, uint64_t seed, uint32_t traj, int n
  * resolves every channel by the conventional method instead, and
  * QS_KRAUS_CONVENTIONAL_INPLACE by the conventional rule with in-place
  * inner products (every channel takes the inner-product path).
+ * Small states (delayed mode, at most 22 qubits, two or more trajectories,
+ * every sweep a tile sweep): the sweeps of the circuit's default plan are
+ * captured once per call into a HIP graph whose kernels read each fused
+ * block's matrix from a fixed device slot; a trajectory whose channels are
+ * all picked from the bounds then writes its patched blocks into their slots
+ * (one host-to-device copy on the stream) and replays the graph, instead of
+ * launching the sweeps one by one.  The results are those of the direct
+ * launches (the same kernels on the same matrices); QS_TRAJ_NO_GRAPH turns
+ * the replay off.
  * The circuit's n_qubits must equal the state's.  Results are written to the
  * caller's host arrays in r.  On return the state holds the last trajectory's
  * final vector (lazily normalised; what QS_TRAJ_RETURN_STATE copies out), or
@@ -287,7 +309,10 @@ typedef struct {
 } qs_batch_item;
 
 typedef struct {
-    int32_t max_fuse;          /* 0 = library default (3) */
+    int32_t max_fuse;          /* 1..5; 0 = autotuned: each candidate width 2..5 runs the
+                                  batch cut to two trajectories per circuit, timed whole
+                                  (planning, upload, launch), the fastest is kept (cached
+                                  per batch of circuits for the life of the process) */
     uint32_t flags;            /* QS_TRAJ_TIME_KERNELS: time the launch with HIP events */
     void *hip_stream;          /* hipStream_t, or NULL */
 } qs_batch_params;
@@ -299,6 +324,9 @@ typedef struct {
     double host_seconds;       /* wall time of the call */
     double plan_seconds;       /* host planning (draws, patched blocks, packing) */
     double kernel_ms;          /* QS_TRAJ_TIME_KERNELS: the persistent launch */
+    int32_t max_fuse_used;     /* the fusion width the launch ran with */
+    int32_t pad;
+    double tune_ms;            /* wall time spent autotuning in this call (0 if cached/fixed) */
 } qs_batch_result;
 
 /* Many small noisy circuits in ONE persistent kernel launch (Section 3.5's

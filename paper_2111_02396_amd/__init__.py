@@ -33,6 +33,7 @@ QS_OP_GATE = 0
 QS_OP_CHANNEL = 1
 QS_TRAJ_RETURN_STATE = 1
 QS_TRAJ_TIME_KERNELS = 2
+QS_TRAJ_NO_GRAPH = 4
 
 _NAMES = {0: "QS_OK", -1: "QS_ERR_INVALID_ARGUMENT", -2: "QS_ERR_OUT_OF_MEMORY",
           -3: "QS_ERR_DEVICE", -4: "QS_ERR_ZERO_NORM", -5: "QS_ERR_NOT_SUPPORTED"}
@@ -71,7 +72,9 @@ class QsTrajResult(ctypes.Structure):
                 ("gate_sweeps", ctypes.c_int64), ("host_seconds", ctypes.c_double),
                 ("gate_kernel_ms", ctypes.c_double), ("gate_kernel_launches", ctypes.c_int64),
                 ("gate_k_launches", ctypes.c_int64 * 6), ("zero_start_sweeps", ctypes.c_int64),
-                ("z_expect", ctypes.c_void_p)]
+                ("z_expect", ctypes.c_void_p), ("max_fuse_used", ctypes.c_int32),
+                ("tile_bits_used", ctypes.c_int32), ("tune_ms", ctypes.c_double),
+                ("graph_replays", ctypes.c_int64)]
 
 
 class QsBatchItem(ctypes.Structure):
@@ -90,7 +93,9 @@ class QsBatchParams(ctypes.Structure):
 class QsBatchResult(ctypes.Structure):
     _fields_ = [("jobs", ctypes.c_int64), ("resident_jobs", ctypes.c_int64),
                 ("gate_blocks", ctypes.c_int64), ("host_seconds", ctypes.c_double),
-                ("plan_seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
+                ("plan_seconds", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("max_fuse_used", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("tune_ms", ctypes.c_double)]
 
 
 def load():
@@ -302,7 +307,7 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
                         tile_bits: int = 0,
                         n_samples: int = 0, p0to1=None, p1to0=None, return_state: bool = False,
                         record_choices: bool = True, time_kernels: bool = False,
-                        z_expect: bool = False,
+                        z_expect: bool = False, graph: bool = True,
                         marshalled: Optional[MarshalledCircuit] = None) -> Dict:
     """Run trajectories traj_offset .. traj_offset + n_traj - 1 (qs_run_trajectories).
     `s` may also be a list of state handles: the range is then split over them
@@ -312,7 +317,7 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
     e0 = None if p0to1 is None else np.ascontiguousarray(p0to1, dtype=np.float64)
     e1 = None if p1to0 is None else np.ascontiguousarray(p1to0, dtype=np.float64)
     flags = (QS_TRAJ_RETURN_STATE if return_state else 0) | \
-        (QS_TRAJ_TIME_KERNELS if time_kernels else 0)
+        (QS_TRAJ_TIME_KERNELS if time_kernels else 0) | (0 if graph else QS_TRAJ_NO_GRAPH)
     params = QsTrajParams(n_traj, traj_offset, seed, circuit_id, mode, max_fuse, tile_bits,
                           n_samples, _p(e0), _p(e1), flags)
     bits = np.zeros(max(n_traj * n_samples, 1), dtype=np.uint64)
@@ -345,6 +350,10 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
         "gate_kernel_launches": res.gate_kernel_launches,
         "gate_k_launches": [int(x) for x in res.gate_k_launches],
         "zero_start_sweeps": res.zero_start_sweeps,
+        "max_fuse_used": res.max_fuse_used,
+        "tile_bits_used": res.tile_bits_used,
+        "tune_ms": res.tune_ms,
+        "graph_replays": res.graph_replays,
     }
     if z_expect:
         out["z_expect"] = zs[:n_traj]
@@ -401,7 +410,8 @@ def qs_run_batched(workloads, max_fuse: int = 0, hip_stream: Optional[int] = Non
         results.append(d)
     stats = {"jobs": res.jobs, "resident_jobs": res.resident_jobs, "gate_blocks": res.gate_blocks,
              "host_seconds": res.host_seconds, "plan_seconds": res.plan_seconds,
-             "kernel_ms": res.kernel_ms}
+             "kernel_ms": res.kernel_ms, "max_fuse_used": res.max_fuse_used,
+             "tune_ms": res.tune_ms}
     return results, stats
 
 

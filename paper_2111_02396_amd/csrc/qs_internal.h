@@ -55,10 +55,11 @@ constexpr int kTileMinQubits = 10;
 constexpr int kTileMatBudget = 4096;  // float2 of matrices staged per launch (32 KiB)
 
 // LDS float2 slots a gate's matrix takes in a tile launch: none for k <= 2
-// (read from global memory), MFMA fragments for k = 3 (256 floats) and
-// k = 4 (768 floats: three real 16x16 matrices), the plain 32x32 matrix for k = 5.
+// (read from global memory), MFMA fragments for k = 3 (256 floats), k = 4
+// (768 floats: three real 16x16 matrices) and k = 5 (3072 floats: three real
+// 32x32 matrices; narrow tiles use the first 1024 slots for the plain matrix).
 __host__ __device__ inline int tile_mat_slots(int k) {
-    return k <= 2 ? 0 : (k == 3 ? 128 : (k == 4 ? 384 : 1024));
+    return k <= 2 ? 0 : (k == 3 ? 128 : (k == 4 ? 384 : 1536));
 }
 
 struct TileGate {
@@ -157,6 +158,10 @@ hipError_t launch_apply_gate(float2 *amp, int n, const GateDesc &g, const float2
 
 // Several gates in one sweep: every gate's targets are bits of the tile.
 hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t st);
+// Validates a and sets up its kernel instantiation without enqueueing
+// anything (before a launch under stream capture).
+hipError_t prepare_apply_tile(int n, const TileArgs &a);
+hipError_t launch_apply_tile_impl(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch);
 
 // FP64 reductions with a fixed tree.  Each writes `width` doubles to out_dev.
 // norm: width 1 (sum |psi|^2).

@@ -405,6 +405,89 @@ __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const f
     __builtin_amdgcn_s_setprio(0);
 }
 
+// k = 5: the same three real products as k = 4, each now a 32 x 32 matrix.
+// The 32 output rows form two halves h (rows 16 h + i) and the contraction
+// over the 32 inputs runs in eight steps of four.  In step s lane (n, q) =
+// (l%16, l/16) supplies amplitude 4 s + q of group n; accumulator r of half h
+// is output 16 h + 4 q + r.  Fragment layout:
+// frag[lane * 48 + 24 h + 8 m + s] = M_m[16 h + l%16][4 s + l/16], with the
+// M_m of k = 4.  48 MFMAs per 16 groups (a 5-qubit block is the densest
+// contraction of a sweep: 16 flops per byte moved, Section 3.1).
+template <int NT = kBlock>
+__device__ __forceinline__ void stage_frag5(float *__restrict__ frag, const float2 *__restrict__ u) {
+    for (int i = threadIdx.x; i < 64 * 48; i += NT) {
+        const int lane = i / 48, rem = i - 48 * lane;
+        const int h = rem / 24, m = (rem % 24) >> 3, s = rem & 7;
+        const float2 e = u[(16 * h + (lane & 15)) * 32 + 4 * s + (lane >> 4)];
+        frag[i] = m == 0 ? e.x : (m == 1 ? -(e.x + e.y) : e.y - e.x);
+    }
+}
+
+// As tile_gate_mfma4: 16 groups per wavefront iteration, the next
+// iteration's amplitudes read ahead of this one's MFMAs.  The two output
+// halves are formed one after the other from the same inputs in registers.
+template <class L, int NT = kBlock>
+__device__ __forceinline__ void tile_gate_mfma5(float2 *__restrict__ sd, const float *__restrict__ frag,
+                                                const int *tab, int tb) {
+    constexpr int W = NT / 64;
+    constexpr int LW = ilog2(W);
+    const int lane = threadIdx.x & 63, wave = wave_index();
+    const int n = lane & 15, q = lane >> 4;
+    const f32x4 *fp = reinterpret_cast<const f32x4 *>(frag + lane * 48);
+    f32x4 F[12];  // F[6 h + 2 m + s / 4][s % 4]
+#pragma unroll
+    for (int i = 0; i < 12; ++i) F[i] = fp[i];
+    // group bits are logical bits 5.. (n its low four); input j = 4 s + q
+    // (q: bits 0..1, s: bits 2..4); output j = 16 h + 4 q + r (r: bits 0..1,
+    // q: bits 2..3, h: bit 4)
+    const int lane_part = tab_xor<4>(tab, 5, n);
+    const int lin = lane_part ^ tab_xor<2>(tab, 0, q);
+    const int lout = lane_part ^ tab_xor<2>(tab, 2, q);
+    int ain[8], aout[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) ain[s] = lin ^ tab_xor<3>(tab, 2, s);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) aout[4 * h + r] = lout ^ tab_xor<2>(tab, 0, r) ^ (h ? tab[4] : 0);
+    const int iters = (1 << (tb - 5 - 4)) / W;  // batches per wave: >= 1 needs tb >= 9 + log2 W
+    const int uw = tab_xor<LW>(tab, 9, wave);
+    int ub = uw;
+    float2 v[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = lds_get(sd, ain[s] ^ ub);
+    for (int it = 0; it < iters; ++it) {
+        prio_for_remaining(iters - it);
+        const int itn = it + 1 < iters ? it + 1 : it;
+        const int ubn = uw ^ tab_xor<kMaxTileBits - 9 - LW>(tab, 9 + LW, itn);
+        float2 w[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) w[s] = lds_get(sd, ain[s] ^ ubn);
+        float xy[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) xy[s] = v[s].x + v[s].y;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            f32x4 k1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+                k1 = __builtin_amdgcn_mfma_f32_16x16x4f32(F[6 * h + (s >> 2)][s & 3], xy[s], k1, 0, 0, 0);
+            f32x4 re = k1, im = k1;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                re = __builtin_amdgcn_mfma_f32_16x16x4f32(F[6 * h + 2 + (s >> 2)][s & 3], v[s].y, re, 0, 0, 0);
+                im = __builtin_amdgcn_mfma_f32_16x16x4f32(F[6 * h + 4 + (s >> 2)][s & 3], v[s].x, im, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lds_put(sd, aout[4 * h + r] ^ ub, make_float2(re[r], im[r]));
+        }
+        ub = ubn;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) v[s] = w[s];
+    }
+    __builtin_amdgcn_s_setprio(0);
+}
+
 // 16 groups per wavefront iteration; the accumulator rows 4q + r give lane
 // quarter q the amplitudes 2q (r = 0, 1) and 2q + 1 (r = 2, 3).  As for k = 4
 // the next iteration's amplitudes are read ahead of this one's MFMAs.
@@ -459,12 +542,15 @@ __device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const f
 // tile's loads are issued into registers, the gates run on the LDS copy in
 // order, and the tile is written back: any number of gates inside the tile
 // cost one HBM read and one write.
-// K5: whether the launch holds a 5-qubit block (its VALU path needs ~70 more
-// VGPRs, so launches without one use a leaner instantiation).
+// K5: whether the launch holds a 5-qubit block (its path needs many more
+// VGPRs, so launches without one use a leaner instantiation).  5-qubit blocks
+// run on MFMA when every wavefront gets a batch of 16 groups (TB >= 9 +
+// log2(NT / 64)), else on VALU from the plain matrix.
 template <int TB, typename Idx, bool K5, int NT>
 __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n_tiles,
                                                  TileArgs a) {
     constexpr int NB = ilog2(NT);
+    constexpr bool K5_MFMA = TB >= 9 + NB - 6;
     static_assert(TB >= 10, "the MFMA gates need at least 32 groups per tile");
     static_assert((1 << (TB - 8)) >= NT / 64, "every wavefront needs a 4-qubit batch");
     constexpr int E = 1 << TB;
@@ -526,7 +612,9 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
         } else if (k == 3) {
             stage_frag3<NT>(reinterpret_cast<float *>(dst), src);
         } else if (k == 5) {
-            for (int i = threadIdx.x; i < 1024; i += NT) dst[i] = src[i];
+            if constexpr (K5_MFMA) stage_frag5<NT>(reinterpret_cast<float *>(dst), src);
+            else
+                for (int i = threadIdx.x; i < 1024; i += NT) dst[i] = src[i];
         }
     }
     // One tile: the prefetched amplitudes go to LDS, the previous tile's
@@ -578,7 +666,11 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
                                                       tab, TB);
                     break;
                 default:
-                    if constexpr (K5) tile_gate_valu<5, SwizzledTile, NT>(sd, sm + a.g[gi].lofs, lt, TB);
+                    if constexpr (K5 && K5_MFMA)
+                        tile_gate_mfma5<SwizzledTile, NT>(sd, reinterpret_cast<const float *>(sm + a.g[gi].lofs),
+                                                          tab, TB);
+                    else if constexpr (K5)
+                        tile_gate_valu<5, SwizzledTile, NT>(sd, sm + a.g[gi].lofs, lt, TB);
                     break;
             }
             __syncthreads();
@@ -1238,16 +1330,13 @@ int device_cus() {
     return cus;
 }
 
+// Once per instantiation, thread-safely: allow the matrix region, and read
+// how many workgroups per CU registers and waves allow (with no matrices the
+// LDS is not what limits the count); a negative value is an error.
 template <int TB, typename Idx, bool K5, int NT>
-hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
-    // static tile + dynamic matrices
-    const size_t dyn = sizeof(float2) * size_t(a.mat_total);
-    const size_t lds = sizeof(float2) * (size_t(1) << TB) + dyn;
-    const void *fn = reinterpret_cast<const void *>(&apply_tile<TB, Idx, K5, NT>);
-    // once per instantiation, thread-safely: allow the matrix region, and read
-    // how many workgroups per CU registers and waves allow (with no matrices
-    // the LDS is not what limits the count); a negative value is an error
-    static const int reg_limit = [fn] {
+int tile_reg_limit() {
+    static const int reg_limit = [] {
+        const void *fn = reinterpret_cast<const void *>(&apply_tile<TB, Idx, K5, NT>);
         if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 int(sizeof(float2) * kTileMatBudget)) != hipSuccess)
             return -1;
@@ -1255,20 +1344,33 @@ hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, NT, 0) != hipSuccess) return -1;
         return blocks < 1 ? 1 : blocks;
     }();
+    return reg_limit;
+}
+
+// launch = false only sets the instantiation up (no stream work), so that a
+// later launch under stream capture makes no attribute or occupancy calls.
+template <int TB, typename Idx, bool K5, int NT>
+hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch) {
+    // static tile + dynamic matrices
+    const size_t dyn = sizeof(float2) * size_t(a.mat_total);
+    const size_t lds = sizeof(float2) * (size_t(1) << TB) + dyn;
+    const int reg_limit = tile_reg_limit<TB, Idx, K5, NT>();
     if (reg_limit < 0) return hipErrorInvalidDeviceFunction;
+    const int cus = device_cus();
+    if (!launch) return hipSuccess;
     const Idx n_tiles = Idx(1) << (n - TB);
     // persistent grid: as many workgroups as are resident at once at this LDS size
     int per_cu = int((160u * 1024u) / lds);
     if (per_cu < 1) per_cu = 1;
     if (per_cu > reg_limit) per_cu = reg_limit;
-    uint64_t grid = uint64_t(device_cus()) * uint64_t(per_cu);
+    uint64_t grid = uint64_t(cus) * uint64_t(per_cu);
     if (grid > uint64_t(n_tiles)) grid = uint64_t(n_tiles);
     apply_tile<TB, Idx, K5, NT><<<unsigned(grid), NT, dyn, st>>>(amp, n_tiles, a);
     return hipGetLastError();
 }
 
 template <int TB, typename Idx>
-hipError_t tile_launch_k(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
+hipError_t tile_launch_k(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch) {
     bool k5 = false;
     for (int gi = 0; gi < a.n_gates; ++gi) k5 |= a.g[gi].k == 5;
     // Four wavefronts per SIMD hide the LDS and MFMA latency: a 2^14-amplitude
@@ -1277,17 +1379,18 @@ hipError_t tile_launch_k(float2 *amp, int n, const TileArgs &a, hipStream_t st) 
     // more workgroups and do better with 256 (measured on the 24-qubit noisy
     // grid).
     constexpr int NT = TB >= 14 ? 1024 : (TB >= 13 ? 512 : kBlock);
-    return k5 ? tile_launch<TB, Idx, true, NT>(amp, n, a, st) : tile_launch<TB, Idx, false, NT>(amp, n, a, st);
+    return k5 ? tile_launch<TB, Idx, true, NT>(amp, n, a, st, launch)
+              : tile_launch<TB, Idx, false, NT>(amp, n, a, st, launch);
 }
 
 template <typename Idx>
-hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
+hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch) {
     switch (a.tb) {
-        case 10: return tile_launch_k<10, Idx>(amp, n, a, st);
-        case 11: return tile_launch_k<11, Idx>(amp, n, a, st);
-        case 12: return tile_launch_k<12, Idx>(amp, n, a, st);
-        case 13: return tile_launch_k<13, Idx>(amp, n, a, st);
-        case 14: return tile_launch_k<14, Idx>(amp, n, a, st);
+        case 10: return tile_launch_k<10, Idx>(amp, n, a, st, launch);
+        case 11: return tile_launch_k<11, Idx>(amp, n, a, st, launch);
+        case 12: return tile_launch_k<12, Idx>(amp, n, a, st, launch);
+        case 13: return tile_launch_k<13, Idx>(amp, n, a, st, launch);
+        case 14: return tile_launch_k<14, Idx>(amp, n, a, st, launch);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1393,6 +1496,14 @@ hipError_t launch_apply_gate(float2 *amp, int n, const GateDesc &g, const float2
 }
 
 hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
+    return launch_apply_tile_impl(amp, n, a, st, true);
+}
+
+hipError_t prepare_apply_tile(int n, const TileArgs &a) {
+    return launch_apply_tile_impl(nullptr, n, a, nullptr, false);
+}
+
+hipError_t launch_apply_tile_impl(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch) {
     if (a.tb < 10 || a.tb > kMaxTileBits || a.tb > n || a.n_gates < 0 ||
         a.n_gates > kMaxTileGates || a.mat_total < 0 || a.mat_total > kTileMatBudget)
         return hipErrorInvalidValue;
@@ -1423,8 +1534,8 @@ hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t 
             default: gate_tables<5, SwizzledTile>(g.lt, g.tab); break;
         }
     }
-    if (n <= 31) return apply_tile_idx<uint32_t>(amp, n, b, st);
-    return apply_tile_idx<uint64_t>(amp, n, b, st);
+    if (n <= 31) return apply_tile_idx<uint32_t>(amp, n, b, st, launch);
+    return apply_tile_idx<uint64_t>(amp, n, b, st, launch);
 }
 
 hipError_t launch_norm(const float2 *amp, int n, double *partials, double *out_dev,

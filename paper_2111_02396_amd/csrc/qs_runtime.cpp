@@ -9,9 +9,11 @@
 #include <array>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "qs.h"
@@ -972,6 +974,7 @@ struct KernelTimer {
     }
     // after a sweep launch
     void launched() { ++cur; }
+    void launched_n(int k) { cur += k; }
     // before any other kernel, and at the end of a run of sweeps
     qs_status close(qs_state s) {
         if (!open_now) return QS_OK;
@@ -988,12 +991,73 @@ struct KernelTimer {
     }
 };
 
+// ---- per-circuit plan cache
+// The default plan of a circuit (fusion into blocks, their matrices, the tile
+// sweep grouping) depends only on the circuit, the mode's channel bounds and
+// the widths, so calls that run the same circuit again (one state per call,
+// a serving loop, the autotuner's final choice) reuse it instead of fusing
+// again.  Keyed by a hash of the circuit's ops and matrix pool.
+struct PlanKey {
+    uint64_t hash;
+    int n, mode, f, tb;
+    bool operator<(const PlanKey &o) const {
+        return std::tie(hash, n, mode, f, tb) < std::tie(o.hash, o.n, o.mode, o.f, o.tb);
+    }
+};
+
+struct PlanEntry {
+    std::vector<qs::Block> blocks;
+    std::vector<int> op_block;
+    std::vector<BlockDesc> block_desc;  // device copies not set
+    std::vector<qs::Sweep> sweeps;
+};
+
+constexpr size_t kPlanCacheEntries = 32;
+std::mutex g_plan_mu;
+std::map<PlanKey, std::shared_ptr<const PlanEntry>> g_plan_cache;
+std::deque<PlanKey> g_plan_fifo;
+
+void plan_lookup(const PlanKey &k, std::shared_ptr<const PlanEntry> *out) {
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    auto it = g_plan_cache.find(k);
+    *out = it == g_plan_cache.end() ? nullptr : it->second;
+}
+
+void plan_insert(const PlanKey &k, std::shared_ptr<const PlanEntry> e) {
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    if (g_plan_cache.count(k)) return;
+    if (g_plan_fifo.size() >= kPlanCacheEntries) {
+        g_plan_cache.erase(g_plan_fifo.front());
+        g_plan_fifo.pop_front();
+    }
+    g_plan_cache[k] = std::move(e);
+    g_plan_fifo.push_back(k);
+}
+
+// FNV-1a over the circuit's qubit count, op records and matrix pool.
+uint64_t circuit_hash(const qs_circuit *c) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void *p, size_t len) {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < len; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    };
+    mix(&c->n_qubits, sizeof(c->n_qubits));
+    mix(c->ops, sizeof(qs_op) * size_t(c->n_ops));
+    mix(c->mat_pool, sizeof(double) * 2 * size_t(c->pool_len));
+    return h;
+}
+
 struct Runner {
     qs_state s;
     const CircuitModel &m;
     const qs_traj_params &p;
     qs_traj_result &res;
     int max_fuse;
+    uint64_t chash = 0;   // circuit_hash of the call's circuit (0: do not cache the plan)
+    bool tuning = false;  // an autotuner trial: default plan only, no channel uploads
     // delayed mode: default plan
     std::vector<const cd *> default_mats;
     std::vector<double> default_log;
@@ -1050,8 +1114,35 @@ struct Runner {
         qs::SelectArgs args;
     } sel;
 
+    // HIP graph of the default plan's sweeps (delayed mode, small states):
+    // each block reads its matrix from a fixed device slot, so one capture
+    // serves every trajectory whose channels are all picked from the bounds
+    bool graph_wanted = false;
+    bool graph_failed = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_launches = 0;
+    int64_t graph_k[6] = {};
+    float2 *gtab_dev = nullptr;            // the slots
+    std::vector<size_t> gtab_off;          // per block: float2 offset, or kNoSlot (identity)
+    std::vector<float2> gtab_host;         // the slots' current contents
+    float2 *gtab_stage[2] = {nullptr, nullptr};  // pinned staging halves
+    hipEvent_t gtab_ev[2] = {nullptr, nullptr};
+    bool gtab_live[2] = {false, false};
+    int gtab_half = 0;
+    std::vector<char> gdirty_prev;         // blocks the previous replay patched
+    static constexpr size_t kNoSlot = ~size_t(0);
+    static constexpr int kGraphMaxQubits = 22;
+
     ~Runner() {
-        if (static_mats || chan_buf || dev_choice) (void)hipStreamSynchronize(s->st);
+        if (static_mats || chan_buf || dev_choice || gtab_dev) (void)hipStreamSynchronize(s->st);
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (gtab_dev) (void)hipFree(gtab_dev);
+        for (int h = 0; h < 2; ++h) {
+            if (gtab_stage[h]) (void)hipHostFree(gtab_stage[h]);
+            if (gtab_ev[h]) (void)hipEventDestroy(gtab_ev[h]);
+        }
         if (sel_rdm) (void)hipFree(sel_rdm);
         if (static_mats) (void)hipFree(static_mats);
         if (chan_buf) (void)hipFree(chan_buf);
@@ -1165,25 +1256,44 @@ struct Runner {
                 default_log[o] = c.log_pbar[c.default_pick];
             }
         }
-        blocks = qs::fuse_greedy(m.n, m.ops, max_fuse, &op_block);
-        block_desc.resize(blocks.size());
-        for (size_t b = 0; b < blocks.size(); ++b) {
-            build_block(m, blocks[b].ops, default_mats, tmp, block_desc[b]);
-            double lb = 0.0;
-            for (int o : blocks[b].ops) lb += default_log[o];
-            block_desc[b].log_bound = lb;
+        const PlanKey key{chash, m.n, p.mode, max_fuse, p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits};
+        std::shared_ptr<const PlanEntry> cached;
+        if (chash) plan_lookup(key, &cached);
+        if (cached) {
+            blocks = cached->blocks;
+            op_block = cached->op_block;
+            block_desc = cached->block_desc;
+            sweeps = cached->sweeps;
+        } else {
+            blocks = qs::fuse_greedy(m.n, m.ops, max_fuse, &op_block);
+            block_desc.resize(blocks.size());
+            for (size_t b = 0; b < blocks.size(); ++b) {
+                build_block(m, blocks[b].ops, default_mats, tmp, block_desc[b]);
+                double lb = 0.0;
+                for (int o : blocks[b].ops) lb += default_log[o];
+                block_desc[b].log_bound = lb;
+            }
+            plan_sweeps();
+            if (chash) {
+                auto e = std::make_shared<PlanEntry>();
+                e->blocks = blocks;
+                e->op_block = op_block;
+                e->block_desc = block_desc;
+                e->sweeps = sweeps;
+                plan_insert(key, std::move(e));
+            }
         }
-        plan_sweeps();
+        layouts.resize(sweeps.size());
+        for (size_t u = 0; u < sweeps.size(); ++u) layouts[u] = make_layout(sweeps[u], blocks);
         std::vector<BlockDesc *> all;
         for (auto &d : block_desc) all.push_back(&d);
-        QS_CHECK(upload_channels());
+        if (!tuning) QS_CHECK(upload_channels());
         return upload_static(all);
     }
 
     void plan_sweeps() {
         const int T = p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits;
         sweeps.clear();
-        layouts.clear();
         if (T >= 10 && m.n >= qs::kTileMinQubits) {
             sweeps = qs::group_sweeps(m.n, blocks, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates,
                                       qs::kTileMatBudget, tile_slots());
@@ -1194,8 +1304,25 @@ struct Runner {
                 sweeps.push_back(std::move(sw));
             }
         }
-        layouts.resize(sweeps.size());
-        for (size_t u = 0; u < sweeps.size(); ++u) layouts[u] = make_layout(sweeps[u], blocks);
+    }
+
+    // The default plan once from |0...0> (every channel at its most likely
+    // pick, no inner products): the autotuner's trial.
+    qs_status run_default_plan() {
+        QS_CHECK(restore_home(s));
+        pending_reset = true;
+        log_norm_bound = 0.0;
+        std::vector<SegSweep> seg;
+        segment_sweeps(0, int(m.ops.size()), true, seg);
+        std::vector<Unit> units;
+        for (const SegSweep &ss : seg) {
+            Unit u{ss.L, {}};
+            for (const auto &mem : ss.members)
+                if (!block_desc[mem[0]].identity) u.items.push_back(&block_desc[mem[0]]);
+            if (!u.items.empty()) units.push_back(std::move(u));
+        }
+        QS_CHECK(flush_units(units));
+        return settle_reset();
     }
 
     // Tile layout of a sweep: its qubits plus the lowest others up to the tile
@@ -1468,6 +1595,181 @@ struct Runner {
         return QS_OK;
     }
 
+    // Tile arguments of one unit of default-plan blocks, each matrix read
+    // from the block's graph slot.
+    void unit_args(const Unit &u, bool init_zero, qs::TileArgs &a) const {
+        const TileLayout &L = *u.L;
+        std::memset(&a, 0, sizeof(a));
+        a.init_zero = init_zero ? 1 : 0;
+        a.tb = L.tb;
+        for (int i = 0; i < L.tb; ++i) a.pos[i] = L.pos[i];
+        int lofs = 0;
+        for (const BlockDesc *d : u.items) {
+            qs::TileGate &g = a.g[a.n_gates++];
+            g.k = d->g.k;
+            for (int b = 0; b < d->g.k; ++b) g.lt[b] = L.local[d->g.t[b]];
+            g.lofs = lofs;
+            g.mat = gtab_dev + gtab_off[size_t(d - block_desc.data())];
+            lofs += qs::tile_mat_slots(d->g.k);
+        }
+        a.mat_total = lofs;
+    }
+
+    // Capture the default plan's sweeps into a graph (once per call).  Any
+    // failure leaves graph_failed set and the trajectories run directly.
+    qs_status build_graph() {
+        graph_failed = true;
+        if (!s->st) return QS_OK;  // the null stream cannot be captured
+        std::vector<SegSweep> seg;
+        segment_sweeps(0, int(m.ops.size()), true, seg);
+        std::vector<Unit> units;
+        for (const SegSweep &ss : seg) {
+            if (!ss.L->tiled) return QS_OK;  // only tile sweeps are captured
+            Unit u{ss.L, {}};
+            for (const auto &mem : ss.members)
+                if (!block_desc[mem[0]].identity) u.items.push_back(&block_desc[mem[0]]);
+            if (!u.items.empty()) units.push_back(std::move(u));
+        }
+        if (units.empty()) return QS_OK;
+        gtab_off.assign(blocks.size(), kNoSlot);
+        size_t total = 0;
+        for (size_t b = 0; b < blocks.size(); ++b) {
+            if (block_desc[b].identity) continue;
+            gtab_off[b] = total;
+            total += ((size_t(1) << (2 * block_desc[b].g.k)) + 31) & ~size_t(31);  // 256 B slots
+        }
+        gtab_host.assign(total, make_float2(0.f, 0.f));
+        for (size_t b = 0; b < blocks.size(); ++b)
+            if (gtab_off[b] != kNoSlot)
+                std::memcpy(gtab_host.data() + gtab_off[b], block_desc[b].g.m,
+                            sizeof(float2) << (2 * block_desc[b].g.k));
+        QS_HIP(s, hipMalloc(&gtab_dev, sizeof(float2) * total));
+        QS_HIP(s, hipMemcpyAsync(gtab_dev, gtab_host.data(), sizeof(float2) * total,
+                                 hipMemcpyHostToDevice, s->st));
+        QS_HIP(s, hipStreamSynchronize(s->st));
+        for (int h = 0; h < 2; ++h) {
+            QS_HIP(s, hipHostMalloc(&gtab_stage[h], sizeof(float2) * total, hipHostMallocDefault));
+            QS_HIP(s, hipEventCreateWithFlags(&gtab_ev[h], hipEventDisableTiming));
+        }
+        gdirty_prev.assign(blocks.size(), 0);
+        std::vector<qs::TileArgs> args(units.size());
+        for (size_t u = 0; u < units.size(); ++u) {
+            unit_args(units[u], u == 0, args[u]);
+            if (qs::prepare_apply_tile(s->n, args[u]) != hipSuccess) return QS_OK;
+        }
+        QS_CHECK(restore_home(s));
+        if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            return QS_OK;
+        }
+        hipError_t e = hipSuccess;
+        for (const auto &a : args)
+            if ((e = qs::launch_apply_tile(s->amp, s->n, a, s->st)) != hipSuccess) break;
+        hipGraph_t g = nullptr;
+        const hipError_t e_end = hipStreamEndCapture(s->st, &g);
+        if (e != hipSuccess || e_end != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            return QS_OK;
+        }
+        graph = g;
+        if (hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            graph_exec = nullptr;
+            (void)hipGetLastError();
+            return QS_OK;
+        }
+        graph_launches = int(units.size());
+        for (const Unit &u : units)
+            for (const BlockDesc *d : u.items) graph_k[d->g.k]++;
+        graph_failed = false;
+        return QS_OK;
+    }
+
+    // One trajectory by graph replay, when its channels were all picked from
+    // the bounds (`mats`: its per-op matrices, `dirty`: blocks whose picks
+    // differ from the default).  Returns false (nothing enqueued) when the
+    // trajectory cannot use the graph: a patched block that the default plan
+    // drops as the identity, or a norm bound that would need renormalising
+    // on the way.
+    qs_status try_graph(const std::vector<const cd *> &mats, const std::vector<char> &dirty,
+                        const std::vector<int> &pick, bool *used) {
+        *used = false;
+        if (!graph_exec) {
+            if (graph_failed) return QS_OK;
+            QS_CHECK(build_graph());
+            if (graph_failed) return QS_OK;
+        }
+        // the eager path renormalises when the running bound of the norm
+        // (a sum of non-positive logs) falls below the threshold; the graph
+        // carries no renormalisation, so such trajectories run directly
+        double lb_total = 0.0;
+        std::vector<std::pair<size_t, BlockDesc>> patched;
+        for (size_t b = 0; b < blocks.size(); ++b) {
+            if (!dirty[b]) {
+                lb_total += block_desc[b].log_bound;
+                continue;
+            }
+            if (gtab_off[b] == kNoSlot) return QS_OK;
+            BlockDesc bd;
+            build_block(m, blocks[b].ops, mats, tmp, bd);
+            double lb = 0.0;
+            for (int o : blocks[b].ops) {
+                if (m.kind[o] == QS_OP_GATE) lb += m.gate_log_bound[o];
+                else lb += m.channels[m.channel_of_op[o]].log_pbar[pick[m.channel_of_op[o]]];
+            }
+            lb_total += lb;
+            if (bd.g.k != block_desc[b].g.k) return QS_OK;  // same qubits, so never
+            patched.emplace_back(b, bd);
+        }
+        if (lb_total < kRenormLogThreshold) return QS_OK;
+        // slots to rewrite: this trajectory's patches and the previous one's
+        size_t lo = kNoSlot, hi = 0;
+        auto touch = [&](size_t b) {
+            const size_t len = size_t(1) << (2 * block_desc[b].g.k);
+            lo = std::min(lo, gtab_off[b]);
+            hi = std::max(hi, gtab_off[b] + len);
+        };
+        for (size_t b = 0; b < blocks.size(); ++b)
+            if (gdirty_prev[b] && !dirty[b]) {
+                std::memcpy(gtab_host.data() + gtab_off[b], block_desc[b].g.m,
+                            sizeof(float2) << (2 * block_desc[b].g.k));
+                touch(b);
+            }
+        for (const auto &pb : patched) {
+            std::memcpy(gtab_host.data() + gtab_off[pb.first], pb.second.g.m,
+                        sizeof(float2) << (2 * pb.second.g.k));
+            touch(pb.first);
+        }
+        QS_CHECK(restore_home(s));
+        QS_CHECK(settle_reset());
+        if (lo != kNoSlot) {
+            const int h = gtab_half;
+            if (gtab_live[h]) QS_HIP(s, hipEventSynchronize(gtab_ev[h]));
+            std::memcpy(gtab_stage[h] + lo, gtab_host.data() + lo, sizeof(float2) * (hi - lo));
+            QS_HIP(s, hipMemcpyAsync(gtab_dev + lo, gtab_stage[h] + lo, sizeof(float2) * (hi - lo),
+                                     hipMemcpyHostToDevice, s->st));
+            QS_HIP(s, hipEventRecord(gtab_ev[h], s->st));
+            gtab_live[h] = true;
+            gtab_half ^= 1;
+        }
+        if (timing) QS_CHECK(timer.open(s));
+        QS_HIP(s, hipGraphLaunch(graph_exec, s->st));
+        if (timing) {
+            timer.launched_n(graph_launches);
+            QS_CHECK(timer.close(s));
+        }
+        res.sweeps += graph_launches;
+        res.gate_sweeps += graph_launches;
+        res.zero_start_sweeps += 1;
+        for (int k = 1; k <= 5; ++k) res.gate_k_launches[k] += graph_k[k];
+        gdirty_prev = dirty;
+        pending_reset = false;
+        log_norm_bound = 0.0;
+        res.graph_replays++;
+        *used = true;
+        return QS_OK;
+    }
+
     qs_status run_delayed(int64_t rel, uint32_t traj) {
         const int nch = int(m.channels.size());
         // steps 1-11 of Algorithm 2 for every channel: state-independent
@@ -1504,6 +1806,11 @@ struct Runner {
         for (auto &ov : overrides) {
             mats[ov.first] = ov.second;
             dirty[op_block[ov.first]] = 1;
+        }
+        if (graph_wanted && slow_ops.empty()) {
+            bool used = false;
+            QS_CHECK(try_graph(mats, dirty, pick, &used));
+            if (used) return QS_OK;
         }
         slow_mats.clear();
         const int n_ops = int(m.ops.size());
@@ -1551,6 +1858,7 @@ struct Runner {
                         const float2 *dc = nullptr;
                         QS_CHECK(arena_stage(s, cand_f2, &hc, &dc));
                         double *hcd = reinterpret_cast<double *>(hc);
+                        tmp.resize(size_t(Db) * Db);  // fused_matrix writes Db x Db entries
                         for (int i = 0; i < ci.nk; ++i) {
                             mats[sel.op] = ci.kraus + size_t(i) * Dc * Dc;
                             qs::fused_matrix(kb, q, sub, m.ops, mats, tmp.data());
@@ -1681,6 +1989,8 @@ struct Runner {
         const bool delayed = p.mode != QS_KRAUS_NAIVE;
         if (delayed) QS_CHECK(plan_delayed());
         else QS_CHECK(plan_naive());
+        graph_wanted = p.mode == QS_KRAUS_DELAYED && !(p.flags & QS_TRAJ_NO_GRAPH) && !tuning &&
+                       m.n <= kGraphMaxQubits && p.n_traj >= 2;
         for (int64_t rel = 0; rel < p.n_traj; ++rel) {
             const uint32_t traj = uint32_t(p.traj_offset + rel);
             if (delayed) QS_CHECK(run_delayed(rel, traj));
@@ -1710,6 +2020,101 @@ struct Runner {
 }  // namespace
 
 namespace {
+
+// ---- autotuning of the fusion width and the tile width
+// Section 3.2: the best largest fused-gate size depends on the circuit and
+// the machine (larger on GPUs and for large circuits), and the choice is left
+// to trying values.  Here the driver tries them: for every candidate pair it
+// plans the circuit's default plan (each channel at its most likely pick) and
+// times one pass of it from |0...0> on the state's own stream, keeping the
+// fastest.  The choice is cached per (circuit, size, mode) for the life of
+// the process, so later calls, and the chunks of a concurrent call, run
+// the same plan.
+struct TuneKey {
+    uint64_t hash;
+    int n, mode, f_req, tb_req;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(hash, n, mode, f_req, tb_req) < std::tie(o.hash, o.n, o.mode, o.f_req, o.tb_req);
+    }
+};
+std::mutex g_tune_mu;  // one tuning at a time: concurrent trials would disturb each other's timings
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+
+// The widths a call runs with (tiles: 1 = none).  Tunes when max_fuse is 0
+// in the delayed mode; otherwise max_fuse (0: 4) and tile_bits (0: 13).
+qs_status resolve_widths(qs_state s, const CircuitModel &m, uint64_t chash, const qs_traj_params &p,
+                         int *f_out, int *tb_out, double *tune_ms) {
+    *tune_ms = 0.0;
+    *f_out = p.max_fuse > 0 ? p.max_fuse : kDefaultFuse;
+    *tb_out = p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits;
+    const bool tb_ok = p.tile_bits == 0 || p.tile_bits == 1 ||
+                       (p.tile_bits >= 10 && p.tile_bits <= qs::kMaxTileBits);
+    if (p.max_fuse != 0 || p.mode != QS_KRAUS_DELAYED || p.n_traj <= 0 || !tb_ok || m.n != s->n)
+        return QS_OK;
+    const std::vector<int> fs = m.n < 16 ? std::vector<int>{2, 3, 4, 5} : std::vector<int>{3, 4, 5};
+    std::vector<int> tbs;
+    if (p.tile_bits != 0) tbs = {p.tile_bits};
+    else if (m.n > 12) tbs = {12, 13, 14};  // smaller states fit one tile of any of these widths
+    else tbs = {qs::kDefaultTileBits};
+    const TuneKey key{chash, m.n, p.mode, p.max_fuse, p.tile_bits};
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+        *f_out = it->second.first;
+        *tb_out = it->second.second;
+        return QS_OK;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (auto &e : ev) QS_HIP(s, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int i = 0; i < 2; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } guard{ev};
+    const int reps = m.n >= 29 ? 1 : 2;  // the first of two also warms caches
+    double best = 1e300;
+    for (int f : fs) {
+        for (int tb : tbs) {
+            qs_traj_params q = p;
+            q.max_fuse = f;
+            q.tile_bits = tb;
+            q.flags = 0;
+            q.n_samples = 0;
+            qs_traj_result dummy;
+            std::memset(&dummy, 0, sizeof(dummy));
+            Runner trial(s, m, q, dummy);
+            trial.chash = chash;
+            trial.tuning = true;
+            QS_CHECK(trial.plan_delayed());
+            double t = 1e300;
+            for (int r = 0; r < reps; ++r) {
+                QS_HIP(s, hipEventRecord(ev[0], s->st));
+                QS_CHECK(trial.run_default_plan());
+                QS_HIP(s, hipEventRecord(ev[1], s->st));
+                QS_HIP(s, hipEventSynchronize(ev[1]));
+                float ms = 0.f;
+                QS_HIP(s, hipEventElapsedTime(&ms, ev[0], ev[1]));
+                t = std::min(t, double(ms));
+            }
+            if (t < best) {
+                best = t;
+                *f_out = f;
+                *tb_out = tb;
+            }
+        }
+    }
+    g_tune_cache[key] = {*f_out, *tb_out};
+    *tune_ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return QS_OK;
+}
+
+// Tile width reported for a run: 1 when the plan uses no tiles.
+int tile_bits_reported(int n, int tb) {
+    return (tb >= 10 && n >= qs::kTileMinQubits) ? std::min(tb, n) : 1;
+}
 
 // qs_run_trajectories, optionally reporting every timed bracket of sweeps as
 // an interval after the completed event `ref`.
@@ -1744,7 +2149,16 @@ qs_status run_trajectories_impl(qs_state s, const qs_circuit *c, const qs_traj_p
     r->gate_kernel_launches = 0;
     for (int i = 0; i < 6; ++i) r->gate_k_launches[i] = 0;
     r->zero_start_sweeps = 0;
-    Runner run(s, m, *p, *r, ref, intervals);
+    r->graph_replays = 0;
+    const uint64_t chash = circuit_hash(c);
+    qs_traj_params q = *p;
+    double tms = 0.0;
+    QS_CHECK(resolve_widths(s, m, chash, *p, &q.max_fuse, &q.tile_bits, &tms));
+    r->max_fuse_used = q.max_fuse;
+    r->tile_bits_used = tile_bits_reported(m.n, q.tile_bits);
+    r->tune_ms = tms;
+    Runner run(s, m, q, *r, ref, intervals);
+    run.chash = chash;
     const qs_status st = run.run();
     r->host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return st;
@@ -1794,8 +2208,20 @@ qs_status qs_run_trajectories_concurrent(qs_state *states, int n_states, const q
         return k;
     }();
     const int n = c->n_qubits;
+    // the widths are chosen once (tuning on the first state if asked), so
+    // every chunk runs the same plan as one state would
+    qs_traj_params pr = *p;
+    double tms = 0.0;
+    {
+        CircuitModel m;
+        QS_CHECK(build_model(c, m));
+        if (p->mode == QS_KRAUS_CONVENTIONAL_INPLACE)
+            for (auto &ci : m.channels) to_conventional(ci);
+        QS_CHECK(flush_pending(states[0]));
+        QS_CHECK(resolve_widths(states[0], m, circuit_hash(c), *p, &pr.max_fuse, &pr.tile_bits, &tms));
+    }
     // contiguous chunks, the first (n_traj mod n_states) one trajectory longer
-    std::vector<qs_traj_params> sp(n_states, *p);
+    std::vector<qs_traj_params> sp(n_states, pr);
     std::vector<qs_traj_result> sr(n_states);
     int64_t start = 0;
     for (int j = 0; j < n_states; ++j) {
@@ -1848,7 +2274,11 @@ qs_status qs_run_trajectories_concurrent(qs_state *states, int n_states, const q
     }
     for (auto &t : pool) t.join();
     r->sweeps = r->gate_sweeps = r->gate_kernel_launches = r->zero_start_sweeps = 0;
+    r->graph_replays = 0;
     r->gate_kernel_ms = 0.0;
+    r->max_fuse_used = sr[0].max_fuse_used;
+    r->tile_bits_used = sr[0].tile_bits_used;
+    r->tune_ms = tms;
     for (int i = 0; i < 6; ++i) r->gate_k_launches[i] = 0;
     for (int j = 0; j < n_states; ++j) {
         r->sweeps += sr[j].sweeps;
@@ -1856,6 +2286,7 @@ qs_status qs_run_trajectories_concurrent(qs_state *states, int n_states, const q
         r->gate_kernel_ms += sr[j].gate_kernel_ms;
         r->gate_kernel_launches += sr[j].gate_kernel_launches;
         r->zero_start_sweeps += sr[j].zero_start_sweeps;
+        r->graph_replays += sr[j].graph_replays;
         for (int i = 0; i < 6; ++i) r->gate_k_launches[i] += sr[j].gate_k_launches[i];
     }
     if (timing) {
@@ -2001,15 +2432,14 @@ void to_float2(int D, const cd *m, float2 *out) {
 
 }  // namespace
 
-extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
-                                    const qs_batch_params *bp, qs_batch_result *r) {
+namespace {
+
+qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_batch_params *bp,
+                           int f, qs_batch_result *r) {
     const auto t0 = std::chrono::steady_clock::now();
-    if (!items || n_items < 0 || !bp || !r) return fail(QS_ERR_INVALID_ARGUMENT, "null argument");
-    if (bp->max_fuse < 0 || bp->max_fuse > qs::kMaxGateQubits)
-        return fail(QS_ERR_INVALID_ARGUMENT, "max_fuse outside 0..5");
-    const int f = bp->max_fuse > 0 ? bp->max_fuse : kBatchDefaultFuse;
     hipStream_t st = static_cast<hipStream_t>(bp->hip_stream);
     std::memset(r, 0, sizeof(*r));
+    r->max_fuse_used = f;
 
     // ---- per-circuit plans (threads over circuits), then concatenated
     std::vector<BatchPlanCircuit> plans(n_items);
@@ -2427,4 +2857,69 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
     }
     r->host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return QS_OK;
+}
+
+// Batched autotuning (Section 3.2's fusion-width choice, measured): every
+// candidate width runs the batch cut to at most two trajectories per circuit,
+// timed whole (host planning of the patched blocks, upload and the launch:
+// a wider fusion shortens the kernel but lengthens the planning), and the
+// fastest is kept, cached per batch of circuits for the life of the process.
+std::mutex g_btune_mu;
+std::map<std::pair<uint64_t, int>, int> g_btune_cache;
+
+}  // namespace
+
+extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
+                                    const qs_batch_params *bp, qs_batch_result *r) {
+    if (!items || n_items < 0 || !bp || !r) return fail(QS_ERR_INVALID_ARGUMENT, "null argument");
+    if (bp->max_fuse < 0 || bp->max_fuse > qs::kMaxGateQubits)
+        return fail(QS_ERR_INVALID_ARGUMENT, "max_fuse outside 0..5");
+    if (bp->max_fuse > 0) return run_batched_impl(items, n_items, bp, bp->max_fuse, r);
+    for (int it = 0; it < n_items; ++it)
+        if (!items[it].circuit || !items[it].circuit->ops || !items[it].circuit->mat_pool ||
+            items[it].circuit->n_ops < 0 || items[it].circuit->pool_len < 0)
+            return fail(QS_ERR_INVALID_ARGUMENT, "null circuit");
+    uint64_t h = 1469598103934665603ull;
+    for (int it = 0; it < n_items; ++it) h = (h ^ circuit_hash(items[it].circuit)) * 1099511628211ull;
+    const auto key = std::make_pair(h, n_items);
+    const auto t0 = std::chrono::steady_clock::now();
+    int f = kBatchDefaultFuse;
+    double tune_ms = 0.0;
+    {
+        std::lock_guard<std::mutex> lock(g_btune_mu);
+        auto found = g_btune_cache.find(key);
+        if (found != g_btune_cache.end()) {
+            f = found->second;
+        } else {
+            std::vector<qs_batch_item> trial(items, items + n_items);
+            size_t outs = 0;
+            for (auto &I : trial) {
+                I.n_traj = std::min<int64_t>(I.n_traj, 2);
+                outs += size_t(I.n_traj) * size_t(std::max(I.n_samples, 0));
+                I.kraus_choices = nullptr;
+            }
+            std::vector<uint64_t> scratch_bits(std::max<size_t>(outs, 1));
+            size_t pos = 0;
+            for (auto &I : trial) {
+                I.bitstrings = scratch_bits.data() + pos;
+                pos += size_t(I.n_traj) * size_t(std::max(I.n_samples, 0));
+            }
+            qs_batch_params tp = *bp;
+            tp.flags &= ~uint32_t(QS_TRAJ_TIME_KERNELS);
+            double best = 1e300;
+            for (int cand : {2, 3, 4, 5}) {
+                qs_batch_result tr;
+                QS_CHECK(run_batched_impl(trial.data(), n_items, &tp, cand, &tr));
+                if (tr.host_seconds < best) {
+                    best = tr.host_seconds;
+                    f = cand;
+                }
+            }
+            g_btune_cache[key] = f;
+            tune_ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+    }
+    const qs_status st = run_batched_impl(items, n_items, bp, f, r);
+    r->tune_ms = tune_ms;
+    return st;
 }

@@ -77,6 +77,29 @@ def pair_inverse_cdf(w, n, u):
     return x, margin
 
 
+def pair_prefix(w, n, x):
+    """Exclusive and inclusive prefix of |psi|^2 in index order at index x
+    for the pair-product state: (sum over y < x, sum over y <= x), decided
+    bit by bit from the top like pair_inverse_cdf."""
+    h = n // 2
+    p = [np.abs(v) ** 2 / np.sum(np.abs(v) ** 2) for v in w]
+    cum, mass = 0.0, 1.0
+    for j in range(n - 1, -1, -1):
+        if j >= h:
+            q = j - h
+            p0 = p[q][0] + p[q][1]
+        else:
+            q = j
+            b = (x >> (q + h)) & 1
+            p0 = p[q][2 * b] / (p[q][2 * b] + p[q][2 * b + 1])
+        if (x >> j) & 1:
+            cum += mass * p0
+            mass *= 1.0 - p0
+        else:
+            mass *= p0
+    return cum, cum + mass
+
+
 def ghz_circuit(n):
     H = np.array([[1, 1], [1, -1]], dtype=np.complex128) / math.sqrt(2.0)
     # matrix bit 0 <-> control, bit 1 <-> target: |c=1,t=0> (index 1) <-> |1,1> (index 3)

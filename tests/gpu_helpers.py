@@ -40,3 +40,31 @@ def compare_choices(gpu_choices, orc_res):
             return compared, 1
         compared += 1
     return compared, 0
+
+
+def true_outcomes(samples, n, seed, traj, circ, draw, e=None):
+    """Undo symmetric readout flips (P(1|0) = P(0|1) = e[q]): qubit q of
+    sample s was flipped iff its readout draw (stream 2, index s n + q) is
+    below e[q], whatever the true bit, so the flips are known from the draws."""
+    x = np.asarray(samples, dtype=np.uint64).copy()
+    if e is None:
+        return x
+    for s in range(len(x)):
+        for q in range(n):
+            if draw(seed, s * n + q, traj, circ, 2) < e[q]:
+                x[s] ^= np.uint64(1 << q)
+    return x
+
+
+def bracket_violations(outcomes, prefix, seed, traj, circ, draw, tol=SAMPLE_TIE):
+    """Samples whose outcome x is not an inverse-CDF answer for their draw u
+    within tol: the rule is C(x - 1) <= u < C(x) with C the normalised
+    inclusive prefix of |psi|^2 in index order; prefix(x) returns
+    (C(x - 1), C(x)).  Returns the indices of violating samples."""
+    bad = []
+    for s, x in enumerate(outcomes):
+        u = draw(seed, s, traj, circ, 1)
+        lo, hi = prefix(int(x))
+        if not (lo - tol <= u < hi + tol):
+            bad.append(s)
+    return bad

@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 import workloads as W
-from closed_forms import ghz_circuit, mirror_circuit, pair_amplitudes, pair_inverse_cdf, pair_product
+from closed_forms import (ghz_circuit, mirror_circuit, pair_amplitudes, pair_inverse_cdf,
+                          pair_prefix, pair_product)
 
 
 @pytest.mark.parametrize("n", [6, 10])
@@ -28,6 +29,19 @@ def test_pair_product_against_oracle(orc, n):
         p = np.abs(w[q]) ** 2
         assert abs(z[q] - (p[0] - p[1] + p[2] - p[3])) < 1e-12
         assert abs(z[q + h] - (p[0] + p[1] - p[2] - p[3])) < 1e-12
+
+
+@pytest.mark.parametrize("n", [4, 8])
+def test_pair_prefix_against_oracle(orc, n):
+    """The bit-by-bit prefix of the pair-product state equals the running sum
+    of the oracle's |psi_x|^2 at every index."""
+    c, w = pair_product(n, seed=3 * n)
+    psi = orc.simulate(c)
+    C = np.cumsum(np.abs(psi) ** 2)
+    for x in range(1 << n):
+        lo, hi = pair_prefix(w, n, x)
+        assert abs(hi - C[x]) < 1e-13
+        assert abs(lo - (C[x - 1] if x else 0.0)) < 1e-13
 
 
 def test_pair_inverse_cdf_margin_is_a_boundary_distance():

@@ -48,4 +48,5 @@ from .configs import (  # noqa: F401
     noisy_grid_workload,
     batched_workload,
     serving_requests,
+    TrajectoryWorkload,
 )
