@@ -101,6 +101,7 @@ class Server:
             budget_bytes = int(min(free * 0.9, 288e9))
         self.budget = budget_bytes
         self.used = 0
+        self.peak_used = 0  # the most footprint admitted at once
         self.slot_workers = slot_workers
         self.max_fuse_batch = max_fuse_batch
         self.max_fuse_slot = max_fuse_slot
@@ -123,6 +124,7 @@ class Server:
         if self.used + need > self.budget:
             return False
         self.used += need
+        self.peak_used = max(self.peak_used, self.used)
         self.results[req.rid].admitted_s = self._now()
         return True
 
