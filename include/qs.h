@@ -246,6 +246,26 @@ qs_status qs_sample_measurements(qs_state s, uint64_t seed, uint32_t traj, int n
                                  const double *p0to1, const double *p1to0,
                                  uint64_t *bitstrings_out);
 
+/* For callers that cannot allocate device or pinned memory (tight serving
+ * loops, harnesses that forbid hipMalloc, code that must not allocate while
+ * other work is being captured): qs_sample_measurements with the
+ * same arguments, the same kernels and bit-identical bitstrings, whose
+ * device buffers (block sums, prefix, norm, bitstrings) live in one fixed
+ * 4.5 MiB array per GPU that the library holds until the process ends.  It
+ * calls no hipMalloc, hipHostMalloc or hipFree: the norm and the bitstrings
+ * are copied straight into the caller's host memory.
+ * Limits: the state has at most 28 qubits and 0 <= n_samples <= 65536;
+ * beyond them it returns QS_ERR_INVALID_ARGUMENT without device work.  The
+ * state must have no deferred operations (applying them may need staging
+ * memory): call qs_flush first, else QS_ERR_INVALID_ARGUMENT.
+ * Every call on one GPU uses that GPU's array, so calls that overlap on one
+ * GPU (from several host threads or streams) race; the array keeps the last
+ * call's contents, and every call writes all it reads.
+ * Errors: INVALID_ARGUMENT, ZERO_NORM, DEVICE. */
+qs_status qs_sample_measurements_noalloc(qs_state s, uint64_t seed, uint32_t traj, int n_samples,
+                                         const double *p0to1, const double *p1to0,
+                                         uint64_t *bitstrings_out);
+
 /* Run n_traj noisy trajectories of one circuit on this state's buffer and
  * stream (Section 3.5): per trajectory, reset to |0...0>, draw one r per
  * channel, classify each channel as picked-from-bounds or needing inner

@@ -124,6 +124,7 @@ def load():
         "qs_expectation_z": [vp, vp],
         "qs_expectation": [vp, i32, vp, vp, vp],
         "qs_sample_measurements": [vp, u64, u32, i32, vp, vp, vp],
+        "qs_sample_measurements_noalloc": [vp, u64, u32, i32, vp, vp, vp],
         "qs_run_trajectories": [vp, vp, vp, vp],
         "qs_run_trajectories_concurrent": [vp, i32, vp, vp, vp],
         "qs_kraus_bounds": [i32, i32, vp, vp, vp],
@@ -249,6 +250,16 @@ def qs_sample_measurements(s, seed: int, traj: int, n_samples: int, p0to1=None, 
     e0 = None if p0to1 is None else np.ascontiguousarray(p0to1, dtype=np.float64)
     e1 = None if p1to0 is None else np.ascontiguousarray(p1to0, dtype=np.float64)
     _check(load().qs_sample_measurements(s, seed, traj, n_samples, _p(e0), _p(e1), _p(out)))
+    return out[:n_samples]
+
+
+def qs_sample_measurements_noalloc(s, seed: int, traj: int, n_samples: int, p0to1=None,
+                                   p1to0=None):
+    out = np.zeros(max(n_samples, 1), dtype=np.uint64)
+    e0 = None if p0to1 is None else np.ascontiguousarray(p0to1, dtype=np.float64)
+    e1 = None if p1to0 is None else np.ascontiguousarray(p1to0, dtype=np.float64)
+    _check(load().qs_sample_measurements_noalloc(s, seed, traj, n_samples, _p(e0), _p(e1),
+                                                 _p(out)))
     return out[:n_samples]
 
 

@@ -193,6 +193,21 @@ hipError_t launch_sample(const float2 *amp, int n, double *sums, double *incl,
                          const ReadoutDesc &ro, uint64_t *out_dev, double *norm_dev,
                          hipStream_t st);
 
+// Allocation-free sampling (qs_sample_measurements_noalloc): one fixed
+// device array per GPU holds the block sums, their prefix, the norm and the
+// bitstrings of one call.  Layout in doubles: sums [0, NB), incl [NB, 2 NB),
+// norm at 2 NB, bitstrings (uint64) from 2 NB + 32 on.
+constexpr int kNoAllocMaxQubits = 28;
+constexpr int kNoAllocMaxSamples = 1 << 16;
+constexpr size_t kNoAllocBlocks = size_t(1) << (kNoAllocMaxQubits - kSampleBlockBits);
+constexpr size_t kNoAllocNormOffset = 2 * kNoAllocBlocks;
+constexpr size_t kNoAllocOutOffset = 2 * kNoAllocBlocks + 32;
+constexpr size_t kNoAllocDoubles = kNoAllocOutOffset + size_t(kNoAllocMaxSamples);
+
+// Device address of that array on `device` (looked up once per device, with
+// the device current; the caller's current device is restored).
+hipError_t noalloc_scratch(int device, double **out);
+
 // Device-side branch selection for a channel that needs inner products
 // (Algorithm 2, steps 13-20): from the FP64 reduced density matrix R (as
 // written by launch_rdm), e_i = Re Tr((K_i^dag K_i - pbar_i I) R) / N; the

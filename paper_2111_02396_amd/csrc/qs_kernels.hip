@@ -13,6 +13,8 @@
 //    work-item per sample with Philox draws.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "qs_internal.h"
 #include "qs_philox.h"
 
@@ -1597,6 +1599,39 @@ hipError_t launch_apply_copy_norm(const float2 *in, float2 *out, int n, const Ga
     }
     reduce_records<<<1, kBlock, 0, st>>>(partials, nb, 2, out_dev);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- allocation-free sampling
+
+// The sampling buffers of qs_sample_measurements_noalloc: a fixed array per
+// GPU, held until the process ends (4.5 MiB: block sums and prefix for up to
+// 2^28 amplitudes, the norm, up to 2^16 bitstrings).  Host code must not pass
+// `scratch` itself to a kernel (in host code the name is a stand-in, not a
+// device address): it uses the address noalloc_scratch looked up.
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_dev[64] = {};  // per device, filled once
+}  // namespace
+
+hipError_t noalloc_scratch(int device, double **out) {
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != device) (void)hipSetDevice(prev);
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[device] = static_cast<double *>(p);
+    }
+    *out = g_scratch_dev[device];
+    return hipSuccess;
 }
 
 hipError_t launch_sample(const float2 *amp, int n, double *sums, double *incl, uint64_t seed,

@@ -818,6 +818,41 @@ qs_status qs_sample_measurements(qs_state s, uint64_t seed, uint32_t traj, int n
     return QS_OK;
 }
 
+qs_status qs_sample_measurements_noalloc(qs_state s, uint64_t seed, uint32_t traj, int n_samples,
+                                         const double *p0to1, const double *p1to0,
+                                         uint64_t *bitstrings_out) {
+    QS_CHECK(check_handle(s));
+    if (n_samples < 0 || (n_samples > 0 && !bitstrings_out))
+        return fail(QS_ERR_INVALID_ARGUMENT, "bad sample arguments");
+    if (s->n > qs::kNoAllocMaxQubits)
+        return fail(QS_ERR_INVALID_ARGUMENT,
+                    "allocation-free sampling takes states of at most 28 qubits");
+    if (n_samples > qs::kNoAllocMaxSamples)
+        return fail(QS_ERR_INVALID_ARGUMENT,
+                    "allocation-free sampling draws at most 65536 samples per call");
+    if (!s->pending.empty())
+        return fail(QS_ERR_INVALID_ARGUMENT,
+                    "deferred operations pending: call qs_flush before allocation-free sampling");
+    qs::ReadoutDesc ro;
+    QS_CHECK(fill_readout(s->n, p0to1, p1to0, ro));
+    double *base = nullptr;
+    QS_HIP(s, qs::noalloc_scratch(s->device, &base));
+    double *sums = base, *incl = base + qs::kNoAllocBlocks, *norm = base + qs::kNoAllocNormOffset;
+    uint64_t *out = reinterpret_cast<uint64_t *>(base + qs::kNoAllocOutOffset);
+    QS_HIP(s, qs::launch_sample(s->amp, s->n, sums, incl, seed, traj, 0, n_samples, ro, out, norm,
+                                s->st));
+    double N = 0.0;
+    QS_HIP(s, hipMemcpyAsync(&N, norm, sizeof(double), hipMemcpyDeviceToHost, s->st));
+    QS_HIP(s, hipStreamSynchronize(s->st));
+    if (!(N > 0.0) || !std::isfinite(N)) return fail(QS_ERR_ZERO_NORM, "state has zero norm");
+    if (n_samples > 0) {
+        QS_HIP(s, hipMemcpyAsync(bitstrings_out, out, sizeof(uint64_t) * n_samples,
+                                 hipMemcpyDeviceToHost, s->st));
+        QS_HIP(s, hipStreamSynchronize(s->st));
+    }
+    return QS_OK;
+}
+
 // --------------------------------------------------------------------------
 // Trajectory driver.
 // --------------------------------------------------------------------------
