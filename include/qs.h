@@ -151,7 +151,10 @@ typedef struct {
 
 /* ---- state lifecycle ---------------------------------------------------- */
 
-/* Create an n-qubit state set to |0...0>.
+/* Create an n-qubit state set to |0...0> (Section 3: the simulator keeps the
+ * 2^n complex amplitudes of the state, in single precision; Section 4.1: a
+ * state takes 8 * 2^n bytes, up to twice that while a noisy trajectory needs
+ * a second state, as the conventional method does here).
  * device_buf: NULL = the library allocates 8*2^n bytes; otherwise a device
  *   buffer of at least 8*2^n bytes (buf_bytes), 16-byte aligned (kernels move
  *   amplitude pairs), that the caller keeps alive.
@@ -215,7 +218,10 @@ qs_status qs_apply_channel(qs_state s, int k, const int *targets, int n_kraus,
                            int *path_out);
 
 /* N = <psi|psi> of the stored vector, accumulated in FP64 with a fixed
- * reduction order (bit-identical run to run).  Flushes; synchronises. */
+ * reduction order (bit-identical run to run).  Section 3.5 defines each
+ * Kraus probability as p_i = <Psi|K_i^dag K_i|Psi> on the normalised state;
+ * with lazy normalisation every probability and sample divides by this N.
+ * Flushes; synchronises.  Errors: INVALID_ARGUMENT (null output), DEVICE. */
 qs_status qs_norm(qs_state s, double *norm_sq_out);
 
 /* Observable estimation on the trajectory's state (Section 3.5: an
@@ -360,6 +366,13 @@ typedef struct {
  * workgroup then samples with readout flips exactly as
  * qs_sample_measurements does (same Philox streams, circuit id from the
  * item).  Results are written to each item's host arrays.
+ * Only mixtures of unitaries are taken: for them Algorithm 2 never needs an
+ * inner product (the bounds sum to one), so every trajectory's program is
+ * fixed before the launch and the workgroups never wait on a reduction.  A
+ * channel with rank-deficient or non-normal Kraus operators (amplitude or
+ * phase damping) needs the state-dependent second loop of Algorithm 2;
+ * circuits with such channels go through qs_run_trajectories (the serving
+ * loop sends them to its slot lane).
  * Errors: INVALID_ARGUMENT, NOT_SUPPORTED (n > 18, a channel that is not a
  * mixture), OUT_OF_MEMORY, DEVICE. */
 qs_status qs_run_batched(const qs_batch_item *items, int n_items, const qs_batch_params *p,

@@ -53,13 +53,18 @@ constexpr int kDefaultTileBits = 13;  // tile sweeps when the caller asks for th
 constexpr int kMaxTileGates = 28;  // keeps TileArgs (a kernel argument) under 4 KiB
 constexpr int kTileMinQubits = 10;
 constexpr int kTileMatBudget = 4096;  // float2 of matrices staged per launch (32 KiB)
+// What the sweep planner lets one launch stage: 13-bit tiles run two
+// 512-work-item groups per CU, which fit the 160 KiB of LDS only with at
+// most 16 KiB of matrices each (64 KiB tile + 16 KiB, twice).
+inline int tile_mat_budget(int tile_bits) { return tile_bits == 13 ? 2048 : kTileMatBudget; }
 
 // LDS float2 slots a gate's matrix takes in a tile launch: none for k <= 2
 // (read from global memory), MFMA fragments for k = 3 (256 floats), k = 4
 // (768 floats: three real 16x16 matrices) and k = 5 (3072 floats: three real
-// 32x32 matrices; narrow tiles use the first 1024 slots for the plain matrix).
+// 32x32 matrices; narrow tiles use the first 1024 slots for the plain
+// matrix), each followed by a 64-entry per-lane offset table (32 slots).
 __host__ __device__ inline int tile_mat_slots(int k) {
-    return k <= 2 ? 0 : (k == 3 ? 128 : (k == 4 ? 384 : 1536));
+    return k <= 2 ? 0 : (k == 3 ? 160 : (k == 4 ? 416 : 1568));
 }
 
 struct TileGate {

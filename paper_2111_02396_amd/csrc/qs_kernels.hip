@@ -197,6 +197,13 @@ __device__ __forceinline__ float2 lds_get(const float2 *sd, int byte) {
 __device__ __forceinline__ void lds_put(float2 *sd, int byte, float2 v) {
     *reinterpret_cast<float2 *>(reinterpret_cast<char *>(sd) + byte) = v;
 }
+// The real and imaginary parts from two accumulators, as two 4-byte stores
+// (one ds_write2_b32, with no register moves to pair them).
+__device__ __forceinline__ void lds_put2(float2 *sd, int byte, float re, float im) {
+    float *p = reinterpret_cast<float *>(reinterpret_cast<char *>(sd) + byte);
+    p[0] = re;
+    p[1] = im;
+}
 __device__ __forceinline__ float lds_getf(const float2 *sd, int byte) {
     return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(sd) + byte);
 }
@@ -301,14 +308,61 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // A fused k-qubit block is a dense contraction W = U V over the tile's
-// 2^(tb-k) index groups.  For k = 3, 4 it runs on FP32 MFMA with U in its
-// real form [[Re U, -Im U], [Im U, Re U]], rows and columns interleaved as
-// 2 j + c (c = 0 real, 1 imaginary).  The A operand (the real form) is laid
-// out per lane once per launch ("fragments"); B comes from the tile in LDS.
+// 2^(tb-k) index groups.  For k = 3, 4, 5 it runs on FP32 MFMA
+// (v_mfma_f32_16x16x4f32: in step s lane l supplies A[l%16][4s + l/16] and
+// B[4s + l/16][l%16]; accumulator r is row 4(l/16) + r, column l%16), 16
+// groups per wavefront batch, the groups' amplitudes (or real components)
+// as B, the matrix as A laid out per lane once per launch ("fragments").
+//
+// The contraction index is permuted so that every lane supplies exactly the
+// amplitudes its accumulators return: lane (n, q) = (l%16, l/16) reads and
+// writes the same LDS words, and one address set per batch serves both.
+// Physical step s, lane quarter q carries logical input index pi(4s + q),
+// and the fragments hold the matrix columns in that order.
+//
+// Every gate also gets a per-lane LDS offset table staged after its
+// fragments (lane_base): the lane part of its addresses (group index low
+// bits n, quarter q), which would otherwise take some thirty VALU
+// instructions per gate and tile on every wavefront.
+constexpr int kFrag3 = 64 * 4;   // floats of k = 3 fragments; the lane table follows
+constexpr int kFrag4 = 64 * 12;
+constexpr int kFrag5 = 64 * 48;
 
 // Real-form entry (row 2 jo + co, column 2 ji + ci) of a complex matrix.
 __device__ __forceinline__ float real_form(float2 u, int co, int ci) {
     return co == 0 ? (ci == 0 ? u.x : -u.y) : (ci == 0 ? u.y : u.x);
+}
+
+// The lane table of a gate: table[lane] = XOR of tab[] over the lane's
+// group bits n (logical bits nb..nb+3) and quarter bits q (logical bits
+// qb, qb+1).
+template <int NT>
+__device__ __forceinline__ void stage_lane_table(int *__restrict__ table, const int *tab, int nb, int qb) {
+    for (int lane = threadIdx.x; lane < 64; lane += NT) {
+        int v = 0;
+        for (int b = 0; b < 4; ++b)
+            if ((lane >> b) & 1) v ^= tab[nb + b];
+        for (int b = 0; b < 2; ++b)
+            if ((lane >> (4 + b)) & 1) v ^= tab[qb + b];
+        table[lane] = v;
+    }
+}
+
+// k = 3 in the real form [[Re U, -Im U], [Im U, Re U]] (rows and columns
+// interleaved as 2 j + c, c = 0 real, 1 imaginary).  Lane quarter q supplies
+// the real components 4q + s (s = 0..3) of its group, i.e. amplitudes 2q and
+// 2q + 1, and its accumulator rows 4q + r are the same components.
+// Fragments: frag[lane * 4 + s] = RealForm[l%16][4 (l/16) + s].
+// Lane table: group bits are logical bits 3.., amplitude 2q has q at bits 1, 2.
+template <int NT = kBlock>
+__device__ __forceinline__ void stage_frag3(float *__restrict__ frag, const float2 *__restrict__ u,
+                                            const int *tab) {
+    for (int i = threadIdx.x; i < 64 * 4; i += NT) {
+        const int lane = i >> 2, s = i & 3;
+        const int row = lane & 15, col = 4 * (lane >> 4) + s;
+        frag[i] = real_form(u[(row >> 1) * 8 + (col >> 1)], row & 1, col & 1);
+    }
+    stage_lane_table<NT>(reinterpret_cast<int *>(frag + kFrag3), tab, 3, 1);
 }
 
 // k = 4 with three real products instead of four (Gauss), arranged so that
@@ -316,75 +370,104 @@ __device__ __forceinline__ float real_form(float2 u, int co, int ci) {
 // with k1 = A (x + y),
 //   Re Uv = A x - B y = k1 - (A + B) y,   Im Uv = B x + A y = k1 + (B - A) x,
 // so one chain forms k1 and two chains seeded with it add (-(A + B)) y and
-// (B - A) x.  The only per-amplitude vector work left is x + y.
-// v_mfma_f32_16x16x4f32: in step s lane l supplies A[l%16][4s + l/16] and
-// B[4s + l/16][l%16]; accumulator r is row 4(l/16) + r, column l%16.
-// Fragment layout: frag[lane * 12 + 4 m + s] = M_m[l%16][4s + l/16] with
+// (B - A) x.  The only per-amplitude vector work left is x + y.  Lane
+// quarter q supplies amplitudes 4q + s in step s and returns 4q + r.
+// Fragments: frag[lane * 12 + 4 m + s] = M_m[l%16][4 (l/16) + s] with
 // M_0 = Re U, M_1 = -(Re U + Im U), M_2 = Im U - Re U.
+// Lane table: group bits are logical bits 4.., q at bits 2, 3.
 template <int NT = kBlock>
-__device__ __forceinline__ void stage_frag4(float *__restrict__ frag, const float2 *__restrict__ u) {
+__device__ __forceinline__ void stage_frag4(float *__restrict__ frag, const float2 *__restrict__ u,
+                                            const int *tab) {
     for (int i = threadIdx.x; i < 64 * 12; i += NT) {
         const int lane = i / 12, rem = i - 12 * lane;
         const int m = rem >> 2, s = rem & 3;
-        const float2 e = u[(lane & 15) * 16 + 4 * s + (lane >> 4)];
+        const float2 e = u[(lane & 15) * 16 + 4 * (lane >> 4) + s];
         frag[i] = m == 0 ? e.x : (m == 1 ? -(e.x + e.y) : e.y - e.x);
     }
+    stage_lane_table<NT>(reinterpret_cast<int *>(frag + kFrag4), tab, 4, 2);
 }
 
-// k = 3, v_mfma_f32_16x16x4f32: lane l supplies A[l%16][l/16] and B[l/16][l%16];
-// step s covers real columns 4s..4s+3: lane quarter q = l/16 reads amplitude
-// j = 2s + q/2 and uses component q%2.  Fragment layout: frag[lane * 4 + s].
+// k = 5: the same three real products as k = 4, each now a 32 x 32 matrix.
+// The 32 output rows form two halves h (rows 16 h + i) and the contraction
+// runs in eight steps of four: lane quarter q supplies amplitude
+// 16 (s / 4) + 4 q + s % 4 in step s and accumulator r of half h returns
+// 16 h + 4 q + r.  48 MFMAs per 16 groups (a 5-qubit block is the densest
+// contraction of a sweep: 16 flops per byte moved, Section 3.1).
+// Fragments: frag[lane * 48 + 24 h + 8 m + s] = M_m[16 h + l%16][16 (s / 4) +
+// 4 (l/16) + s % 4].  Lane table: group bits are logical bits 5.., q at 2, 3.
 template <int NT = kBlock>
-__device__ __forceinline__ void stage_frag3(float *__restrict__ frag, const float2 *__restrict__ u) {
-    for (int i = threadIdx.x; i < 64 * 4; i += NT) {
-        const int lane = i >> 2, s = i & 3;
-        const int m = lane & 15, q = lane >> 4;
-        const int ji = 2 * s + (q >> 1);
-        frag[i] = real_form(u[(m >> 1) * 8 + ji], m & 1, q & 1);
+__device__ __forceinline__ void stage_frag5(float *__restrict__ frag, const float2 *__restrict__ u,
+                                            const int *tab) {
+    for (int i = threadIdx.x; i < 64 * 48; i += NT) {
+        const int lane = i / 48, rem = i - 48 * lane;
+        const int h = rem / 24, m = (rem % 24) >> 3, s = rem & 7;
+        const float2 e = u[(16 * h + (lane & 15)) * 32 + 16 * (s >> 2) + 4 * (lane >> 4) + (s & 3)];
+        frag[i] = m == 0 ? e.x : (m == 1 ? -(e.x + e.y) : e.y - e.x);
     }
+    stage_lane_table<NT>(reinterpret_cast<int *>(frag + kFrag5), tab, 5, 2);
 }
 
-// 16 groups per wavefront iteration: lane (n, q) = (l%16, l/16) reads
-// amplitudes 4s + q of group n and ends with amplitudes 4q + r.  The next
-// iteration's amplitudes are read before this one's MFMAs, so the LDS latency
-// hides behind them; iterations touch disjoint groups, so reading ahead of
-// the writes is safe.
+// 16 groups per wavefront batch; the next batch's amplitudes are read before
+// this one's MFMAs, so the LDS latency hides behind them (batches touch
+// disjoint groups, so reading ahead of the writes is safe).  The batch index
+// b = wave + W it occupies the logical bits after the lane's group bits.
+template <class L, int NT = kBlock>
+__device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const float *__restrict__ frag,
+                                                const int *tab, int tb) {
+    constexpr int W = NT / 64;
+    constexpr int LW = ilog2(W);
+    const int lane = threadIdx.x & 63, wave = wave_index();
+    const f32x4 afr = *reinterpret_cast<const f32x4 *>(frag + lane * 4);
+    const int a0 = reinterpret_cast<const int *>(frag + kFrag3)[lane];  // amplitude 2q
+    const int a1 = a0 ^ tab[0];                                         // amplitude 2q + 1
+    const int iters = (1 << (tb - 3 - 4)) / W;  // batches per wave: >= 1 needs tb >= 7 + log2 W
+    const int uw = tab_xor<LW>(tab, 7, wave);
+    int ub = uw;
+    float2 v0 = lds_get(sd, a0 ^ ub), v1 = lds_get(sd, a1 ^ ub);
+    for (int it = 0; it < iters; ++it) {
+        prio_for_remaining(iters - it);
+        const int itn = it + 1 < iters ? it + 1 : it;
+        const int ubn = uw ^ tab_xor<kMaxTileBits - 7 - LW>(tab, 7 + LW, itn);
+        const float2 w0 = lds_get(sd, a0 ^ ubn), w1 = lds_get(sd, a1 ^ ubn);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[0], v0.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[1], v0.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[2], v1.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[3], v1.y, acc, 0, 0, 0);
+        lds_put(sd, a0 ^ ub, make_float2(acc[0], acc[1]));
+        lds_put(sd, a1 ^ ub, make_float2(acc[2], acc[3]));
+        ub = ubn;
+        v0 = w0;
+        v1 = w1;
+    }
+    __builtin_amdgcn_s_setprio(0);
+}
+
 template <class L, int NT = kBlock>
 __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const float *__restrict__ frag,
                                                 const int *tab, int tb) {
     constexpr int W = NT / 64;
     constexpr int LW = ilog2(W);
     const int lane = threadIdx.x & 63, wave = wave_index();
-    const int n = lane & 15, q = lane >> 4;
     const f32x4 *fp = reinterpret_cast<const f32x4 *>(frag + lane * 12);
     const f32x4 fa = fp[0], fb = fp[1], fs = fp[2];
-    // LDS byte offset of amplitude j of group 16 b + n: the group index is
-    // logical bits 4.. of the gate's frame (n its low four), j its targets;
-    // with j = 4 s + q (inputs) or 4 q + r (outputs) the offset is a per-lane
-    // part (n, q, and the unrolled s or r) XOR a wave-uniform part (b).
-    const int lane_part = tab_xor<4>(tab, 4, n);
-    const int lin = lane_part ^ tab_xor<2>(tab, 0, q);
-    const int lout = lane_part ^ tab_xor<2>(tab, 2, q);
-    int ain[4], aout[4];
+    const int base = reinterpret_cast<const int *>(frag + kFrag4)[lane];
+    int a[4];  // amplitude 4q + s of the lane's group
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        ain[s] = lin ^ tab_xor<2>(tab, 2, s);
-        aout[s] = lout ^ tab_xor<2>(tab, 0, s);
-    }
+    for (int s = 0; s < 4; ++s) a[s] = base ^ tab_xor<2>(tab, 0, s);
     const int iters = (1 << (tb - 4 - 4)) / W;  // batches per wave: >= 1 needs tb >= 8 + log2 W
-    // batch b = wave + W it: its bits are logical bits 8.. (wave) and 8 + LW.. (it)
     const int uw = tab_xor<LW>(tab, 8, wave);
     int ub = uw;
     float2 v[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = lds_get(sd, ain[s] ^ ub);
+    for (int s = 0; s < 4; ++s) v[s] = lds_get(sd, a[s] ^ ub);
     for (int it = 0; it < iters; ++it) {
         prio_for_remaining(iters - it);
         const int itn = it + 1 < iters ? it + 1 : it;
         const int ubn = uw ^ tab_xor<kMaxTileBits - 8 - LW>(tab, 8 + LW, itn);
         float2 w[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) w[s] = lds_get(sd, ain[s] ^ ubn);
+        for (int s = 0; s < 4; ++s) w[s] = lds_get(sd, a[s] ^ ubn);
         f32x4 k1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < 4; ++s) k1 = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[s], v[s].x + v[s].y, k1, 0, 0, 0);
@@ -395,11 +478,7 @@ __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const f
             im = __builtin_amdgcn_mfma_f32_16x16x4f32(fs[s], v[s].x, im, 0, 0, 0);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            char *dst = reinterpret_cast<char *>(sd) + (aout[r] ^ ub);
-            reinterpret_cast<float *>(dst)[0] = re[r];
-            reinterpret_cast<float *>(dst)[1] = im[r];
-        }
+        for (int r = 0; r < 4; ++r) lds_put2(sd, a[r] ^ ub, re[r], im[r]);
         ub = ubn;
 #pragma unroll
         for (int s = 0; s < 4; ++s) v[s] = w[s];
@@ -407,64 +486,37 @@ __device__ __forceinline__ void tile_gate_mfma4(float2 *__restrict__ sd, const f
     __builtin_amdgcn_s_setprio(0);
 }
 
-// k = 5: the same three real products as k = 4, each now a 32 x 32 matrix.
-// The 32 output rows form two halves h (rows 16 h + i) and the contraction
-// over the 32 inputs runs in eight steps of four.  In step s lane (n, q) =
-// (l%16, l/16) supplies amplitude 4 s + q of group n; accumulator r of half h
-// is output 16 h + 4 q + r.  Fragment layout:
-// frag[lane * 48 + 24 h + 8 m + s] = M_m[16 h + l%16][4 s + l/16], with the
-// M_m of k = 4.  48 MFMAs per 16 groups (a 5-qubit block is the densest
-// contraction of a sweep: 16 flops per byte moved, Section 3.1).
-template <int NT = kBlock>
-__device__ __forceinline__ void stage_frag5(float *__restrict__ frag, const float2 *__restrict__ u) {
-    for (int i = threadIdx.x; i < 64 * 48; i += NT) {
-        const int lane = i / 48, rem = i - 48 * lane;
-        const int h = rem / 24, m = (rem % 24) >> 3, s = rem & 7;
-        const float2 e = u[(16 * h + (lane & 15)) * 32 + 4 * s + (lane >> 4)];
-        frag[i] = m == 0 ? e.x : (m == 1 ? -(e.x + e.y) : e.y - e.x);
-    }
-}
-
-// As tile_gate_mfma4: 16 groups per wavefront iteration, the next
-// iteration's amplitudes read ahead of this one's MFMAs.  The two output
-// halves are formed one after the other from the same inputs in registers.
+// The two output halves are formed one after the other from the same
+// inputs in registers.
 template <class L, int NT = kBlock>
 __device__ __forceinline__ void tile_gate_mfma5(float2 *__restrict__ sd, const float *__restrict__ frag,
                                                 const int *tab, int tb) {
     constexpr int W = NT / 64;
     constexpr int LW = ilog2(W);
     const int lane = threadIdx.x & 63, wave = wave_index();
-    const int n = lane & 15, q = lane >> 4;
     const f32x4 *fp = reinterpret_cast<const f32x4 *>(frag + lane * 48);
     f32x4 F[12];  // F[6 h + 2 m + s / 4][s % 4]
 #pragma unroll
     for (int i = 0; i < 12; ++i) F[i] = fp[i];
-    // group bits are logical bits 5.. (n its low four); input j = 4 s + q
-    // (q: bits 0..1, s: bits 2..4); output j = 16 h + 4 q + r (r: bits 0..1,
-    // q: bits 2..3, h: bit 4)
-    const int lane_part = tab_xor<4>(tab, 5, n);
-    const int lin = lane_part ^ tab_xor<2>(tab, 0, q);
-    const int lout = lane_part ^ tab_xor<2>(tab, 2, q);
-    int ain[8], aout[8];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) ain[s] = lin ^ tab_xor<3>(tab, 2, s);
+    const int base = reinterpret_cast<const int *>(frag + kFrag5)[lane];
+    int a[8];  // amplitude 16 h + 4 q + r of the lane's group at a[4 h + r]
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) aout[4 * h + r] = lout ^ tab_xor<2>(tab, 0, r) ^ (h ? tab[4] : 0);
+        for (int r = 0; r < 4; ++r) a[4 * h + r] = base ^ tab_xor<2>(tab, 0, r) ^ (h ? tab[4] : 0);
     const int iters = (1 << (tb - 5 - 4)) / W;  // batches per wave: >= 1 needs tb >= 9 + log2 W
     const int uw = tab_xor<LW>(tab, 9, wave);
     int ub = uw;
     float2 v[8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) v[s] = lds_get(sd, ain[s] ^ ub);
+    for (int s = 0; s < 8; ++s) v[s] = lds_get(sd, a[s] ^ ub);
     for (int it = 0; it < iters; ++it) {
         prio_for_remaining(iters - it);
         const int itn = it + 1 < iters ? it + 1 : it;
         const int ubn = uw ^ tab_xor<kMaxTileBits - 9 - LW>(tab, 9 + LW, itn);
         float2 w[8];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) w[s] = lds_get(sd, ain[s] ^ ubn);
+        for (int s = 0; s < 8; ++s) w[s] = lds_get(sd, a[s] ^ ubn);
         float xy[8];
 #pragma unroll
         for (int s = 0; s < 8; ++s) xy[s] = v[s].x + v[s].y;
@@ -480,58 +532,13 @@ __device__ __forceinline__ void tile_gate_mfma5(float2 *__restrict__ sd, const f
                 re = __builtin_amdgcn_mfma_f32_16x16x4f32(F[6 * h + 2 + (s >> 2)][s & 3], v[s].y, re, 0, 0, 0);
                 im = __builtin_amdgcn_mfma_f32_16x16x4f32(F[6 * h + 4 + (s >> 2)][s & 3], v[s].x, im, 0, 0, 0);
             }
+            // inputs are in registers, so this half's outputs may overwrite them in LDS
 #pragma unroll
-            for (int r = 0; r < 4; ++r) lds_put(sd, aout[4 * h + r] ^ ub, make_float2(re[r], im[r]));
+            for (int r = 0; r < 4; ++r) lds_put2(sd, a[4 * h + r] ^ ub, re[r], im[r]);
         }
         ub = ubn;
 #pragma unroll
         for (int s = 0; s < 8; ++s) v[s] = w[s];
-    }
-    __builtin_amdgcn_s_setprio(0);
-}
-
-// 16 groups per wavefront iteration; the accumulator rows 4q + r give lane
-// quarter q the amplitudes 2q (r = 0, 1) and 2q + 1 (r = 2, 3).  As for k = 4
-// the next iteration's amplitudes are read ahead of this one's MFMAs.
-template <class L, int NT = kBlock>
-__device__ __forceinline__ void tile_gate_mfma3(float2 *__restrict__ sd, const float *__restrict__ frag,
-                                                const int *tab, int tb) {
-    constexpr int W = NT / 64;
-    constexpr int LW = ilog2(W);
-    const int lane = threadIdx.x & 63, wave = wave_index();
-    const int n = lane & 15, q = lane >> 4;
-    const f32x4 afr = *reinterpret_cast<const f32x4 *>(frag + lane * 4);
-    // Offsets split into per-lane and wave-uniform parts as for k = 4 (group
-    // bits are logical bits 3..): input amplitude 2 s + (q >> 1), component
-    // q & 1 (lane quarter q needs only that float); outputs 2 q and 2 q + 1.
-    const int lane_part = tab_xor<4>(tab, 3, n);
-    const int lin = (lane_part ^ ((q >> 1) ? tab[0] : 0)) | (4 * (q & 1));
-    const int lout = lane_part ^ tab_xor<2>(tab, 1, q);
-    const int lout1 = lout ^ tab[0];
-    int ain[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) ain[s] = lin ^ tab_xor<2>(tab, 1, s);
-    const int iters = (1 << (tb - 3 - 4)) / W;  // batches per wave: >= 1 needs tb >= 7 + log2 W
-    const int uw = tab_xor<LW>(tab, 7, wave);
-    int ub = uw;
-    float v[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = lds_getf(sd, ain[s] ^ ub);
-    for (int it = 0; it < iters; ++it) {
-        prio_for_remaining(iters - it);
-        const int itn = it + 1 < iters ? it + 1 : it;
-        const int ubn = uw ^ tab_xor<kMaxTileBits - 7 - LW>(tab, 7 + LW, itn);
-        float w[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) w[s] = lds_getf(sd, ain[s] ^ ubn);
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[s], v[s], acc, 0, 0, 0);
-        lds_put(sd, lout ^ ub, make_float2(acc[0], acc[1]));
-        lds_put(sd, lout1 ^ ub, make_float2(acc[2], acc[3]));
-        ub = ubn;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) v[s] = w[s];
     }
     __builtin_amdgcn_s_setprio(0);
 }
@@ -609,12 +616,15 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
         const int k = a.g[gi].k;
         const float2 *src = a.g[gi].mat;
         float2 *dst = sm + a.g[gi].lofs;
+        int gtab[kMaxTileBits];
+#pragma unroll
+        for (int b = 0; b < kMaxTileBits; ++b) gtab[b] = a.g[gi].tab[b];
         if (k == 4) {
-            stage_frag4<NT>(reinterpret_cast<float *>(dst), src);
+            stage_frag4<NT>(reinterpret_cast<float *>(dst), src, gtab);
         } else if (k == 3) {
-            stage_frag3<NT>(reinterpret_cast<float *>(dst), src);
+            stage_frag3<NT>(reinterpret_cast<float *>(dst), src, gtab);
         } else if (k == 5) {
-            if constexpr (K5_MFMA) stage_frag5<NT>(reinterpret_cast<float *>(dst), src);
+            if constexpr (K5_MFMA) stage_frag5<NT>(reinterpret_cast<float *>(dst), src, gtab);
             else
                 for (int i = threadIdx.x; i < 1024; i += NT) dst[i] = src[i];
         }
@@ -769,12 +779,12 @@ __device__ __forceinline__ void batched_gate(float2 *__restrict__ sd, float *__r
         tile_gate_small<2, PlainTile>(sd, m, lt, tab, tb);
     } else if (g.k == 3 && tb >= 10) {
         gate_tables<3, PlainTile>(lt, tab);
-        stage_frag3(frag, m);
+        stage_frag3(frag, m, tab);
         __syncthreads();
         tile_gate_mfma3<PlainTile>(sd, frag, tab, tb);
     } else if (g.k == 4 && tb >= 10) {
         gate_tables<4, PlainTile>(lt, tab);
-        stage_frag4(frag, m);
+        stage_frag4(frag, m, tab);
         __syncthreads();
         tile_gate_mfma4<PlainTile>(sd, frag, tab, tb);
     } else {

@@ -1331,7 +1331,7 @@ struct Runner {
         sweeps.clear();
         if (T >= 10 && m.n >= qs::kTileMinQubits) {
             sweeps = qs::group_sweeps(m.n, blocks, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates,
-                                      qs::kTileMatBudget, tile_slots());
+                                      qs::tile_mat_budget(std::min(T, m.n)), tile_slots());
         } else {
             for (size_t b = 0; b < blocks.size(); ++b) {
                 qs::Sweep sw;
@@ -1423,7 +1423,8 @@ struct Runner {
         const int T = p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits;
         std::vector<qs::Sweep> sw;
         if (T >= 10 && m.n >= qs::kTileMinQubits) {
-            sw = qs::group_sweeps(m.n, rb, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates, qs::kTileMatBudget,
+            sw = qs::group_sweeps(m.n, rb, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates,
+                                  qs::tile_mat_budget(std::min(T, m.n)),
                                   tile_slots(), true);
         } else {
             for (size_t b = 0; b < rb.size(); ++b) {
@@ -2385,7 +2386,8 @@ qs_status qs_sweep_plan(const qs_circuit *c, int max_fuse, int tile_bits, int32_
     const int T = tile_bits == 0 ? qs::kDefaultTileBits : tile_bits;
     std::vector<qs::Sweep> sw;
     if (T >= 10 && m.n >= qs::kTileMinQubits) {
-        sw = qs::group_sweeps(m.n, blocks, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates, qs::kTileMatBudget,
+        sw = qs::group_sweeps(m.n, blocks, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates,
+                              qs::tile_mat_budget(std::min(T, m.n)),
                               tile_slots());
     } else {
         for (size_t b = 0; b < blocks.size(); ++b) {
