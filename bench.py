@@ -139,7 +139,7 @@ def sweep_roofline(n, ms, launches, zero_start, k_hist):
 
 
 def run_grid(qs, W, args, torch, rows=4, cols=6, p_dep=1e-3, n_traj=1000, steps=1, warmup=1,
-             streams=2, max_fuse=0, tile_bits=0, workload=None, mark=False):
+             streams=2, max_fuse=0, tile_bits=0, workload=None, mark=False, graph=True):
     """Trajectory steps of a noisy grid on `streams` concurrent states;
     returns the rate, the sweep roofline and the plan the driver used."""
     w = workload or W.grid24_workload(p_dep=p_dep, rows=rows, cols=cols)
@@ -155,7 +155,7 @@ def run_grid(qs, W, args, torch, rows=4, cols=6, p_dep=1e-3, n_traj=1000, steps=
             return qs.qs_run_trajectories(
                 handles, c, n_traj, seed=w.seed, traj_offset=offset, max_fuse=max_fuse,
                 tile_bits=tile_bits, n_samples=w.n_samples, p0to1=w.e0, p1to0=w.e1,
-                record_choices=False, time_kernels=timed, marshalled=mc)
+                record_choices=False, time_kernels=timed, graph=graph, marshalled=mc)
 
         tune_ms = 0.0
         for i in range(warmup):
@@ -166,7 +166,7 @@ def run_grid(qs, W, args, torch, rows=4, cols=6, p_dep=1e-3, n_traj=1000, steps=
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ms = 0.0
-        launches = zero = gate_sweeps = sweeps = slow = 0
+        launches = zero = gate_sweeps = sweeps = slow = replays = 0
         k_hist = [0] * 6
         used = None
         for s in range(steps):
@@ -180,6 +180,7 @@ def run_grid(qs, W, args, torch, rows=4, cols=6, p_dep=1e-3, n_traj=1000, steps=
             k_hist = [a + b for a, b in zip(k_hist, r["gate_k_launches"])]
             used = (r["max_fuse_used"], r["tile_bits_used"])
             tune_ms += r["tune_ms"]
+            replays += r["graph_replays"]
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
         if mark:
@@ -194,11 +195,12 @@ def run_grid(qs, W, args, torch, rows=4, cols=6, p_dep=1e-3, n_traj=1000, steps=
         "max_fuse": used[0], "tile_bits": used[1], "tune_ms": tune_ms,
         "gate_sweeps_per_traj": gate_sweeps / total, "sweeps_per_traj": sweeps / total,
         "slow_paths_per_traj": slow / total, "gate_width_histogram": k_hist[1:],
+        "graph_replays_per_traj": replays / total,
         "sweep": sweep_roofline(n, ms, launches, zero, k_hist),
     }
 
 
-def one_state_rate(qs, W, torch, w, n_traj, mode, max_fuse=0, tile_bits=0, warm=1):
+def one_state_rate(qs, W, torch, w, n_traj, mode, max_fuse=0, tile_bits=0, warm=1, graph=True):
     """Trajectories/s of one state on one stream (kernels untimed)."""
     c = w.circuit
     mc = qs.MarshalledCircuit(c)
@@ -207,7 +209,7 @@ def one_state_rate(qs, W, torch, w, n_traj, mode, max_fuse=0, tile_bits=0, warm=
     with qs.State(c.n, buf.data_ptr(), buf.numel() * 8, s.cuda_stream) as st:
         kw = dict(seed=w.seed, mode=mode, max_fuse=max_fuse, tile_bits=tile_bits,
                   n_samples=w.n_samples, p0to1=w.e0, p1to0=w.e1, record_choices=False,
-                  marshalled=mc)
+                  graph=graph, marshalled=mc)
         if warm:
             qs.qs_run_trajectories(st.h, c, warm, traj_offset=50_000_000, **kw)
         torch.cuda.synchronize()
@@ -217,7 +219,7 @@ def one_state_rate(qs, W, torch, w, n_traj, mode, max_fuse=0, tile_bits=0, warm=
         dt = time.perf_counter() - t0
     return {"value": n_traj / dt, "unit": "trajectories/s", "trajectories": n_traj,
             "sweeps_per_traj": r["sweeps"] / n_traj, "max_fuse": r["max_fuse_used"],
-            "tile_bits": r["tile_bits_used"]}
+            "tile_bits": r["tile_bits_used"], "graph_replays": r["graph_replays"]}
 
 
 def cpu_info():
@@ -543,6 +545,21 @@ def main() -> int:
             extras["larger_states"].append(
                 {"qubits": nq, "workload": r["workload"], "value": r["value"], "unit": r["unit"],
                  "max_fuse": r["max_fuse"], "tile_bits": r["tile_bits"], "sweep": r["sweep"]})
+        log("20-qubit grid (graph replay on and off) and 20-qubit phase damping")
+        small = {}
+        for streams in (2, 4):
+            for graph in (True, False):
+                r = run_grid(qs, W, args, torch, rows=4, cols=5, n_traj=1000, steps=1, warmup=1,
+                             streams=streams, graph=graph)
+                small[f"{streams}_streams_graph_{'on' if graph else 'off'}"] = {
+                    k: r[k] for k in ("value", "unit", "max_fuse", "tile_bits",
+                                      "graph_replays_per_traj", "slow_paths_per_traj")}
+        pd = phase_damped_circuit(4, 5, 1e-3)
+        wl = W.TrajectoryWorkload(pd.name, pd, n_traj=200, n_samples=1)
+        for graph in (True, False):
+            small[f"phase_damping_1e-3_one_state_graph_{'on' if graph else 'off'}"] = one_state_rate(
+                qs, W, torch, wl, 200, qs.QS_KRAUS_DELAYED, 0, 0, graph=graph)
+        extras["grid20"] = small
         log("grid28 (noiseless, f <= 4)")
         extras["grid28"] = sub_grid28(qs, W, torch)
         extras["grid28_autotuned"] = {k: v for k, v in sub_grid28(qs, W, torch, max_fuse=0).items()

@@ -73,6 +73,14 @@ struct qs_state_s {
     size_t arena_committed = 0;  // first float2 not yet copied
     std::vector<PendingOp> pending;
     bool poisoned = false;
+    // trajectory-driver buffers kept across calls (allocated on first use)
+    int *sel_choice_dev = nullptr;   // device-side picks [kChoiceCap] + error flag
+    int *sel_choice_host = nullptr;  // pinned mirror
+    double *sel_rdm = nullptr;       // the pending channel's reduced density matrix
+    float2 *static_buf = nullptr;    // default-plan matrices
+    size_t static_cap = 0;           // float2
+    double *chan_dev = nullptr;      // channels' excess matrices and bounds
+    size_t chan_cap = 0;             // doubles
 };
 
 namespace {
@@ -589,6 +597,11 @@ qs_status qs_destroy_state(qs_state s) {
         (void)hipHostFree(s->arena_host);
         for (int i = 0; i < 2; ++i) (void)hipEventDestroy(s->arena_ev[i]);
     }
+    if (s->sel_choice_dev) (void)hipFree(s->sel_choice_dev);
+    if (s->sel_choice_host) (void)hipHostFree(s->sel_choice_host);
+    if (s->sel_rdm) (void)hipFree(s->sel_rdm);
+    if (s->static_buf) (void)hipFree(s->static_buf);
+    if (s->chan_dev) (void)hipFree(s->chan_dev);
     delete s;
     return QS_OK;
 }
@@ -1128,7 +1141,7 @@ struct Runner {
     KernelTimer timer;
     bool timing = false;
     bool pending_reset = false;     // the state must become |0...0> before its next use
-    float2 *static_mats = nullptr;  // default-plan matrices, uploaded once per call
+    float2 *static_mats = nullptr;  // default-plan matrices (the state's buffer), uploaded once per call
     // device-side branch selection (delayed mode): per-channel excess
     // matrices and bounds, the picks written by the select kernel, an error flag
     double *chan_buf = nullptr;
@@ -1154,6 +1167,7 @@ struct Runner {
     // serves every trajectory whose channels are all picked from the bounds
     bool graph_wanted = false;
     bool graph_failed = false;
+    hipStream_t capture_st = nullptr;      // private non-blocking stream the graph is captured on
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int graph_launches = 0;
@@ -1170,19 +1184,16 @@ struct Runner {
     static constexpr int kGraphMaxQubits = 22;
 
     ~Runner() {
-        if (static_mats || chan_buf || dev_choice || gtab_dev) (void)hipStreamSynchronize(s->st);
+        if (gtab_dev) (void)hipStreamSynchronize(s->st);
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (capture_st) (void)hipStreamDestroy(capture_st);
         if (gtab_dev) (void)hipFree(gtab_dev);
         for (int h = 0; h < 2; ++h) {
             if (gtab_stage[h]) (void)hipHostFree(gtab_stage[h]);
             if (gtab_ev[h]) (void)hipEventDestroy(gtab_ev[h]);
         }
-        if (sel_rdm) (void)hipFree(sel_rdm);
-        if (static_mats) (void)hipFree(static_mats);
-        if (chan_buf) (void)hipFree(chan_buf);
-        if (dev_choice) (void)hipFree(dev_choice);
-        if (host_choice) (void)hipHostFree(host_choice);
+
     }
 
     // Channels that can need inner products: upload K^dag K - pbar I (ascending
@@ -1194,9 +1205,15 @@ struct Runner {
         size_t total = 0;
         for (const auto &c : m.channels)
             if (!c.mixture) total += c.excess_sorted.size() * 2 + c.pbar.size();
-        QS_HIP(s, hipMalloc(&dev_choice, sizeof(int) * (kChoiceCap + 1)));
-        QS_HIP(s, hipMalloc(&sel_rdm, sizeof(double) * qs::kMaxReduceWidth));
-        QS_HIP(s, hipHostMalloc(&host_choice, sizeof(int) * (kChoiceCap + 1), hipHostMallocDefault));
+        if (!s->sel_choice_dev) {
+            QS_HIP(s, hipMalloc(&s->sel_choice_dev, sizeof(int) * (kChoiceCap + 1)));
+            QS_HIP(s, hipMalloc(&s->sel_rdm, sizeof(double) * qs::kMaxReduceWidth));
+            QS_HIP(s, hipHostMalloc(&s->sel_choice_host, sizeof(int) * (kChoiceCap + 1),
+                                    hipHostMallocDefault));
+        }
+        dev_choice = s->sel_choice_dev;
+        host_choice = s->sel_choice_host;
+        sel_rdm = s->sel_rdm;
         QS_HIP(s, hipMemsetAsync(dev_choice + kChoiceCap, 0, sizeof(int), s->st));
         if (total == 0) return QS_OK;
         std::vector<double> host(total);
@@ -1212,8 +1229,17 @@ struct Runner {
             }
             for (double pb : ci.pbar) host[pos++] = pb;
         }
-        QS_HIP(s, hipMalloc(&chan_buf, sizeof(double) * total));
-        QS_HIP(s, hipMemcpy(chan_buf, host.data(), sizeof(double) * total, hipMemcpyHostToDevice));
+        if (total > s->chan_cap) {
+            if (s->chan_dev) QS_HIP(s, hipFree(s->chan_dev));
+            s->chan_dev = nullptr;
+            s->chan_cap = 0;
+            QS_HIP(s, hipMalloc(&s->chan_dev, sizeof(double) * total));
+            s->chan_cap = total;
+        }
+        chan_buf = s->chan_dev;
+        QS_HIP(s, hipMemcpyAsync(chan_buf, host.data(), sizeof(double) * total, hipMemcpyHostToDevice,
+                                 s->st));
+        QS_HIP(s, hipStreamSynchronize(s->st));  // `host` is pageable and ends with this call
         for (size_t c = 0; c < nch; ++c) {
             const auto &ci = m.channels[c];
             if (ci.mixture) continue;
@@ -1225,7 +1251,11 @@ struct Runner {
 
     // Copy the picks made on the device back into the result array.
     qs_status drain_choices() {
-        QS_HIP(s, hipMemcpyAsync(host_choice, dev_choice, sizeof(int) * (kChoiceCap + 1),
+        // the picks made so far and the error flag
+        if (!choice_owner.empty())
+            QS_HIP(s, hipMemcpyAsync(host_choice, dev_choice, sizeof(int) * choice_owner.size(),
+                                     hipMemcpyDeviceToHost, s->st));
+        QS_HIP(s, hipMemcpyAsync(host_choice + kChoiceCap, dev_choice + kChoiceCap, sizeof(int),
                                  hipMemcpyDeviceToHost, s->st));
         QS_HIP(s, hipStreamSynchronize(s->st));
         const int nch = int(m.channels.size());
@@ -1253,8 +1283,18 @@ struct Runner {
             std::memcpy(host.data() + pos, d->g.m, sizeof(float2) * dd);
             pos += dd;
         }
-        QS_HIP(s, hipMalloc(&static_mats, sizeof(float2) * total));
-        QS_HIP(s, hipMemcpy(static_mats, host.data(), sizeof(float2) * total, hipMemcpyHostToDevice));
+        if (total > s->static_cap) {
+            QS_HIP(s, hipStreamSynchronize(s->st));  // an earlier call's kernels may still read it
+            if (s->static_buf) QS_HIP(s, hipFree(s->static_buf));
+            s->static_buf = nullptr;
+            s->static_cap = 0;
+            QS_HIP(s, hipMalloc(&s->static_buf, sizeof(float2) * total));
+            s->static_cap = total;
+        }
+        static_mats = s->static_buf;
+        QS_HIP(s, hipMemcpyAsync(static_mats, host.data(), sizeof(float2) * total, hipMemcpyHostToDevice,
+                                 s->st));
+        QS_HIP(s, hipStreamSynchronize(s->st));  // `host` is pageable and ends with this call
         pos = 0;
         for (auto *d : descs) {
             if (d->identity) continue;
@@ -1655,7 +1695,7 @@ struct Runner {
     // failure leaves graph_failed set and the trajectories run directly.
     qs_status build_graph() {
         graph_failed = true;
-        if (!s->st) return QS_OK;  // the null stream cannot be captured
+        if (!s->st) return QS_OK;  // replays on the null stream are left out
         std::vector<SegSweep> seg;
         segment_sweeps(0, int(m.ops.size()), true, seg);
         std::vector<Unit> units;
@@ -1694,15 +1734,25 @@ struct Runner {
             if (qs::prepare_apply_tile(s->n, args[u]) != hipSuccess) return QS_OK;
         }
         QS_CHECK(restore_home(s));
-        if (hipStreamBeginCapture(s->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        // Captured on a private non-blocking stream, not the state's: capture
+        // runs nothing, and a caller's stream may be a blocking one, whose
+        // capture would make a synchronous copy on another thread (another
+        // state of a concurrent call) fail for depending on it.  The graph is
+        // replayed on the state's stream.
+        if (hipStreamCreateWithFlags(&capture_st, hipStreamNonBlocking) != hipSuccess) {
+            capture_st = nullptr;
+            (void)hipGetLastError();
+            return QS_OK;
+        }
+        if (hipStreamBeginCapture(capture_st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             (void)hipGetLastError();
             return QS_OK;
         }
         hipError_t e = hipSuccess;
         for (const auto &a : args)
-            if ((e = qs::launch_apply_tile(s->amp, s->n, a, s->st)) != hipSuccess) break;
+            if ((e = qs::launch_apply_tile(s->amp, s->n, a, capture_st)) != hipSuccess) break;
         hipGraph_t g = nullptr;
-        const hipError_t e_end = hipStreamEndCapture(s->st, &g);
+        const hipError_t e_end = hipStreamEndCapture(capture_st, &g);
         if (e != hipSuccess || e_end != hipSuccess || !g) {
             if (g) (void)hipGraphDestroy(g);
             (void)hipGetLastError();
@@ -2019,7 +2069,7 @@ struct Runner {
         if (res.z_expect && p.n_traj > 0)
             QS_CHECK(ensure_zrecords(s, size_t(std::min<int64_t>(p.n_traj, 4096))));
         timing = (p.flags & QS_TRAJ_TIME_KERNELS) != 0;
-        if (timing) QS_CHECK(timer.init(s, 4096));
+        if (timing) QS_CHECK(timer.init(s, 256));
         // the in-place conventional mode runs on the delayed machinery (its
         // channels carry zero bounds, so every one takes the inner-product path)
         const bool delayed = p.mode != QS_KRAUS_NAIVE;
@@ -2422,6 +2472,41 @@ namespace {
 
 constexpr int kBatchDefaultFuse = 3;
 
+// Per-circuit fusion and sweep grouping of the batched launch, cached by
+// circuit hash and fusion width (a batch of the same circuits is planned
+// once; only the per-trajectory draws and patched blocks are redone).
+struct BatchPlanKey {
+    uint64_t hash;
+    int f;
+    bool operator<(const BatchPlanKey &o) const { return std::tie(hash, f) < std::tie(o.hash, o.f); }
+};
+struct BatchPlanEntry {
+    std::vector<qs::Block> blocks;
+    std::vector<int> op_block;
+    std::vector<qs::Sweep> sweeps;
+};
+constexpr size_t kBatchPlanEntries = 2048;
+std::mutex g_bplan_mu;
+std::map<BatchPlanKey, std::shared_ptr<const BatchPlanEntry>> g_bplan_cache;
+std::deque<BatchPlanKey> g_bplan_fifo;
+
+void batch_plan_lookup(const BatchPlanKey &k, std::shared_ptr<const BatchPlanEntry> *out) {
+    std::lock_guard<std::mutex> lock(g_bplan_mu);
+    auto it = g_bplan_cache.find(k);
+    *out = it == g_bplan_cache.end() ? nullptr : it->second;
+}
+
+void batch_plan_insert(const BatchPlanKey &k, std::shared_ptr<const BatchPlanEntry> e) {
+    std::lock_guard<std::mutex> lock(g_bplan_mu);
+    if (g_bplan_cache.count(k)) return;
+    if (g_bplan_fifo.size() >= kBatchPlanEntries) {
+        g_bplan_cache.erase(g_bplan_fifo.front());
+        g_bplan_fifo.pop_front();
+    }
+    g_bplan_cache[k] = std::move(e);
+    g_bplan_fifo.push_back(k);
+}
+
 struct BatchPlanCircuit {
     CircuitModel m;
     std::vector<qs::Block> blocks;
@@ -2538,15 +2623,29 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
                 P.default_mats[o] = fast_pick_matrix(c, c.default_pick);
             }
         }
-        P.blocks = qs::fuse_greedy(n, P.m.ops, f, &P.op_block);
         std::vector<qs::Sweep> sw;
-        if (P.resident) {
-            qs::Sweep one;
-            for (size_t b = 0; b < P.blocks.size(); ++b) one.blocks.push_back(int(b));
-            sw.push_back(std::move(one));
+        const BatchPlanKey bkey{circuit_hash(I.circuit), f};
+        std::shared_ptr<const BatchPlanEntry> hit;
+        batch_plan_lookup(bkey, &hit);
+        if (hit) {
+            P.blocks = hit->blocks;
+            P.op_block = hit->op_block;
+            sw = hit->sweeps;
         } else {
-            static const int no_budget[6] = {0, 0, 0, 0, 0, 0};
-            sw = qs::group_sweeps(n, P.blocks, qs::kBatchTileBits, 6, 1 << 30, 1 << 30, no_budget);
+            P.blocks = qs::fuse_greedy(n, P.m.ops, f, &P.op_block);
+            if (P.resident) {
+                qs::Sweep one;
+                for (size_t b = 0; b < P.blocks.size(); ++b) one.blocks.push_back(int(b));
+                sw.push_back(std::move(one));
+            } else {
+                static const int no_budget[6] = {0, 0, 0, 0, 0, 0};
+                sw = qs::group_sweeps(n, P.blocks, qs::kBatchTileBits, 6, 1 << 30, 1 << 30, no_budget);
+            }
+            auto e = std::make_shared<BatchPlanEntry>();
+            e->blocks = P.blocks;
+            e->op_block = P.op_block;
+            e->sweeps = sw;
+            batch_plan_insert(bkey, std::move(e));
         }
         qs::BatchCircuit &C = circs[it];
         C.n = n;
@@ -2668,8 +2767,12 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
         for (int64_t t = 0; t < items[it].n_traj; ++t)
             refs.push_back({it, t, double(int64_t(1) << plans[it].m.n) * double(plans[it].blocks.size())});
     std::vector<BatchTrajOut> outs(refs.size());
+    // threads by the number of draws (one Philox call per channel per trajectory)
+    size_t draws = 0;
+    for (const auto &R : refs) draws += plans[R.item].m.channels.size();
     unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    nthreads = unsigned(std::min<size_t>(nthreads, std::max<size_t>(refs.size() / 64, 1)));
+    nthreads = unsigned(std::min<size_t>({size_t(nthreads), std::max<size_t>(draws / 4096, 1),
+                                          std::max<size_t>(refs.size(), 1)}));
     auto worker = [&](size_t lo, size_t hi) {
         std::vector<cd> t2(1024);
         std::vector<int> sub;

@@ -77,3 +77,23 @@ def test_graph_call_repeated_with_eager_work_between(qs):
             assert again["graph_replays"] == 8
             assert np.array_equal(again["samples"], first["samples"])
             assert np.array_equal(again["choices"], first["choices"])
+
+
+def test_graph_with_concurrent_states(qs):
+    """Four states on their own streams and host threads, each capturing and
+    replaying its own graph while the others copy matrices and samples: the
+    outputs equal the one-state run of the same range."""
+    c = W.grid_circuit(4, 4, 8, p_dep=0.01, gamma=0.0005, seed=17)
+    kw = dict(seed=8, n_samples=4, max_fuse=4, tile_bits=12, z_expect=True)
+    ref = _run(qs, c, 48, False, **kw)
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    for _ in range(2):
+        states = [qs.State(c.n, hip_stream=s.cuda_stream) for s in streams]
+        try:
+            got = qs.qs_run_trajectories([st.h for st in states], c, 48, **kw)
+        finally:
+            for st in states:
+                st.close()
+        assert got["graph_replays"] > 24
+        for key in ("samples", "choices", "paths", "n_slow", "z_expect"):
+            assert np.array_equal(got[key], ref[key]), key
