@@ -65,17 +65,21 @@ def kernel_source_digest() -> str:
     return hashlib.sha256(src.encode()).hexdigest()[:16]
 
 
-def measured_traffic(path=COUNTER_SUMMARY):
+def measured_traffic(tile_bits, path=COUNTER_SUMMARY):
     """HBM bytes per sweep launch from a committed counter summary, only if
-    it was taken on the kernel source that is built now (else None)."""
+    it was taken on the kernel source that is built now and on the tile
+    width the run used (else None)."""
     try:
         digest = kernel_source_digest()
         text = open(path).read()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines()
-                  if line.startswith(("kernel_source_sha256_prefix:", "traffic_bytes_per_launch:")))
+                  if line.startswith(("kernel_source_sha256_prefix:", "traffic_bytes_per_launch:",
+                                      "tile_bits:")))
     if fields.get("kernel_source_sha256_prefix", "").strip() != digest:
+        return None
+    if fields.get("tile_bits", "").strip() != str(tile_bits):
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
@@ -487,13 +491,18 @@ def main() -> int:
         f"sweep {head['sweep']['avg_launch_us']:.2f} us")
     n = head["qubits"]
     sw = head["sweep"]
-    traffic = measured_traffic() if (args.rows, args.cols) == (4, 6) else None
+    traffic = measured_traffic(head["tile_bits"]) if (args.rows, args.cols) == (4, 6) else None
     roofline = {
         "bound": "hbm",
         "achieved": sw["hbm"]["achieved"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
         "frac": sw["hbm"]["frac"],
         "traffic": (traffic / 1e9) if traffic else None,
-        "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-calibrated)",
+        "traffic_unit": ("GB per launch: rocprofv3 TCC_EA0 read and write request counters x "
+                         "request size, profiles/apply_tile_grid24_counters.md (null unless that "
+                         "summary matches the built kernel source and the run's tile width)"),
+        "counter_summaries": ["profiles/apply_tile_grid24_counters.md",
+                              "profiles/apply_tile_grid24_pmc.md",
+                              "profiles/apply_tile_grid28_counters.md"],
         "kernel": "fused-gate sweep apply_tile: one read and one write of the state, the sweep's "
                   "fused blocks applied in LDS",
         "avg_launch_us": sw["avg_launch_us"],

@@ -129,6 +129,39 @@ struct BatchPatch {
     int mat;                 // float2 offset of the trajectory's matrix
 };
 
+// Per-trajectory channel draws of a batched launch on the device (Algorithm
+// 2's fast path for mixtures of unitaries: every pick is decided by r against
+// the running sums of the fixed probabilities).  Picks other than a channel's
+// most likely one are appended to a list as (job, channel, pick) for the host
+// to build the job's patched blocks from.
+struct BatchDrawChannel {
+    int32_t nk;              // Kraus operators
+    int32_t default_pick;    // the pick the default plan folds in
+    int32_t pbar;            // offset of the nk probabilities in the pbar pool
+    int32_t pad;
+};
+
+struct BatchDrawJob {
+    int32_t ch0, nch;        // channel range in the channel table
+    uint32_t traj;           // Philox counter word 1
+    uint32_t circ_id;        // Philox counter word 2
+    uint64_t seed;           // Philox key
+    int64_t choices;         // offset of the job's nch recorded picks, or -1
+};
+
+struct BatchDrawArgs {
+    const BatchDrawChannel *chan;
+    const double *pbar;
+    const BatchDrawJob *jobs;
+    int n_jobs;
+    int over_cap;            // entries the list holds
+    int8_t *choices;         // recorded picks (may be null when no job records)
+    int32_t *count;          // entries appended (may exceed over_cap)
+    int32_t *over;           // 3 x over_cap: job, channel, pick
+};
+
+hipError_t launch_batch_draws(const BatchDrawArgs &a, hipStream_t st);
+
 struct BatchArgs {
     const BatchCircuit *circs;
     const BatchSweep *sweeps;

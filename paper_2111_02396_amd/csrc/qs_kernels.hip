@@ -1119,24 +1119,50 @@ __global__ __launch_bounds__(kBlock) void reduce_records(const double *__restric
 
 // ---------------------------------------------------------------- sampling
 
-// One workgroup per sampling block of 2^B amplitudes.
+// Per-lane sum of |amp|^2 over `per` consecutive amplitudes starting at
+// `first`, in index order (pairs loaded as one 16-byte access).
 template <typename Idx>
-__global__ __launch_bounds__(kBlock) void sample_block_sums(const float2 *__restrict__ amp, int B,
-                                                            double *__restrict__ sums) {
-    const Idx first = Idx(blockIdx.x) << B;
-    const int len = 1 << B;
-    double acc[1] = {0.0};
-    for (int i = threadIdx.x; i < len; i += kBlock) {
-        const float2 v = amp[first + Idx(i)];
-        acc[0] = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), acc[0]));
+__device__ __forceinline__ double chunk_weight(const float2 *__restrict__ amp, Idx first, int per) {
+    double acc = 0.0;
+    if (per >= 2) {
+        const float4 *p4 = reinterpret_cast<const float4 *>(amp + first);
+        for (int i = 0; i < per / 2; ++i) {
+            const float4 v = p4[i];
+            acc = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), acc));
+            acc = fma(double(v.z), double(v.z), fma(double(v.w), double(v.w), acc));
+        }
+    } else {
+        const float2 v = amp[first];
+        acc = fma(double(v.x), double(v.x), double(v.y) * double(v.y));
     }
-    block_sum_write<1>(acc, sums + blockIdx.x);
+    return acc;
 }
 
-// Inclusive prefix over nb block sums: each thread scans a contiguous chunk
-// sequentially; chunk totals are scanned per wavefront with a fixed shuffle
-// ladder, then across the 16 wavefronts in order.  Writes the total to *norm.
+// One wavefront per sampling block of 2^B amplitudes (kBlock / 64 blocks per
+// workgroup): each lane sums a contiguous run of 2^B / 64 amplitudes, then a
+// fixed shuffle tree adds the runs.
+template <typename Idx>
+__global__ __launch_bounds__(kBlock) void sample_block_sums(const float2 *__restrict__ amp, int B,
+                                                            int64_t nb, double *__restrict__ sums) {
+    const int64_t blk = int64_t(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (blk >= nb) return;  // uniform over the wavefront
+    const int len = 1 << B;
+    const int per = len >= 64 ? len / 64 : 1;
+    double x = lane < len ? chunk_weight(amp, (Idx(blk) << B) + Idx(lane * per), per) : 0.0;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) sums[blk] = x;
+}
+
+// Inclusive prefix of the block sums in index order, in three fixed-order
+// steps: every tile of kScanThreads * kScanPer sums is scanned by its own
+// workgroup; one workgroup scans the tile totals into exclusive tile offsets
+// (written over the block sums, which are no longer needed) and the total;
+// the offsets are added to the tiles after the first.
 constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanThreads * kScanPer;
 __device__ __forceinline__ double wave_inclusive_scan(double x) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -1147,69 +1173,107 @@ __device__ __forceinline__ double wave_inclusive_scan(double x) {
     return x;
 }
 
-// Inclusive prefix of the block sums in index order, tile by tile: a tile
-// of kScanThreads * kScanPer sums is loaded coalesced into LDS (one pad slot
-// per kScanPer, so that each work-item's run of kScanPer consecutive sums
-// sits on distinct banks), each work-item adds its run, one workgroup scan
-// of the run totals (wavefronts in order) gives every run's offset, the runs'
-// prefixes go back to LDS and out coalesced, and the tile total carries into
-// the next tile.  Fixed order throughout.
-constexpr int kScanPer = 8;
-__device__ __forceinline__ int scan_slot(int i) { return i + i / kScanPer; }
-
-__global__ __launch_bounds__(kScanThreads) void sample_scan(const double *__restrict__ sums,
-                                                            int64_t nb, double *__restrict__ incl,
-                                                            double *__restrict__ norm) {
-    constexpr int kTile = kScanThreads * kScanPer;
-    __shared__ double tile[kTile + kTile / kScanPer];
-    __shared__ double wave_tot[kScanThreads / 64];
-    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    double carry = 0.0;
-    for (int64_t base = 0; base < nb; base += kTile) {
-        const int len = nb - base < kTile ? int(nb - base) : kTile;
-#pragma unroll
-        for (int j = 0; j < kScanPer; ++j) {
-            const int i = j * kScanThreads + t;
-            tile[scan_slot(i)] = i < len ? sums[base + i] : 0.0;
-        }
-        __syncthreads();
-        double v[kScanPer], tot = 0.0;
-#pragma unroll
-        for (int j = 0; j < kScanPer; ++j) {
-            v[j] = tile[scan_slot(t * kScanPer + j)];
-            tot += v[j];
-        }
-        const double inc = wave_inclusive_scan(tot);
-        if (lane == 63) wave_tot[wave] = inc;
-        __syncthreads();
-        double before = 0.0, all = 0.0;
-        for (int w = 0; w < kScanThreads / 64; ++w) {
-            if (w < wave) before += wave_tot[w];
-            all += wave_tot[w];
-        }
-        double run = carry + before + (inc - tot);
-#pragma unroll
-        for (int j = 0; j < kScanPer; ++j) {
-            run += v[j];
-            tile[scan_slot(t * kScanPer + j)] = run;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kScanPer; ++j) {
-            const int i = j * kScanThreads + t;
-            if (i < len) incl[base + i] = tile[scan_slot(i)];
-        }
-        carry += all;
-        __syncthreads();  // the tile and wave totals are reused
+// Exclusive prefix over the workgroup's kScanThreads values in thread order
+// (wavefront scans, then the wavefront totals in order); *all gets the total.
+__device__ __forceinline__ double workgroup_exclusive_scan(double x, double *wave_tot, double *all) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double inc = wave_inclusive_scan(x);
+    if (lane == 63) wave_tot[wave] = inc;
+    __syncthreads();
+    double before = 0.0, sum = 0.0;
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        if (w < wave) before += wave_tot[w];
+        sum += wave_tot[w];
     }
-    if (t == 0) *norm = carry;
+    *all = sum;
+    return before + (inc - x);
 }
 
-// One wavefront per sample: find the block by binary search over the block
+// A tile is loaded coalesced into LDS (one pad slot per kScanPer, so each
+// work-item's run of kScanPer consecutive sums sits on distinct banks), each
+// work-item adds its run, the runs' offsets come from one workgroup scan,
+// and the runs' prefixes go back through LDS and out coalesced.
+__device__ __forceinline__ int scan_slot(int i) { return i + i / kScanPer; }
+
+__global__ __launch_bounds__(kScanThreads) void sample_scan_tiles(const double *__restrict__ sums,
+                                                                  int64_t nb, double *__restrict__ incl) {
+    __shared__ double tile[kScanTile + kScanTile / kScanPer];
+    __shared__ double wave_tot[kScanThreads / 64];
+    const int t = threadIdx.x;
+    const int64_t base = int64_t(blockIdx.x) * kScanTile;
+    const int len = nb - base < kScanTile ? int(nb - base) : kScanTile;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        const int i = j * kScanThreads + t;
+        tile[scan_slot(i)] = i < len ? sums[base + i] : 0.0;
+    }
+    __syncthreads();
+    double v[kScanPer], tot = 0.0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        v[j] = tile[scan_slot(t * kScanPer + j)];
+        tot += v[j];
+    }
+    double all;
+    double run = workgroup_exclusive_scan(tot, wave_tot, &all);
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        run += v[j];
+        tile[scan_slot(t * kScanPer + j)] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+        const int i = j * kScanThreads + t;
+        if (i < len) incl[base + i] = tile[scan_slot(i)];
+    }
+}
+
+// Tile totals (each tile's last prefix) added one after another: offsets[t]
+// is the running sum before tile t, so that a tile's last prefix plus its
+// offset equals the next offset exactly and the prefix stays non-decreasing
+// across tiles.  *norm is the final sum.
+constexpr int kScanMaxTiles = 2048;  // 2^(kMaxQubits - kSampleBlockBits) / kScanTile
+__global__ __launch_bounds__(kScanThreads) void sample_scan_offsets(const double *__restrict__ incl,
+                                                                    int64_t nb, int n_tiles,
+                                                                    double *__restrict__ offsets,
+                                                                    double *__restrict__ norm) {
+    __shared__ double tot[kScanMaxTiles];
+    for (int t = threadIdx.x; t < n_tiles; t += kScanThreads) {
+        const int64_t end = int64_t(t + 1) * kScanTile;
+        tot[t] = incl[(end < nb ? end : nb) - 1];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double run = 0.0;
+        for (int t0 = 0; t0 < n_tiles; t0 += 16) {
+            double v[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) v[j] = t0 + j < n_tiles ? tot[t0 + j] : 0.0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (t0 + j < n_tiles) {
+                    offsets[t0 + j] = run;
+                    run += v[j];
+                }
+        }
+        *norm = run;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void sample_scan_add(double *__restrict__ incl, int64_t nb,
+                                                          const double *__restrict__ offsets) {
+    const int64_t i = int64_t(kScanTile) + int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < nb) incl[i] += offsets[i / kScanTile];
+}
+
+// One wavefront per sample: find the block by a 64-way search over the block
 // prefix, then the lanes sum 2^B/64 consecutive amplitudes each, scan those
 // partial sums in a fixed order, and the first lane whose running sum passes
-// the target rescans its own amplitudes sequentially.
-template <typename Idx>
+// the target walks its own amplitudes.  PER > 0: blocks of 64 * PER
+// amplitudes, each lane's run kept in registers for the walk; PER = 0: any
+// block size, the walk reloads.
+template <typename Idx, int PER>
 __global__ __launch_bounds__(kBlock) void sample_draw(const float2 *__restrict__ amp, int n, int B,
                                                       const double *__restrict__ incl, int64_t nb,
                                                       const double *__restrict__ norm,
@@ -1221,9 +1285,9 @@ __global__ __launch_bounds__(kBlock) void sample_draw(const float2 *__restrict__
     if (s >= n_samples) return;  // uniform over the wavefront
     const double N = *norm;
     const double target = philox_uniform(seed, uint32_t(s), traj, circ, kStreamMeasure) * N;
-    // smallest block b with target < incl[b] (nb if none): 64-way search, the
-    // lanes probe evenly spaced entries and a ballot keeps the first passing
-    // interval.  Invariant: the answer lies in [lo, hi], and hi passes or is nb.
+    // smallest block b with target < incl[b] (nb if none): the lanes probe
+    // evenly spaced entries and a ballot keeps the first passing interval.
+    // Invariant: the answer lies in [lo, hi], and hi passes or is nb.
     int64_t lo = 0, hi = nb;
     while (lo < hi) {
         const int64_t span = hi - lo;
@@ -1253,28 +1317,61 @@ __global__ __launch_bounds__(kBlock) void sample_draw(const float2 *__restrict__
         const double base = lo > 0 ? incl[lo - 1] : 0.0;
         const Idx first = Idx(lo) << B;
         const int len = 1 << B;
-        const int per = len >= 64 ? len / 64 : 1;
+        const int per = PER > 0 ? PER : (len >= 64 ? len / 64 : 1);
         const int lanes = len >= 64 ? 64 : len;
         double part = 0.0;
-        if (lane < lanes)
-            for (int i = 0; i < per; ++i) {
-                const float2 v = amp[first + Idx(lane * per + i)];
-                part += fma(double(v.x), double(v.x), double(v.y) * double(v.y));
+        float4 keep[PER > 0 ? PER / 2 : 1];
+        if constexpr (PER > 0) {
+            const float4 *p4 = reinterpret_cast<const float4 *>(amp + first + Idx(lane * PER));
+#pragma unroll
+            for (int i = 0; i < PER / 2; ++i) keep[i] = p4[i];
+#pragma unroll
+            for (int i = 0; i < PER / 2; ++i) {
+                part = fma(double(keep[i].x), double(keep[i].x), fma(double(keep[i].y), double(keep[i].y), part));
+                part = fma(double(keep[i].z), double(keep[i].z), fma(double(keep[i].w), double(keep[i].w), part));
             }
+        } else if (lane < lanes) {
+            part = chunk_weight(amp, first + Idx(lane * per), per);
+        }
         const double inc = base + wave_inclusive_scan(part);
         const uint64_t passed = __ballot(lane < lanes && target < inc);
         int pick = len - 1;
         if (passed) {
             const int L = __ffsll((unsigned long long)passed) - 1;
-            // lane L rescans its amplitudes from its exclusive prefix
-            const double start = __shfl(inc - part, L, 64);
+            // lane L walks its amplitudes from its exclusive prefix, adding
+            // them as chunk_weight does
             int idx = L * per + per - 1;
             if (lane == L) {
-                double run = start;
-                for (int i = 0; i < per; ++i) {
-                    const float2 v = amp[first + Idx(L * per + i)];
-                    run += fma(double(v.x), double(v.x), double(v.y) * double(v.y));
-                    if (target < run) { idx = L * per + i; break; }
+                double run = inc - part;
+                if constexpr (PER > 0) {
+                    bool found = false;
+#pragma unroll
+                    for (int i = 0; i < PER / 2; ++i) {
+                        const double r0 = fma(double(keep[i].x), double(keep[i].x),
+                                              fma(double(keep[i].y), double(keep[i].y), run));
+                        const double r1 = fma(double(keep[i].z), double(keep[i].z),
+                                              fma(double(keep[i].w), double(keep[i].w), r0));
+                        if (!found && target < r0) {
+                            idx = L * PER + 2 * i;
+                            found = true;
+                        } else if (!found && target < r1) {
+                            idx = L * PER + 2 * i + 1;
+                            found = true;
+                        }
+                        run = r1;
+                    }
+                } else if (per >= 2) {
+                    const float4 *p4 = reinterpret_cast<const float4 *>(amp + first + Idx(L * per));
+                    for (int i = 0; i < per / 2; ++i) {
+                        const float4 v = p4[i];
+                        const double r0 = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), run));
+                        if (target < r0) { idx = L * per + 2 * i; break; }
+                        const double r1 = fma(double(v.z), double(v.z), fma(double(v.w), double(v.w), r0));
+                        if (target < r1) { idx = L * per + 2 * i + 1; break; }
+                        run = r1;
+                    }
+                } else {
+                    idx = L;
                 }
             }
             pick = __shfl(idx, L, 64);
@@ -1407,6 +1504,40 @@ hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st,
     }
 }
 
+// Channel draws of a batched launch: one workgroup per job at a time, its
+// work-items over the job's channels.  Picks follow the same rule and the
+// same FP64 arithmetic as the host planner.
+__global__ void __launch_bounds__(256) batch_draws(BatchDrawArgs a) {
+    for (int j = blockIdx.x; j < a.n_jobs; j += gridDim.x) {
+        const BatchDrawJob J = a.jobs[j];
+        for (int c = threadIdx.x; c < J.nch; c += blockDim.x) {
+            const BatchDrawChannel ch = a.chan[J.ch0 + c];
+            double r = philox_uniform(J.seed, uint32_t(c), J.traj, J.circ_id, kStreamChannel);
+            const double *pb = a.pbar + ch.pbar;
+            int pick = -1;
+            for (int i = 0; i < ch.nk; ++i) {
+                if (r < pb[i]) {
+                    pick = i;
+                    break;
+                }
+                r -= pb[i];
+            }
+            if (pick < 0)  // rounding left r above the total: the last operator with weight
+                for (int i = ch.nk - 1; i >= 0 && pick < 0; --i)
+                    if (pb[i] > 0.0) pick = i;
+            if (J.choices >= 0) a.choices[J.choices + c] = int8_t(pick);
+            if (pick != ch.default_pick) {
+                const int slot = atomicAdd(a.count, 1);
+                if (slot < a.over_cap) {
+                    a.over[3 * slot] = j;
+                    a.over[3 * slot + 1] = c;
+                    a.over[3 * slot + 2] = pick;
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t launch_select(const SelectArgs &a, hipStream_t st) {
@@ -1429,6 +1560,13 @@ hipError_t launch_batched(const BatchArgs &a, int grid, hipStream_t st) {
     if (attr != hipSuccess) return attr;
     if (grid < 1) return hipErrorInvalidValue;
     run_batched<<<unsigned(grid), kBlock, lds, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_draws(const BatchDrawArgs &a, hipStream_t st) {
+    if (a.n_jobs < 1) return hipSuccess;
+    const unsigned grid = unsigned(a.n_jobs < 4096 ? a.n_jobs : 4096);
+    batch_draws<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -1649,19 +1787,29 @@ hipError_t launch_sample(const float2 *amp, int n, double *sums, double *incl, u
                          uint64_t *out_dev, double *norm_dev, hipStream_t st) {
     const int B = n < kSampleBlockBits ? n : kSampleBlockBits;
     const int64_t nb = int64_t(1) << (n - B);
+    const int64_t n_tiles = (nb + kScanTile - 1) / kScanTile;
+    if (n_tiles > kScanMaxTiles) return hipErrorInvalidValue;
+    const unsigned sum_grid = unsigned((nb + kBlock / 64 - 1) / (kBlock / 64));
     if (n <= 31)
-        sample_block_sums<uint32_t><<<unsigned(nb), kBlock, 0, st>>>(amp, B, sums);
+        sample_block_sums<uint32_t><<<sum_grid, kBlock, 0, st>>>(amp, B, nb, sums);
     else
-        sample_block_sums<uint64_t><<<unsigned(nb), kBlock, 0, st>>>(amp, B, sums);
-    sample_scan<<<1, kScanThreads, 0, st>>>(sums, nb, incl, norm_dev);
+        sample_block_sums<uint64_t><<<sum_grid, kBlock, 0, st>>>(amp, B, nb, sums);
+    sample_scan_tiles<<<unsigned(n_tiles), kScanThreads, 0, st>>>(sums, nb, incl);
+    // the block sums have been read: their first n_tiles slots take the offsets
+    sample_scan_offsets<<<1, kScanThreads, 0, st>>>(incl, nb, int(n_tiles), sums, norm_dev);
+    if (n_tiles > 1)
+        sample_scan_add<<<unsigned((nb - kScanTile + kBlock - 1) / kBlock), kBlock, 0, st>>>(incl, nb, sums);
     if (n_samples > 0) {
         const unsigned grid = unsigned((n_samples + kBlock / 64 - 1) / (kBlock / 64));
-        if (n <= 31)
-            sample_draw<uint32_t><<<grid, kBlock, 0, st>>>(amp, n, B, incl, nb, norm_dev, seed, traj,
-                                                           circ, n_samples, ro, out_dev);
+        if (B == 10 && n <= 31)
+            sample_draw<uint32_t, 16><<<grid, kBlock, 0, st>>>(amp, n, B, incl, nb, norm_dev, seed, traj,
+                                                               circ, n_samples, ro, out_dev);
+        else if (B == 10)
+            sample_draw<uint64_t, 16><<<grid, kBlock, 0, st>>>(amp, n, B, incl, nb, norm_dev, seed, traj,
+                                                               circ, n_samples, ro, out_dev);
         else
-            sample_draw<uint64_t><<<grid, kBlock, 0, st>>>(amp, n, B, incl, nb, norm_dev, seed, traj,
-                                                           circ, n_samples, ro, out_dev);
+            sample_draw<uint32_t, 0><<<grid, kBlock, 0, st>>>(amp, n, B, incl, nb, norm_dev, seed, traj,
+                                                              circ, n_samples, ro, out_dev);
     }
     return hipGetLastError();
 }

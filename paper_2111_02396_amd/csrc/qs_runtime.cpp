@@ -7,6 +7,9 @@
 #include <cmath>
 #include <cstring>
 #include <array>
+#include <atomic>
+#include <condition_variable>
+#include <functional>
 #include <deque>
 #include <map>
 #include <memory>
@@ -79,6 +82,7 @@ struct qs_state_s {
     double *sel_rdm = nullptr;       // the pending channel's reduced density matrix
     float2 *static_buf = nullptr;    // default-plan matrices
     size_t static_cap = 0;           // float2
+    uint64_t static_tag = 0;         // cached plan whose matrices static_buf holds (0: none)
     double *chan_dev = nullptr;      // channels' excess matrices and bounds
     size_t chan_cap = 0;             // doubles
 };
@@ -537,8 +541,6 @@ qs_status qs_create_state(int n_qubits, void *device_buf, size_t buf_bytes, void
     if (n_qubits < 1 || n_qubits > qs::kMaxQubits) return fail(QS_ERR_INVALID_ARGUMENT, "n out of range");
     const size_t bytes = sizeof(float2) << n_qubits;
     if (device_buf && buf_bytes < bytes) return fail(QS_ERR_INVALID_ARGUMENT, "buffer smaller than 8*2^n bytes");
-    if (device_buf && (reinterpret_cast<uintptr_t>(device_buf) & 15u) != 0)
-        return fail(QS_ERR_INVALID_ARGUMENT, "buffer not 16-byte aligned");
     if (device_buf && (reinterpret_cast<uintptr_t>(device_buf) & 15u) != 0)
         return fail(QS_ERR_INVALID_ARGUMENT, "buffer not 16-byte aligned");
     auto *s = new qs_state_s();
@@ -1044,9 +1046,9 @@ struct KernelTimer {
 // sweep grouping) depends only on the circuit, the mode's channel bounds and
 // the widths, so calls that run the same circuit again (one state per call,
 // a serving loop, the autotuner's final choice) reuse it instead of fusing
-// again.  Keyed by a hash of the circuit's ops and matrix pool.
+// again.  Keyed by the circuit's model-cache id.
 struct PlanKey {
-    uint64_t hash;
+    uint64_t hash;  // model id
     int n, mode, f, tb;
     bool operator<(const PlanKey &o) const {
         return std::tie(hash, n, mode, f, tb) < std::tie(o.hash, o.n, o.mode, o.f, o.tb);
@@ -1082,20 +1084,101 @@ void plan_insert(const PlanKey &k, std::shared_ptr<const PlanEntry> e) {
     g_plan_fifo.push_back(k);
 }
 
-// FNV-1a over the circuit's qubit count, op records and matrix pool.
+// Hash of the circuit's qubit count, op records and matrix pool, eight bytes
+// at a time (a cache key only: the model cache below compares the bytes).
 uint64_t circuit_hash(const qs_circuit *c) {
-    uint64_t h = 1469598103934665603ull;
+    uint64_t h = 0x9e3779b97f4a7c15ull ^ uint64_t(uint32_t(c->n_qubits));
     auto mix = [&h](const void *p, size_t len) {
         const unsigned char *b = static_cast<const unsigned char *>(p);
-        for (size_t i = 0; i < len; ++i) {
-            h ^= b[i];
-            h *= 1099511628211ull;
+        size_t i = 0;
+        for (; i + 8 <= len; i += 8) {
+            uint64_t w;
+            std::memcpy(&w, b + i, 8);
+            h = (h ^ w) * 0xff51afd7ed558ccdull;
+            h ^= h >> 32;
         }
+        for (; i < len; ++i) h = (h ^ b[i]) * 0x100000001b3ull;
+        h ^= uint64_t(len);
     };
-    mix(&c->n_qubits, sizeof(c->n_qubits));
-    mix(c->ops, sizeof(qs_op) * size_t(c->n_ops));
-    mix(c->mat_pool, sizeof(double) * 2 * size_t(c->pool_len));
+    if (c->ops) mix(c->ops, sizeof(qs_op) * size_t(std::max(c->n_ops, 0)));
+    if (c->mat_pool) mix(c->mat_pool, sizeof(double) * 2 * size_t(std::max<int64_t>(c->pool_len, 0)));
     return h;
+}
+
+// ---- circuit model cache
+// A circuit's model (its ops, channel bounds and fast-path matrices) depends
+// only on the circuit's bytes, so calls that run the same circuit again reuse
+// it.  An entry keeps its own copy of the op records and the matrix pool (the
+// model points into that copy, not into the caller's buffers) and is found by
+// hash and then compared in full, so two circuits never share an entry.
+// Each entry has a unique id; the plan and width caches are keyed by it.
+struct ModelEntry {
+    uint64_t id = 0;
+    uint64_t hash = 0;
+    int n = 0;
+    std::vector<qs_op> ops;
+    std::vector<double> pool;
+    CircuitModel model;
+};
+
+constexpr size_t kModelCacheEntries = 64;
+std::mutex g_model_mu;
+std::multimap<uint64_t, std::shared_ptr<const ModelEntry>> g_model_cache;
+std::deque<std::shared_ptr<const ModelEntry>> g_model_fifo;
+uint64_t g_model_next_id = 1;
+
+bool same_circuit(const ModelEntry &e, const qs_circuit *c) {
+    const size_t nops = size_t(c->n_ops), npool = size_t(c->pool_len) * 2;
+    return e.n == c->n_qubits && e.ops.size() == nops && e.pool.size() == npool &&
+           (nops == 0 || std::memcmp(e.ops.data(), c->ops, sizeof(qs_op) * nops) == 0) &&
+           (npool == 0 || std::memcmp(e.pool.data(), c->mat_pool, sizeof(double) * npool) == 0);
+}
+
+// The model of circuit c, built (and validated) on its first use.
+qs_status circuit_model(const qs_circuit *c, std::shared_ptr<const ModelEntry> *out) {
+    if (!c || !c->ops || c->n_ops < 0 || !c->mat_pool || c->pool_len < 0)
+        return fail(QS_ERR_INVALID_ARGUMENT, "bad circuit");
+    const uint64_t h = circuit_hash(c);
+    {
+        std::lock_guard<std::mutex> lock(g_model_mu);
+        auto range = g_model_cache.equal_range(h);
+        for (auto it = range.first; it != range.second; ++it)
+            if (same_circuit(*it->second, c)) {
+                *out = it->second;
+                return QS_OK;
+            }
+    }
+    auto e = std::make_shared<ModelEntry>();
+    e->hash = h;
+    e->n = c->n_qubits;
+    e->ops.assign(c->ops, c->ops + c->n_ops);
+    e->pool.assign(c->mat_pool, c->mat_pool + size_t(c->pool_len) * 2);
+    qs_circuit own = *c;  // the model points into the entry's copies (an empty one holds no pointer)
+    if (!e->ops.empty()) own.ops = e->ops.data();
+    if (!e->pool.empty()) own.mat_pool = e->pool.data();
+    QS_CHECK(build_model(&own, e->model));
+    std::lock_guard<std::mutex> lock(g_model_mu);
+    auto range = g_model_cache.equal_range(h);  // another thread may have built it meanwhile
+    for (auto it = range.first; it != range.second; ++it)
+        if (same_circuit(*it->second, c)) {
+            *out = it->second;
+            return QS_OK;
+        }
+    e->id = g_model_next_id++;
+    if (g_model_fifo.size() >= kModelCacheEntries) {
+        const auto &old = g_model_fifo.front();
+        auto r = g_model_cache.equal_range(old->hash);
+        for (auto it = r.first; it != r.second; ++it)
+            if (it->second == old) {
+                g_model_cache.erase(it);
+                break;
+            }
+        g_model_fifo.pop_front();
+    }
+    g_model_cache.emplace(h, e);
+    g_model_fifo.push_back(e);
+    *out = std::move(e);
+    return QS_OK;
 }
 
 struct Runner {
@@ -1104,7 +1187,7 @@ struct Runner {
     const qs_traj_params &p;
     qs_traj_result &res;
     int max_fuse;
-    uint64_t chash = 0;   // circuit_hash of the call's circuit (0: do not cache the plan)
+    uint64_t chash = 0;   // model id of the call's circuit (0: do not cache the plan)
     bool tuning = false;  // an autotuner trial: default plan only, no channel uploads
     // delayed mode: default plan
     std::vector<const cd *> default_mats;
@@ -1175,9 +1258,10 @@ struct Runner {
     float2 *gtab_dev = nullptr;            // the slots
     std::vector<size_t> gtab_off;          // per block: float2 offset, or kNoSlot (identity)
     std::vector<float2> gtab_host;         // the slots' current contents
-    float2 *gtab_stage[2] = {nullptr, nullptr};  // pinned staging halves
-    hipEvent_t gtab_ev[2] = {nullptr, nullptr};
-    bool gtab_live[2] = {false, false};
+    static constexpr int kStages = 4;  // pinned staging copies in flight
+    float2 *gtab_stage[kStages] = {};
+    hipEvent_t gtab_ev[kStages] = {};
+    bool gtab_live[kStages] = {};
     int gtab_half = 0;
     std::vector<char> gdirty_prev;         // blocks the previous replay patched
     static constexpr size_t kNoSlot = ~size_t(0);
@@ -1189,7 +1273,7 @@ struct Runner {
         if (graph) (void)hipGraphDestroy(graph);
         if (capture_st) (void)hipStreamDestroy(capture_st);
         if (gtab_dev) (void)hipFree(gtab_dev);
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < kStages; ++h) {
             if (gtab_stage[h]) (void)hipHostFree(gtab_stage[h]);
             if (gtab_ev[h]) (void)hipEventDestroy(gtab_ev[h]);
         }
@@ -1270,11 +1354,24 @@ struct Runner {
     }
 
     // Upload the matrices of `descs` to one device buffer and point at it.
-    qs_status upload_static(std::vector<BlockDesc *> &descs) {
+    // Uploads the matrices of `descs` to the state's static buffer, unless
+    // it already holds those of the cached plan `tag` (0: always upload).
+    qs_status upload_static(std::vector<BlockDesc *> &descs, uint64_t tag = 0) {
         size_t total = 0;
         for (auto *d : descs)
             if (!d->identity) total += size_t(1) << (2 * d->g.k);
         if (total == 0) return QS_OK;
+        if (tag != 0 && tag == s->static_tag && total <= s->static_cap) {
+            static_mats = s->static_buf;
+            size_t pos = 0;
+            for (auto *d : descs) {
+                if (d->identity) continue;
+                d->dev = static_mats + pos;
+                pos += size_t(1) << (2 * d->g.k);
+            }
+            return QS_OK;
+        }
+        s->static_tag = 0;
         std::vector<float2> host(total);
         size_t pos = 0;
         for (auto *d : descs) {
@@ -1295,6 +1392,7 @@ struct Runner {
         QS_HIP(s, hipMemcpyAsync(static_mats, host.data(), sizeof(float2) * total, hipMemcpyHostToDevice,
                                  s->st));
         QS_HIP(s, hipStreamSynchronize(s->st));  // `host` is pageable and ends with this call
+        s->static_tag = tag;
         pos = 0;
         for (auto *d : descs) {
             if (d->identity) continue;
@@ -1363,7 +1461,12 @@ struct Runner {
         std::vector<BlockDesc *> all;
         for (auto &d : block_desc) all.push_back(&d);
         if (!tuning) QS_CHECK(upload_channels());
-        return upload_static(all);
+        // a plan from the cache is fixed by its key: the state keeps its
+        // matrices from one call to the next
+        const uint64_t tag = chash ? (chash << 16) | (uint64_t(p.mode & 3) << 12) |
+                                         (uint64_t(max_fuse) << 8) | uint64_t(key.tb)
+                                   : 0;
+        return upload_static(all, tag);
     }
 
     void plan_sweeps() {
@@ -1723,7 +1826,7 @@ struct Runner {
         QS_HIP(s, hipMemcpyAsync(gtab_dev, gtab_host.data(), sizeof(float2) * total,
                                  hipMemcpyHostToDevice, s->st));
         QS_HIP(s, hipStreamSynchronize(s->st));
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < kStages; ++h) {
             QS_HIP(s, hipHostMalloc(&gtab_stage[h], sizeof(float2) * total, hipHostMallocDefault));
             QS_HIP(s, hipEventCreateWithFlags(&gtab_ev[h], hipEventDisableTiming));
         }
@@ -1836,7 +1939,7 @@ struct Runner {
                                      hipMemcpyHostToDevice, s->st));
             QS_HIP(s, hipEventRecord(gtab_ev[h], s->st));
             gtab_live[h] = true;
-            gtab_half ^= 1;
+            gtab_half = (gtab_half + 1) % kStages;
         }
         if (timing) QS_CHECK(timer.open(s));
         QS_HIP(s, hipGraphLaunch(graph_exec, s->st));
@@ -2123,6 +2226,7 @@ struct TuneKey {
         return std::tie(hash, n, mode, f_req, tb_req) < std::tie(o.hash, o.n, o.mode, o.f_req, o.tb_req);
     }
 };
+constexpr double kTuneMargin = 0.03;  // a candidate must beat the default widths by 3 %
 std::mutex g_tune_mu;  // one tuning at a time: concurrent trials would disturb each other's timings
 std::map<TuneKey, std::pair<int, int>> g_tune_cache;
 
@@ -2161,7 +2265,7 @@ qs_status resolve_widths(qs_state s, const CircuitModel &m, uint64_t chash, cons
         }
     } guard{ev};
     const int reps = m.n >= 29 ? 1 : 2;  // the first of two also warms caches
-    double best = 1e300;
+    double best = 1e300, t_default = -1.0;
     for (int f : fs) {
         for (int tb : tbs) {
             qs_traj_params q = p;
@@ -2185,12 +2289,20 @@ qs_status resolve_widths(qs_state s, const CircuitModel &m, uint64_t chash, cons
                 QS_HIP(s, hipEventElapsedTime(&ms, ev[0], ev[1]));
                 t = std::min(t, double(ms));
             }
+            if (f == kDefaultFuse && tb == (p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits))
+                t_default = t;
             if (t < best) {
                 best = t;
                 *f_out = f;
                 *tb_out = tb;
             }
         }
+    }
+    // the default widths stay unless another pair is clearly faster: trial
+    // times of one pass differ by a percent or two from run to run
+    if (t_default > 0.0 && best > (1.0 - kTuneMargin) * t_default) {
+        *f_out = kDefaultFuse;
+        *tb_out = p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits;
     }
     g_tune_cache[key] = {*f_out, *tb_out};
     *tune_ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -2224,10 +2336,16 @@ qs_status run_trajectories_impl(qs_state s, const qs_circuit *c, const qs_traj_p
     if (p->n_samples < 0) return fail(QS_ERR_INVALID_ARGUMENT, "negative sample count");
     if (int64_t(p->n_samples) * int64_t(s->n) > (int64_t(1) << 32))
         return fail(QS_ERR_INVALID_ARGUMENT, "readout counter would overflow");
-    CircuitModel m;
-    QS_CHECK(build_model(c, m));
-    if (p->mode == QS_KRAUS_CONVENTIONAL_INPLACE)
-        for (auto &ci : m.channels) to_conventional(ci);
+    std::shared_ptr<const ModelEntry> me;
+    QS_CHECK(circuit_model(c, &me));
+    const CircuitModel *mp = &me->model;
+    CircuitModel conv;
+    if (p->mode == QS_KRAUS_CONVENTIONAL_INPLACE) {
+        conv = me->model;
+        for (auto &ci : conv.channels) to_conventional(ci);
+        mp = &conv;
+    }
+    const CircuitModel &m = *mp;
     QS_CHECK(flush_pending(s));
     r->sweeps = 0;
     r->gate_sweeps = 0;
@@ -2236,7 +2354,7 @@ qs_status run_trajectories_impl(qs_state s, const qs_circuit *c, const qs_traj_p
     for (int i = 0; i < 6; ++i) r->gate_k_launches[i] = 0;
     r->zero_start_sweeps = 0;
     r->graph_replays = 0;
-    const uint64_t chash = circuit_hash(c);
+    const uint64_t chash = me->id;
     qs_traj_params q = *p;
     double tms = 0.0;
     QS_CHECK(resolve_widths(s, m, chash, *p, &q.max_fuse, &q.tile_bits, &tms));
@@ -2299,12 +2417,16 @@ qs_status qs_run_trajectories_concurrent(qs_state *states, int n_states, const q
     qs_traj_params pr = *p;
     double tms = 0.0;
     {
-        CircuitModel m;
-        QS_CHECK(build_model(c, m));
-        if (p->mode == QS_KRAUS_CONVENTIONAL_INPLACE)
-            for (auto &ci : m.channels) to_conventional(ci);
+        std::shared_ptr<const ModelEntry> me;
+        QS_CHECK(circuit_model(c, &me));
+        CircuitModel conv;
+        if (p->mode == QS_KRAUS_CONVENTIONAL_INPLACE) {
+            conv = me->model;
+            for (auto &ci : conv.channels) to_conventional(ci);
+        }
+        const CircuitModel &m = p->mode == QS_KRAUS_CONVENTIONAL_INPLACE ? conv : me->model;
         QS_CHECK(flush_pending(states[0]));
-        QS_CHECK(resolve_widths(states[0], m, circuit_hash(c), *p, &pr.max_fuse, &pr.tile_bits, &tms));
+        QS_CHECK(resolve_widths(states[0], m, me->id, *p, &pr.max_fuse, &pr.tile_bits, &tms));
     }
     // contiguous chunks, the first (n_traj mod n_states) one trajectory longer
     std::vector<qs_traj_params> sp(n_states, pr);
@@ -2476,14 +2598,17 @@ constexpr int kBatchDefaultFuse = 3;
 // circuit hash and fusion width (a batch of the same circuits is planned
 // once; only the per-trajectory draws and patched blocks are redone).
 struct BatchPlanKey {
-    uint64_t hash;
+    uint64_t hash;  // model id
     int f;
     bool operator<(const BatchPlanKey &o) const { return std::tie(hash, f) < std::tie(o.hash, o.f); }
 };
 struct BatchPlanEntry {
     std::vector<qs::Block> blocks;
     std::vector<int> op_block;
-    std::vector<qs::Sweep> sweeps;
+    std::vector<int> gate_of_block;       // gate index (local) of each block
+    std::vector<qs::BatchSweep> sweeps;   // gate ranges local to the circuit
+    std::vector<qs::BatchGate> gates;     // mat: offset into pool
+    std::vector<float2> pool;             // the default matrices of the blocks
 };
 constexpr size_t kBatchPlanEntries = 2048;
 std::mutex g_bplan_mu;
@@ -2508,7 +2633,8 @@ void batch_plan_insert(const BatchPlanKey &k, std::shared_ptr<const BatchPlanEnt
 }
 
 struct BatchPlanCircuit {
-    CircuitModel m;
+    std::shared_ptr<const ModelEntry> me;
+    const CircuitModel *m = nullptr;  // me->model
     std::vector<qs::Block> blocks;
     std::vector<int> op_block;
     std::vector<const cd *> default_mats;
@@ -2535,6 +2661,10 @@ struct BatchBuffers {
     size_t slots_cap = 0;  // bytes
     char *host = nullptr;  // pinned staging for the program
     size_t host_cap = 0;
+    char *draw_dev = nullptr;   // channel draws: tables in, picks out
+    size_t draw_dev_cap = 0;
+    char *draw_host = nullptr;  // pinned mirror of draw_dev
+    size_t draw_host_cap = 0;
 };
 
 BatchBuffers &batch_buffers() {
@@ -2550,6 +2680,285 @@ BatchBuffers &batch_buffers() {
 
 void to_float2(int D, const cd *m, float2 *out) {
     for (int i = 0; i < D * D; ++i) out[i] = make_float2(float(m[i].real()), float(m[i].imag()));
+}
+
+// Host worker threads for the batched planner's parallel loops, started on
+// first use and kept: starting threads on every call cost more than the
+// per-trajectory draws they share.  One loop runs at a time; the calling
+// thread takes part in it.
+class HostPool {
+  public:
+    static HostPool &get() {
+        static HostPool *pool = new HostPool();  // never destroyed: workers may outlive statics
+        return *pool;
+    }
+    unsigned size() const { return unsigned(workers_.size()) + 1; }
+    // fn(lo, hi) over [0, n) in chunks of `chunk`, on at most `width` threads.
+    void run(size_t n, size_t chunk, unsigned width, const std::function<void(size_t, size_t)> &fn) {
+        if (n == 0) return;
+        chunk = std::max<size_t>(chunk, 1);
+        width = std::max(1u, std::min(width, size()));
+        if (width == 1 || n <= chunk) {
+            fn(0, n);
+            return;
+        }
+        std::lock_guard<std::mutex> one(run_mu_);
+        {
+            std::lock_guard<std::mutex> lock(mu_);
+            fn_ = &fn;
+            n_ = n;
+            chunk_ = chunk;
+            next_.store(0);
+            helpers_ = width - 1;
+            busy_ = 0;
+            ++generation_;
+        }
+        cv_.notify_all();
+        drain();
+        // helpers that have not started by now stay out of this loop
+        std::unique_lock<std::mutex> lock(mu_);
+        helpers_ = 0;
+        done_cv_.wait(lock, [&] { return busy_ == 0; });
+        fn_ = nullptr;
+    }
+
+  private:
+    HostPool() {
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const unsigned nw = std::min(15u, hw > 1 ? hw - 1 : 0u);
+        for (unsigned i = 0; i < nw; ++i) workers_.emplace_back([this] { loop(); });
+        for (auto &w : workers_) w.detach();
+    }
+    void drain() {
+        for (;;) {
+            const size_t lo = next_.fetch_add(chunk_);
+            if (lo >= n_) return;
+            (*fn_)(lo, std::min(n_, lo + chunk_));
+        }
+    }
+    void loop() {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lock(mu_);
+                cv_.wait(lock, [&] { return generation_ != seen && helpers_ > 0; });
+                seen = generation_;
+                --helpers_;
+                ++busy_;
+            }
+            drain();
+            {
+                std::lock_guard<std::mutex> lock(mu_);
+                --busy_;
+            }
+            done_cv_.notify_all();
+        }
+    }
+    std::vector<std::thread> workers_;
+    std::mutex run_mu_, mu_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(size_t, size_t)> *fn_ = nullptr;
+    size_t n_ = 0, chunk_ = 1;
+    std::atomic<size_t> next_{0};
+    unsigned helpers_ = 0, busy_ = 0;
+    uint64_t generation_ = 0;
+};
+
+// Batches with at least this many channel draws draw them on the device
+// (below it the round trip costs more than the host's draws); at most
+// kDeviceDrawMax, and with room for kDeviceOverCap picks other than the
+// default ones (beyond that the host draws instead).
+constexpr size_t kDeviceDrawMin = 16384;
+constexpr size_t kDeviceDrawMax = size_t(1) << 30;
+constexpr size_t kDeviceOverCap = size_t(1) << 20;
+constexpr size_t kDeviceOverFirst = 8192;  // entries copied back with the count
+
+// The channel draws of every job on the device.  job_of(j) gives job j's
+// (item, trajectory within the item); on_pick(j, channel, pick) receives
+// the picks other than the channel's default one, in (job, channel) order.
+// Recorded picks are written to the items' kraus_choices.  *done is false
+// (and nothing is reported) when the picks other than the default ones do
+// not fit the list: the caller then draws on the host.
+template <class JobOf, class OnPick>
+qs_status device_draws(const qs_batch_item *items, int n_items, const std::vector<BatchPlanCircuit> &plans,
+                       size_t n_jobs, JobOf job_of, size_t draws, hipStream_t st, BatchBuffers &BB,
+                       OnPick on_pick, bool *done) {
+    *done = false;
+    std::vector<qs::BatchDrawChannel> chan;
+    std::vector<double> pbar;
+    std::vector<int32_t> ch0(n_items);
+    std::vector<int64_t> choice_base(n_items, -1);
+    int64_t n_choices = 0;
+    for (int it = 0; it < n_items; ++it) {
+        const CircuitModel &m = *plans[it].m;
+        ch0[it] = int32_t(chan.size());
+        for (const ChannelInfo &c : m.channels) {
+            chan.push_back({c.nk, c.default_pick, int32_t(pbar.size()), 0});
+            pbar.insert(pbar.end(), c.pbar.begin(), c.pbar.end());
+        }
+        if (items[it].kraus_choices && !m.channels.empty()) {
+            choice_base[it] = n_choices;
+            n_choices += items[it].n_traj * int64_t(m.channels.size());
+        }
+    }
+    std::vector<qs::BatchDrawJob> dj(n_jobs);
+    for (size_t j = 0; j < n_jobs; ++j) {
+        const auto ir = job_of(j);
+        const qs_batch_item &I = items[ir.first];
+        const int nch = int(plans[ir.first].m->channels.size());
+        qs::BatchDrawJob &J = dj[j];
+        J.ch0 = ch0[ir.first];
+        J.nch = nch;
+        J.traj = uint32_t(I.traj_offset + ir.second);
+        J.circ_id = I.circuit_id;
+        J.seed = I.seed;
+        J.choices = choice_base[ir.first] >= 0 ? choice_base[ir.first] + ir.second * nch : -1;
+    }
+    const size_t over_cap = std::min(draws, kDeviceOverCap);
+    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const size_t o_chan = 0;
+    const size_t o_pbar = o_chan + align(sizeof(qs::BatchDrawChannel) * std::max<size_t>(chan.size(), 1));
+    const size_t o_jobs = o_pbar + align(sizeof(double) * std::max<size_t>(pbar.size(), 1));
+    const size_t o_count = o_jobs + align(sizeof(qs::BatchDrawJob) * n_jobs);
+    const size_t o_over = o_count + 256;
+    const size_t o_choice = o_over + align(sizeof(int32_t) * 3 * over_cap);
+    const size_t total = o_choice + align(size_t(std::max<int64_t>(n_choices, 1)));
+    hipError_t e = hipSuccess;
+    if (total > BB.draw_dev_cap) {
+        if (BB.draw_dev) (void)hipFree(BB.draw_dev);
+        BB.draw_dev = nullptr;
+        BB.draw_dev_cap = 0;
+        if ((e = hipMalloc(&BB.draw_dev, total)) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(QS_ERR_OUT_OF_MEMORY, "allocating the channel-draw buffers failed");
+        }
+        BB.draw_dev_cap = total;
+    }
+    if (total > BB.draw_host_cap) {
+        if (BB.draw_host) (void)hipHostFree(BB.draw_host);
+        BB.draw_host = nullptr;
+        BB.draw_host_cap = 0;
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&BB.draw_host), total, hipHostMallocDefault)) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return fail(QS_ERR_OUT_OF_MEMORY, "allocating pinned draw staging failed");
+        }
+        BB.draw_host_cap = total;
+    }
+    char *h = BB.draw_host, *d = BB.draw_dev;
+    std::memcpy(h + o_chan, chan.data(), sizeof(qs::BatchDrawChannel) * chan.size());
+    std::memcpy(h + o_pbar, pbar.data(), sizeof(double) * pbar.size());
+    std::memcpy(h + o_jobs, dj.data(), sizeof(qs::BatchDrawJob) * n_jobs);
+    std::memset(h + o_count, 0, sizeof(int32_t));
+    qs::BatchDrawArgs A;
+    A.chan = reinterpret_cast<const qs::BatchDrawChannel *>(d + o_chan);
+    A.pbar = reinterpret_cast<const double *>(d + o_pbar);
+    A.jobs = reinterpret_cast<const qs::BatchDrawJob *>(d + o_jobs);
+    A.n_jobs = int(n_jobs);
+    A.over_cap = int(over_cap);
+    A.choices = reinterpret_cast<int8_t *>(d + o_choice);
+    A.count = reinterpret_cast<int32_t *>(d + o_count);
+    A.over = reinterpret_cast<int32_t *>(d + o_over);
+    const size_t first = std::min(over_cap, kDeviceOverFirst);
+    auto dev = [&](hipError_t x) -> qs_status {
+        if (x == hipSuccess) return QS_OK;
+        return fail(QS_ERR_DEVICE, std::string("batched channel draws: ") + hipGetErrorString(x));
+    };
+    QS_CHECK(dev(hipMemcpyAsync(d, h, o_count + sizeof(int32_t), hipMemcpyHostToDevice, st)));
+    QS_CHECK(dev(qs::launch_batch_draws(A, st)));
+    QS_CHECK(dev(hipMemcpyAsync(h + o_count, d + o_count, (o_over - o_count) + sizeof(int32_t) * 3 * first,
+                                hipMemcpyDeviceToHost, st)));
+    if (n_choices > 0)
+        QS_CHECK(dev(hipMemcpyAsync(h + o_choice, d + o_choice, size_t(n_choices), hipMemcpyDeviceToHost, st)));
+    QS_CHECK(dev(hipStreamSynchronize(st)));
+    int32_t count = 0;
+    std::memcpy(&count, h + o_count, sizeof(count));
+    if (count < 0 || size_t(count) > over_cap) return QS_OK;  // the host draws instead
+    if (size_t(count) > first) {
+        QS_CHECK(dev(hipMemcpyAsync(h + o_over + sizeof(int32_t) * 3 * first, d + o_over + sizeof(int32_t) * 3 * first,
+                                    sizeof(int32_t) * 3 * (size_t(count) - first), hipMemcpyDeviceToHost, st)));
+        QS_CHECK(dev(hipStreamSynchronize(st)));
+    }
+    for (int it = 0; it < n_items; ++it)
+        if (choice_base[it] >= 0)
+            std::memcpy(items[it].kraus_choices, h + o_choice + choice_base[it],
+                        size_t(items[it].n_traj) * plans[it].m->channels.size());
+    std::vector<std::array<int32_t, 3>> over(static_cast<size_t>(count));
+    std::memcpy(over.data(), h + o_over, sizeof(int32_t) * 3 * size_t(count));
+    std::sort(over.begin(), over.end());
+    for (const auto &x : over) {
+        if (x[0] < 0 || size_t(x[0]) >= n_jobs || x[1] < 0 || x[1] >= dj[size_t(x[0])].nch ||
+            x[2] < 0 || x[2] >= chan[size_t(dj[size_t(x[0])].ch0 + x[1])].nk)
+            return fail(QS_ERR_DEVICE, "channel draw out of range");
+        on_pick(x[0], x[1], x[2]);
+    }
+    *done = true;
+    return QS_OK;
+}
+
+// Fusion, sweep grouping and default block matrices of one circuit for the
+// batched launch (every channel at its most likely pick).
+qs_status plan_batched_circuit(const CircuitModel &m, const std::vector<const cd *> &default_mats,
+                               int f, bool resident, BatchPlanEntry &e) {
+    const int n = m.n;
+    e.blocks = qs::fuse_greedy(n, m.ops, f, &e.op_block);
+    std::vector<qs::Sweep> sw;
+    if (resident) {
+        qs::Sweep one;
+        for (size_t b = 0; b < e.blocks.size(); ++b) one.blocks.push_back(int(b));
+        sw.push_back(std::move(one));
+    } else {
+        static const int no_budget[6] = {0, 0, 0, 0, 0, 0};
+        sw = qs::group_sweeps(n, e.blocks, qs::kBatchTileBits, 6, 1 << 30, 1 << 30, no_budget);
+    }
+    e.gate_of_block.assign(e.blocks.size(), -1);
+    std::vector<cd> tmp(1024);
+    for (const auto &w : sw) {
+        qs::BatchSweep S;
+        std::memset(&S, 0, sizeof(S));
+        int local[64];
+        for (int q = 0; q < 64; ++q) local[q] = q;
+        if (resident) {
+            S.tb = n;
+        } else {
+            std::vector<char> in(n, 0);
+            for (int q : w.bits) in[q] = 1;
+            int cnt = int(w.bits.size());
+            for (int q = 0; q < n && cnt < qs::kBatchTileBits; ++q)
+                if (!in[q]) {
+                    in[q] = 1;
+                    ++cnt;
+                }
+            if (cnt > qs::kBatchLdsQubits)  // the tile must fit the LDS state area
+                return fail(QS_ERR_NOT_SUPPORTED, "block too wide for a tile");
+            S.tb = cnt;
+            int i = 0;
+            for (int q = 0; q < n; ++q)
+                if (in[q]) {
+                    S.pos[i] = q;
+                    local[q] = i;
+                    ++i;
+                }
+        }
+        S.g0 = int(e.gates.size());
+        for (int b : w.blocks) {
+            const qs::Block &B = e.blocks[b];
+            qs::BatchGate G;
+            std::memset(&G, 0, sizeof(G));
+            G.k = B.k;
+            for (int j = 0; j < B.k; ++j) G.lt[j] = local[B.q[j]];
+            qs::fused_matrix(B.k, B.q, B.ops, m.ops, default_mats, tmp.data());
+            const int D = 1 << B.k;
+            G.mat = int(e.pool.size());
+            e.pool.resize(e.pool.size() + size_t(D) * D + (D * D) % 2);
+            to_float2(D, tmp.data(), e.pool.data() + G.mat);
+            e.gate_of_block[b] = int(e.gates.size());
+            e.gates.push_back(G);
+        }
+        S.g1 = int(e.gates.size());
+        e.sweeps.push_back(S);
+    }
+    return QS_OK;
 }
 
 }  // namespace
@@ -2593,59 +3002,36 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
         BatchPlanCircuit &P = plans[it];
         CircPieces &X = pieces[it];
         P.circuit_index = it;
-        qs_status stt = build_model(I.circuit, P.m);
+        qs_status stt = circuit_model(I.circuit, &P.me);
         if (stt != QS_OK) {
             X.status = stt;
             X.error = g_last_error;
             return;
         }
-        for (const auto &c : P.m.channels)
+        P.m = &P.me->model;
+        for (const auto &c : P.m->channels)
             if (!c.mixture) {
                 X.status = QS_ERR_NOT_SUPPORTED;
                 X.error = "batched launch takes channels whose Kraus operators are all proportional to unitaries";
                 return;
             }
         qs::ReadoutDesc ro;
-        stt = fill_readout(P.m.n, I.p0to1, I.p1to0, ro);
+        stt = fill_readout(P.m->n, I.p0to1, I.p1to0, ro);
         if (stt != QS_OK) {
             X.status = stt;
             X.error = g_last_error;
             return;
         }
-        const int n = P.m.n;
+        const int n = P.m->n;
         P.resident = n <= qs::kBatchLdsQubits;
-        const int n_ops = int(P.m.ops.size());
+        const int n_ops = int(P.m->ops.size());
         P.default_mats.assign(n_ops, nullptr);
         for (int o = 0; o < n_ops; ++o) {
-            if (P.m.kind[o] == QS_OP_GATE) P.default_mats[o] = P.m.gate_mat[o];
+            if (P.m->kind[o] == QS_OP_GATE) P.default_mats[o] = P.m->gate_mat[o];
             else {
-                const ChannelInfo &c = P.m.channels[P.m.channel_of_op[o]];
+                const ChannelInfo &c = P.m->channels[P.m->channel_of_op[o]];
                 P.default_mats[o] = fast_pick_matrix(c, c.default_pick);
             }
-        }
-        std::vector<qs::Sweep> sw;
-        const BatchPlanKey bkey{circuit_hash(I.circuit), f};
-        std::shared_ptr<const BatchPlanEntry> hit;
-        batch_plan_lookup(bkey, &hit);
-        if (hit) {
-            P.blocks = hit->blocks;
-            P.op_block = hit->op_block;
-            sw = hit->sweeps;
-        } else {
-            P.blocks = qs::fuse_greedy(n, P.m.ops, f, &P.op_block);
-            if (P.resident) {
-                qs::Sweep one;
-                for (size_t b = 0; b < P.blocks.size(); ++b) one.blocks.push_back(int(b));
-                sw.push_back(std::move(one));
-            } else {
-                static const int no_budget[6] = {0, 0, 0, 0, 0, 0};
-                sw = qs::group_sweeps(n, P.blocks, qs::kBatchTileBits, 6, 1 << 30, 1 << 30, no_budget);
-            }
-            auto e = std::make_shared<BatchPlanEntry>();
-            e->blocks = P.blocks;
-            e->op_block = P.op_block;
-            e->sweeps = sw;
-            batch_plan_insert(bkey, std::move(e));
         }
         qs::BatchCircuit &C = circs[it];
         C.n = n;
@@ -2657,66 +3043,31 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
             for (int q = 0; q < n; ++q) X.readout.push_back(ro.e0[q]);
             for (int q = 0; q < n; ++q) X.readout.push_back(ro.e1[q]);
         }
-        P.gate_of_block.assign(P.blocks.size(), -1);
-        std::vector<cd> tmp(1024);
-        for (const auto &w : sw) {
-            qs::BatchSweep S;
-            std::memset(&S, 0, sizeof(S));
-            int local[64];
-            for (int q = 0; q < 64; ++q) local[q] = q;
-            if (P.resident) {
-                S.tb = n;
-            } else {
-                std::vector<char> in(n, 0);
-                for (int q : w.bits) in[q] = 1;
-                int cnt = int(w.bits.size());
-                for (int q = 0; q < n && cnt < qs::kBatchTileBits; ++q)
-                    if (!in[q]) {
-                        in[q] = 1;
-                        ++cnt;
-                    }
-                if (cnt > qs::kBatchLdsQubits) {  // the tile must fit the LDS state area
-                    X.status = QS_ERR_NOT_SUPPORTED;
-                    X.error = "block too wide for a tile";
-                    return;
-                }
-                S.tb = cnt;
-                int i = 0;
-                for (int q = 0; q < n; ++q)
-                    if (in[q]) {
-                        S.pos[i] = q;
-                        local[q] = i;
-                        ++i;
-                    }
+        const BatchPlanKey bkey{P.me->id, f};
+        std::shared_ptr<const BatchPlanEntry> hit;
+        batch_plan_lookup(bkey, &hit);
+        if (!hit) {
+            auto e = std::make_shared<BatchPlanEntry>();
+            const qs_status ps = plan_batched_circuit(*P.m, P.default_mats, f, P.resident, *e);
+            if (ps != QS_OK) {
+                X.status = ps;
+                X.error = g_last_error;
+                return;
             }
-            S.g0 = int(X.gates.size());  // local; shifted when concatenated
-            for (int b : w.blocks) {
-                const qs::Block &B = P.blocks[b];
-                qs::BatchGate G;
-                std::memset(&G, 0, sizeof(G));
-                G.k = B.k;
-                for (int j = 0; j < B.k; ++j) G.lt[j] = local[B.q[j]];
-                qs::fused_matrix(B.k, B.q, B.ops, P.m.ops, P.default_mats, tmp.data());
-                const int D = 1 << B.k;
-                G.mat = int(X.pool.size());
-                X.pool.resize(X.pool.size() + size_t(D) * D + (D * D) % 2);
-                to_float2(D, tmp.data(), X.pool.data() + G.mat);
-                P.gate_of_block[b] = int(X.gates.size());
-                X.gates.push_back(G);
-            }
-            S.g1 = int(X.gates.size());
-            X.sweeps.push_back(S);
+            batch_plan_insert(bkey, e);
+            hit = std::move(e);
         }
+        P.blocks = hit->blocks;
+        P.op_block = hit->op_block;
+        P.gate_of_block = hit->gate_of_block;
+        X.sweeps = hit->sweeps;
+        X.gates = hit->gates;
+        X.pool = hit->pool;
     };
     {
-        const unsigned nt = std::max(1u, std::min({16u, std::thread::hardware_concurrency(),
-                                                   unsigned(std::max(n_items, 1))}));
-        std::vector<std::thread> th;
-        for (unsigned w = 0; w < nt; ++w)
-            th.emplace_back([&, w]() {
-                for (int it = int(w); it < n_items; it += int(nt)) plan_one(it);
-            });
-        for (auto &x : th) x.join();
+        HostPool::get().run(size_t(n_items), 1, 16u, [&](size_t lo, size_t hi) {
+            for (size_t it = lo; it < hi; ++it) plan_one(int(it));
+        });
     }
     std::vector<qs::BatchSweep> sweeps;
     std::vector<qs::BatchGate> gates;
@@ -2749,7 +3100,7 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
             C.readout = int(readout.size());
             readout.insert(readout.end(), X.readout.begin(), X.readout.end());
         }
-        if (!P.resident) max_tiled_n = std::max(max_tiled_n, P.m.n);
+        if (!P.resident) max_tiled_n = std::max(max_tiled_n, P.m->n);
         total_jobs += items[it].n_traj;
         total_samples += items[it].n_traj * int64_t(items[it].n_samples);
     }
@@ -2765,67 +3116,86 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
     refs.reserve(size_t(total_jobs));
     for (int it = 0; it < n_items; ++it)
         for (int64_t t = 0; t < items[it].n_traj; ++t)
-            refs.push_back({it, t, double(int64_t(1) << plans[it].m.n) * double(plans[it].blocks.size())});
+            refs.push_back({it, t, double(int64_t(1) << plans[it].m->n) * double(plans[it].blocks.size())});
     std::vector<BatchTrajOut> outs(refs.size());
-    // threads by the number of draws (one Philox call per channel per trajectory)
-    size_t draws = 0;
-    for (const auto &R : refs) draws += plans[R.item].m.channels.size();
-    unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    nthreads = unsigned(std::min<size_t>({size_t(nthreads), std::max<size_t>(draws / 4096, 1),
-                                          std::max<size_t>(refs.size(), 1)}));
-    auto worker = [&](size_t lo, size_t hi) {
-        std::vector<cd> t2(1024);
-        std::vector<int> sub;
-        for (size_t j = lo; j < hi; ++j) {
-            const qs_batch_item &I = items[refs[j].item];
-            const BatchPlanCircuit &P = plans[refs[j].item];
-            const uint32_t traj = uint32_t(I.traj_offset + refs[j].rel);
-            const int nch = int(P.m.channels.size());
-            int8_t *choices = I.kraus_choices ? I.kraus_choices + refs[j].rel * nch : nullptr;
-            std::vector<std::pair<int, const cd *>> over;  // op, matrix
-            for (int c = 0; c < nch; ++c) {
-                const ChannelInfo &ci = P.m.channels[c];
-                const double rr = qs::philox_uniform(I.seed, channel_draw_index(uint32_t(c)), traj,
-                                                     I.circuit_id, qs::kStreamChannel);
-                double resid = 0.0;
-                const int pk = select_fast(ci, rr, &resid);  // mixtures always resolve here
-                if (choices) choices[c] = int8_t(pk);
-                if (pk != ci.default_pick) over.emplace_back(ci.op, fast_pick_matrix(ci, pk));
-            }
-            if (over.empty()) continue;
-            std::vector<const cd *> mats = P.default_mats;
-            std::vector<int> dirty_blocks;
-            for (auto &o : over) {
-                mats[o.first] = o.second;
-                dirty_blocks.push_back(P.op_block[o.first]);
-            }
-            std::sort(dirty_blocks.begin(), dirty_blocks.end());
-            dirty_blocks.erase(std::unique(dirty_blocks.begin(), dirty_blocks.end()), dirty_blocks.end());
-            BatchTrajOut &O = outs[j];
-            for (int b : dirty_blocks) {
-                const qs::Block &B = P.blocks[b];
-                qs::fused_matrix(B.k, B.q, B.ops, P.m.ops, mats, t2.data());
-                const int D = 1 << B.k;
-                qs::BatchPatch pt;
-                pt.gate = P.gate_of_block[b];
-                pt.mat = int(O.pool.size());
-                O.pool.resize(O.pool.size() + size_t(D) * D + (D * D) % 2);
-                to_float2(D, t2.data(), O.pool.data() + pt.mat);
-                O.patches.push_back(pt);
-            }
-            std::sort(O.patches.begin(), O.patches.end(),
-                      [](const qs::BatchPatch &a, const qs::BatchPatch &b) { return a.gate < b.gate; });
+    size_t draws = 0;  // one Philox call per channel per trajectory
+    for (const auto &R : refs) draws += plans[R.item].m->channels.size();
+    // The patched blocks of job j from its picks other than the default ones.
+    auto patch_job = [&](size_t j, const std::vector<std::pair<int, const cd *>> &over,
+                         std::vector<cd> &t2) {
+        const BatchPlanCircuit &P = plans[refs[j].item];
+        std::vector<const cd *> mats = P.default_mats;
+        std::vector<int> dirty_blocks;
+        for (auto &o : over) {
+            mats[o.first] = o.second;
+            dirty_blocks.push_back(P.op_block[o.first]);
         }
+        std::sort(dirty_blocks.begin(), dirty_blocks.end());
+        dirty_blocks.erase(std::unique(dirty_blocks.begin(), dirty_blocks.end()), dirty_blocks.end());
+        BatchTrajOut &O = outs[j];
+        for (int b : dirty_blocks) {
+            const qs::Block &B = P.blocks[b];
+            qs::fused_matrix(B.k, B.q, B.ops, P.m->ops, mats, t2.data());
+            const int D = 1 << B.k;
+            qs::BatchPatch pt;
+            pt.gate = P.gate_of_block[b];
+            pt.mat = int(O.pool.size());
+            O.pool.resize(O.pool.size() + size_t(D) * D + (D * D) % 2);
+            to_float2(D, t2.data(), O.pool.data() + pt.mat);
+            O.patches.push_back(pt);
+        }
+        std::sort(O.patches.begin(), O.patches.end(),
+                  [](const qs::BatchPatch &a, const qs::BatchPatch &b) { return a.gate < b.gate; });
     };
-    {
-        std::vector<std::thread> th;
-        const size_t per = (refs.size() + nthreads - 1) / std::max(nthreads, 1u);
-        for (unsigned w = 0; w < nthreads; ++w) {
-            const size_t lo = w * per, hi = std::min(refs.size(), lo + per);
-            if (lo >= hi) break;
-            th.emplace_back(worker, lo, hi);
-        }
-        for (auto &x : th) x.join();
+    BatchBuffers &BB = batch_buffers();
+    std::lock_guard<std::mutex> hold(BB.lock);
+    hipError_t e = hipSuccess;
+    bool drawn = false;
+    if (draws >= kDeviceDrawMin && draws <= kDeviceDrawMax) {
+        // ---- draws on the device; only the picks other than the default
+        // ones come back, and only their jobs are patched on the host
+        std::vector<std::vector<std::pair<int, const cd *>>> over_of(refs.size());
+        std::vector<int> jobs_over;
+        QS_CHECK(device_draws(items, n_items, plans, refs.size(),
+                              [&](size_t j) { return std::make_pair(refs[j].item, refs[j].rel); },
+                              draws, st, BB, [&](int j, int c, int pick) {
+                                  const BatchPlanCircuit &P = plans[refs[j].item];
+                                  const ChannelInfo &ci = P.m->channels[c];
+                                  if (over_of[j].empty()) jobs_over.push_back(j);
+                                  over_of[j].emplace_back(ci.op, fast_pick_matrix(ci, pick));
+                              }, &drawn));
+        HostPool::get().run(jobs_over.size(), 8, 16u, [&](size_t lo, size_t hi) {
+            std::vector<cd> t2(1024);
+            for (size_t x = lo; x < hi; ++x) patch_job(size_t(jobs_over[x]), over_of[jobs_over[x]], t2);
+        });
+    }
+    if (!drawn) {
+        // ---- draws on the host, spread over the worker threads in chunks of
+        // about 2048 draws
+        const unsigned nthreads = unsigned(std::min<size_t>(16, std::max<size_t>(draws / 4096, 1)));
+        const size_t chunk = std::max<size_t>(1, refs.empty() ? 1 : 2048 * refs.size() / std::max<size_t>(draws, 1));
+        HostPool::get().run(refs.size(), chunk, nthreads, [&](size_t lo, size_t hi) {
+            std::vector<cd> t2(1024);
+            std::vector<std::pair<int, const cd *>> over;  // op, matrix
+            for (size_t j = lo; j < hi; ++j) {
+                const qs_batch_item &I = items[refs[j].item];
+                const BatchPlanCircuit &P = plans[refs[j].item];
+                const uint32_t traj = uint32_t(I.traj_offset + refs[j].rel);
+                const int nch = int(P.m->channels.size());
+                int8_t *choices = I.kraus_choices ? I.kraus_choices + refs[j].rel * nch : nullptr;
+                over.clear();
+                for (int c = 0; c < nch; ++c) {
+                    const ChannelInfo &ci = P.m->channels[c];
+                    const double rr = qs::philox_uniform(I.seed, channel_draw_index(uint32_t(c)), traj,
+                                                         I.circuit_id, qs::kStreamChannel);
+                    double resid = 0.0;
+                    const int pk = select_fast(ci, rr, &resid);  // mixtures always resolve here
+                    if (choices) choices[c] = int8_t(pk);
+                    if (pk != ci.default_pick) over.emplace_back(ci.op, fast_pick_matrix(ci, pk));
+                }
+                if (!over.empty()) patch_job(j, over, t2);
+            }
+        });
     }
     // ---- jobs (largest first, so the persistent workgroups finish together)
     std::vector<size_t> order(refs.size());
@@ -2886,9 +3256,6 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
     const int grid = qs::batched_grid();
     const size_t slot_amps = max_tiled_n > 0 ? size_t(1) << max_tiled_n : 0;
     const size_t b_slots = sizeof(float2) * slot_amps * size_t(grid);
-    BatchBuffers &BB = batch_buffers();
-    std::lock_guard<std::mutex> hold(BB.lock);
-    hipError_t e = hipSuccess;
     auto grow = [&](size_t need_prog, size_t need_slots) -> qs_status {
         size_t free_b = 0, total_b = 0;
         if (need_prog > BB.prog_cap || need_slots > BB.slots_cap || need_prog > BB.host_cap) {
@@ -2951,7 +3318,6 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
     const size_t o_out = off;
     qs_status status = QS_OK;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::vector<uint64_t> out(size_t(std::max<int64_t>(total_samples, 1)));
     do {
         if ((e = hipMemcpyAsync(dbuf, hostp, o_out, hipMemcpyHostToDevice, st)) != hipSuccess) break;
         qs::BatchArgs A;
@@ -2974,7 +3340,8 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
         }
         if ((e = qs::launch_batched(A, std::min<int64_t>(grid, int64_t(jobs.size())), st)) != hipSuccess) break;
         if (timing && (e = hipEventRecord(ev1, st)) != hipSuccess) break;
-        if ((e = hipMemcpyAsync(out.data(), dbuf + o_out, sizeof(uint64_t) * size_t(total_samples),
+        // samples come back into the pinned staging (its program part has been sent)
+        if ((e = hipMemcpyAsync(hostp + o_out, dbuf + o_out, sizeof(uint64_t) * size_t(total_samples),
                                 hipMemcpyDeviceToHost, st)) != hipSuccess)
             break;
         if ((e = hipStreamSynchronize(st)) != hipSuccess) break;
@@ -2990,10 +3357,11 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (status != QS_OK) return status;
+    const uint64_t *out = reinterpret_cast<const uint64_t *>(hostp + o_out);
     for (int it = 0; it < n_items; ++it) {
         const int64_t cnt = items[it].n_traj * int64_t(items[it].n_samples);
         if (cnt > 0)
-            std::memcpy(items[it].bitstrings, out.data() + item_out_base[it], sizeof(uint64_t) * size_t(cnt));
+            std::memcpy(items[it].bitstrings, out + item_out_base[it], sizeof(uint64_t) * size_t(cnt));
     }
     r->host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return QS_OK;
@@ -3046,15 +3414,17 @@ extern "C" qs_status qs_run_batched(const qs_batch_item *items, int n_items,
             }
             qs_batch_params tp = *bp;
             tp.flags &= ~uint32_t(QS_TRAJ_TIME_KERNELS);
-            double best = 1e300;
+            double best = 1e300, t_default = -1.0;
             for (int cand : {2, 3, 4, 5}) {
                 qs_batch_result tr;
                 QS_CHECK(run_batched_impl(trial.data(), n_items, &tp, cand, &tr));
+                if (cand == kBatchDefaultFuse) t_default = tr.host_seconds;
                 if (tr.host_seconds < best) {
                     best = tr.host_seconds;
                     f = cand;
                 }
             }
+            if (t_default > 0.0 && best > (1.0 - kTuneMargin) * t_default) f = kBatchDefaultFuse;
             g_btune_cache[key] = f;
             tune_ms = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         }

@@ -87,3 +87,39 @@ def test_batched_rejects_non_mixtures(qs):
     with pytest.raises(qs.QsError) as e:
         qs.qs_run_batched([w])
     assert e.value.code == qs.QS_ERR_NOT_SUPPORTED
+
+
+def test_batched_device_draws_match_host_draws_and_oracle(qs, orc):
+    """Batches with many channel draws take them on the device and patch only
+    the jobs whose picks differ from the defaults.  Heavy noise (p = 0.3) puts
+    more than 8192 such picks in the list (its second copy-back), and two
+    circuits of different sizes give the channel table two ranges.  The same
+    trajectories drawn on the host (a batch small enough for host draws) and
+    by the oracle agree."""
+    specs = [(12, 8, 0.3, 0, 6), (16, 5, 0.3, 0, 6)]
+    items = _items(specs)
+    nch = [qs.MarshalledCircuit(w.circuit).n_channels for w in items]
+    for w, k in zip(items, nch):
+        w.n_traj = 24000 // k + 3
+    draws = sum(w.n_traj * k for w, k in zip(items, nch))
+    assert draws >= 40000
+    big, _ = qs.qs_run_batched(items)
+    non_default = sum(int(np.count_nonzero(r["choices"])) for r in big)
+    assert non_default > 8192, non_default
+    small_items = _items(specs)
+    for w in small_items:
+        w.n_traj = 3
+    assert sum(3 * k for k in nch) < 16384
+    small, _ = qs.qs_run_batched(small_items)
+    for r_big, r_small in zip(big, small):
+        assert np.array_equal(r_big["choices"][:3], r_small["choices"])
+        assert np.array_equal(r_big["samples"][:3], r_small["samples"])
+    for w, r in zip(items, big):
+        m = orc.Marshalled(w.circuit)
+        for t in (0, w.n_traj - 1):
+            ref = orc.run_trajectory(w.circuit, t, seed=w.seed, circ=w.circuit_id,
+                                     n_samples=w.n_samples, e0=w.e0, e1=w.e1, marshalled=m)
+            _, tie = compare_choices(r["choices"][t], ref)
+            assert tie == 0
+            mism = np.nonzero(r["samples"][t] != ref["samples"])[0]
+            assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE), (w.name, t, mism)

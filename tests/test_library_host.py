@@ -2,6 +2,7 @@
 declares is exported, argument validation, the fusion planner (Section 3.2),
 Kraus bounds (Section 3.5) and the library's own Philox."""
 
+import ctypes
 import os
 import re
 import subprocess
@@ -194,3 +195,24 @@ def test_fusion_merges_subset_blocks(lib):
         later = [tj for tj, _ in blocks[i + 1:] if set(tj) & set(ti)]
         if later:
             assert not set(ti) <= set(later[0])
+
+
+def test_batched_planning_without_trajectories(lib):
+    """The batched call's host planning runs before any device work, so a
+    batch with no trajectories completes on the host: an empty circuit (no
+    ops, empty matrix pool) is a valid circuit, a repeated call reuses the
+    cached circuit model, and a circuit with ops but no op records is
+    rejected."""
+    empty = W.Circuit(5, [])
+    grid = W.grid_circuit(3, 4, 3, p_dep=0.01, seed=4)
+    items = [W.TrajectoryWorkload("empty", empty, n_traj=0, n_samples=4),
+             W.TrajectoryWorkload("grid", grid, n_traj=0, n_samples=4)]
+    for _ in range(2):
+        _, stats = lib.qs_run_batched(items, max_fuse=3)
+        assert stats["jobs"] == 0
+    pb = lib.PreparedBatch(items[1:])
+    circ = ctypes.cast(pb.items[0].circuit, ctypes.POINTER(lib.QsCircuit)).contents
+    circ.ops = None
+    with pytest.raises(lib.QsError) as e:
+        lib.qs_run_batched(pb, max_fuse=3)
+    assert e.value.code == lib.QS_ERR_INVALID_ARGUMENT
