@@ -143,7 +143,7 @@ def sweep_roofline(n, ms, launches, zero_start, k_hist):
 
 
 def run_grid(qs, W, args, torch, rows=4, cols=6, p_dep=1e-3, n_traj=1000, steps=1, warmup=1,
-             streams=2, max_fuse=0, tile_bits=0, workload=None, mark=False, graph=True):
+             streams=2, max_fuse=0, tile_bits=0, workload=None, mark=False, graph=False):
     """Trajectory steps of a noisy grid on `streams` concurrent states;
     returns the rate, the sweep roofline and the plan the driver used."""
     w = workload or W.grid24_workload(p_dep=p_dep, rows=rows, cols=cols)
@@ -204,7 +204,7 @@ def run_grid(qs, W, args, torch, rows=4, cols=6, p_dep=1e-3, n_traj=1000, steps=
     }
 
 
-def one_state_rate(qs, W, torch, w, n_traj, mode, max_fuse=0, tile_bits=0, warm=1, graph=True):
+def one_state_rate(qs, W, torch, w, n_traj, mode, max_fuse=0, tile_bits=0, warm=1, graph=False):
     """Trajectories/s of one state on one stream (kernels untimed)."""
     c = w.circuit
     mc = qs.MarshalledCircuit(c)

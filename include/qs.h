@@ -95,8 +95,10 @@ enum {
     QS_TRAJ_RETURN_STATE = 1u, /* copy the last trajectory's final amplitudes to final_state */
     QS_TRAJ_TIME_KERNELS = 2u, /* bracket every fused-gate launch with HIP events on the
                                   state's stream and report their summed durations */
-    QS_TRAJ_NO_GRAPH = 4u      /* launch every sweep directly: no HIP-graph replay of the
-                                  default plan (see qs_run_trajectories) */
+    QS_TRAJ_NO_GRAPH = 4u,     /* launch every sweep directly (the default; overrides
+                                  QS_TRAJ_GRAPH) */
+    QS_TRAJ_GRAPH = 8u         /* replay the default plan's sweeps from a HIP graph where
+                                  possible (see qs_run_trajectories) */
 };
 
 typedef struct {
@@ -282,15 +284,16 @@ qs_status qs_sample_measurements_noalloc(qs_state s, uint64_t seed, uint32_t tra
  * resolves every channel by the conventional method instead, and
  * QS_KRAUS_CONVENTIONAL_INPLACE by the conventional rule with in-place
  * inner products (every channel takes the inner-product path).
- * Small states (delayed mode, at most 22 qubits, two or more trajectories,
- * every sweep a tile sweep): the sweeps of the circuit's default plan are
- * captured once per call into a HIP graph whose kernels read each fused
- * block's matrix from a fixed device slot; a trajectory whose channels are
- * all picked from the bounds then writes its patched blocks into their slots
- * (one host-to-device copy on the stream) and replays the graph, instead of
- * launching the sweeps one by one.  The results are those of the direct
- * launches (the same kernels on the same matrices); QS_TRAJ_NO_GRAPH turns
- * the replay off.
+ * With QS_TRAJ_GRAPH, on small states (delayed mode, at most 22 qubits, two
+ * or more trajectories, every sweep a tile sweep): the sweeps of the
+ * circuit's default plan are captured once per call into a HIP graph whose
+ * kernels read each fused block's matrix from a fixed device slot; a
+ * trajectory whose channels are all picked from the bounds then writes its
+ * patched blocks into their slots (one host-to-device copy on the stream)
+ * and replays the graph, instead of launching the sweeps one by one.  The
+ * results are those of the direct launches (the same kernels on the same
+ * matrices).  Off by default: on MI355X with ROCm 7 the replays measured a
+ * few percent slower than direct launches of the same sweeps.
  * The circuit's n_qubits must equal the state's.  Results are written to the
  * caller's host arrays in r.  On return the state holds the last trajectory's
  * final vector (lazily normalised; what QS_TRAJ_RETURN_STATE copies out), or

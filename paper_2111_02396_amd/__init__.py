@@ -34,6 +34,7 @@ QS_OP_CHANNEL = 1
 QS_TRAJ_RETURN_STATE = 1
 QS_TRAJ_TIME_KERNELS = 2
 QS_TRAJ_NO_GRAPH = 4
+QS_TRAJ_GRAPH = 8
 
 _NAMES = {0: "QS_OK", -1: "QS_ERR_INVALID_ARGUMENT", -2: "QS_ERR_OUT_OF_MEMORY",
           -3: "QS_ERR_DEVICE", -4: "QS_ERR_ZERO_NORM", -5: "QS_ERR_NOT_SUPPORTED"}
@@ -318,7 +319,7 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
                         tile_bits: int = 0,
                         n_samples: int = 0, p0to1=None, p1to0=None, return_state: bool = False,
                         record_choices: bool = True, time_kernels: bool = False,
-                        z_expect: bool = False, graph: bool = True,
+                        z_expect: bool = False, graph: bool = False,
                         marshalled: Optional[MarshalledCircuit] = None) -> Dict:
     """Run trajectories traj_offset .. traj_offset + n_traj - 1 (qs_run_trajectories).
     `s` may also be a list of state handles: the range is then split over them
@@ -328,7 +329,7 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
     e0 = None if p0to1 is None else np.ascontiguousarray(p0to1, dtype=np.float64)
     e1 = None if p1to0 is None else np.ascontiguousarray(p1to0, dtype=np.float64)
     flags = (QS_TRAJ_RETURN_STATE if return_state else 0) | \
-        (QS_TRAJ_TIME_KERNELS if time_kernels else 0) | (0 if graph else QS_TRAJ_NO_GRAPH)
+        (QS_TRAJ_TIME_KERNELS if time_kernels else 0) | (QS_TRAJ_GRAPH if graph else 0)
     params = QsTrajParams(n_traj, traj_offset, seed, circuit_id, mode, max_fuse, tile_bits,
                           n_samples, _p(e0), _p(e1), flags)
     bits = np.zeros(max(n_traj * n_samples, 1), dtype=np.uint64)

@@ -588,27 +588,24 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
             if (((r << (NB + 1)) >> b) & 1) o |= Idx(1) << a.pos[b];
         off_r[r] = o;
     }
+    // First index of tile t: the bits of t spread over the positions the tile
+    // does not hold.  Inserting a zero at position q adds the part of the
+    // index at and above q to itself (shifting it up by one); positions 0..3
+    // are always the tile's, which is one shift.
     auto tile_base = [&](Idx t) {
-        Idx base = t;
+        Idx base = t << kTileLowBits;
 #pragma unroll
-        for (int b = 0; b < TB; ++b) {
-            const int q = a.pos[b];
-            base = ((base >> q) << (q + 1)) | (base & ((Idx(1) << q) - Idx(1)));
-        }
+        for (int b = kTileLowBits; b < TB; ++b) base += base & (~Idx(0) << a.pos[b]);
         return base + off_tid;
     };
-    // A tile's amplitude pairs; with init_zero the sweep starts from |0...0>
-    // (amplitude 1 at index 0) without reading the state.
+    // A tile's amplitude pairs.  With init_zero the sweep starts from
+    // |0...0> without reading the state: nothing is fetched, and the tile's
+    // LDS copy is written from zeros (amplitude 1 at index 0).
     auto fetch = [&](Idx t, float4 (&dst)[R]) {
+        if (a.init_zero) return;
         const Idx base = tile_base(t);
-        if (a.init_zero) {
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                dst[r] = make_float4(base + off_r[r] == Idx(0) ? 1.f : 0.f, 0.f, 0.f, 0.f);
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) dst[r] = *reinterpret_cast<const float4 *>(amp + base + off_r[r]);
-        }
+        for (int r = 0; r < R; ++r) dst[r] = *reinterpret_cast<const float4 *>(amp + base + off_r[r]);
     };
     float4 v[R];
     fetch(tile, v);
@@ -646,12 +643,21 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
     Idx prev_base = 0;
     auto run_tile = [&](Idx t, bool has_prev) {
         __syncthreads();  // the previous tile is out of LDS; matrices staged
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            sd[tid_l + (r << (NB + 1))] = make_float2(v[r].x, v[r].y);
-            sd[(tid_l ^ 1) + (r << (NB + 1))] = make_float2(v[r].z, v[r].w);
-        }
         const Idx base = tile_base(t);
+        if (a.init_zero) {
+            const float one = base == Idx(0) ? 1.f : 0.f;  // index 0 is pair 0 of work-item 0
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                sd[tid_l + (r << (NB + 1))] = make_float2(r == 0 ? one : 0.f, 0.f);
+                sd[(tid_l ^ 1) + (r << (NB + 1))] = make_float2(0.f, 0.f);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                sd[tid_l + (r << (NB + 1))] = make_float2(v[r].x, v[r].y);
+                sd[(tid_l ^ 1) + (r << (NB + 1))] = make_float2(v[r].z, v[r].w);
+            }
+        }
         if (has_prev) {
 #pragma unroll
             for (int r = 0; r < R; ++r) *reinterpret_cast<float4 *>(amp + prev_base + off_r[r]) = o[r];
@@ -1139,8 +1145,9 @@ __device__ __forceinline__ double chunk_weight(const float2 *__restrict__ amp, I
 }
 
 // One wavefront per sampling block of 2^B amplitudes (kBlock / 64 blocks per
-// workgroup): each lane sums a contiguous run of 2^B / 64 amplitudes, then a
-// fixed shuffle tree adds the runs.
+// workgroup): the lanes read the block coalesced (lane j takes pairs j,
+// j + 64, ... as 16-byte loads) and add in that fixed order, then a fixed
+// shuffle tree adds the lanes.
 template <typename Idx>
 __global__ __launch_bounds__(kBlock) void sample_block_sums(const float2 *__restrict__ amp, int B,
                                                             int64_t nb, double *__restrict__ sums) {
@@ -1148,8 +1155,22 @@ __global__ __launch_bounds__(kBlock) void sample_block_sums(const float2 *__rest
     const int lane = threadIdx.x & 63;
     if (blk >= nb) return;  // uniform over the wavefront
     const int len = 1 << B;
-    const int per = len >= 64 ? len / 64 : 1;
-    double x = lane < len ? chunk_weight(amp, (Idx(blk) << B) + Idx(lane * per), per) : 0.0;
+    const Idx first = Idx(blk) << B;
+    double x = 0.0;
+    if (len >= 128) {
+        const float4 *p4 = reinterpret_cast<const float4 *>(amp + first);
+#pragma unroll 8
+        for (int i = lane; i < len / 2; i += 64) {
+            const float4 v = p4[i];
+            x = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), x));
+            x = fma(double(v.z), double(v.z), fma(double(v.w), double(v.w), x));
+        }
+    } else {
+        for (int i = lane; i < len; i += 64) {
+            const float2 v = amp[first + Idx(i)];
+            x = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), x));
+        }
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
     if (lane == 0) sums[blk] = x;

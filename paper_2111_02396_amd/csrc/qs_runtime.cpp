@@ -2178,7 +2178,8 @@ struct Runner {
         const bool delayed = p.mode != QS_KRAUS_NAIVE;
         if (delayed) QS_CHECK(plan_delayed());
         else QS_CHECK(plan_naive());
-        graph_wanted = p.mode == QS_KRAUS_DELAYED && !(p.flags & QS_TRAJ_NO_GRAPH) && !tuning &&
+        graph_wanted = p.mode == QS_KRAUS_DELAYED && (p.flags & QS_TRAJ_GRAPH) &&
+                       !(p.flags & QS_TRAJ_NO_GRAPH) && !tuning &&
                        m.n <= kGraphMaxQubits && p.n_traj >= 2;
         for (int64_t rel = 0; rel < p.n_traj; ++rel) {
             const uint32_t traj = uint32_t(p.traj_offset + rel);

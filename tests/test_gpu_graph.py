@@ -1,5 +1,5 @@
-"""HIP-graph replay of the default plan (small states, delayed mode): the
-replayed trajectories match the oracle and are bit-identical to the same
+"""HIP-graph replay of the default plan (QS_TRAJ_GRAPH; small states,
+delayed mode): the replayed trajectories match the oracle and are bit-identical to the same
 trajectories launched directly, over many replays with direct trajectories
 (those that need inner products) and synchronisations in between."""
 
@@ -48,7 +48,8 @@ def test_graph_replays_against_oracle(qs, orc):
     m = orc.Marshalled(c)
     stream = torch.cuda.Stream()
     with qs.State(c.n, hip_stream=stream.cuda_stream) as st:
-        got = qs.qs_run_trajectories(st.h, c, 6, seed=5, n_samples=40, max_fuse=4, z_expect=True)
+        got = qs.qs_run_trajectories(st.h, c, 6, seed=5, n_samples=40, max_fuse=4, z_expect=True,
+                                     graph=True)
         # every trajectory ran as a replay; the state holds the last one
         assert got["graph_replays"] == 6
         last = qs.qs_copy_state_to_host(st.h)
@@ -69,11 +70,11 @@ def test_graph_call_repeated_with_eager_work_between(qs):
     c = W.grid_circuit(3, 4, 6, p_dep=0.02, seed=2)
     stream = torch.cuda.Stream()
     with qs.State(c.n, hip_stream=stream.cuda_stream) as st:
-        first = qs.qs_run_trajectories(st.h, c, 8, seed=1, n_samples=8)
+        first = qs.qs_run_trajectories(st.h, c, 8, seed=1, n_samples=8, graph=True)
         for _ in range(3):
             qs.qs_apply_fused_gate(st.h, [0, 5], W.random_unitary(2, np.random.default_rng(0)))
             qs.qs_norm(st.h)
-            again = qs.qs_run_trajectories(st.h, c, 8, seed=1, n_samples=8)
+            again = qs.qs_run_trajectories(st.h, c, 8, seed=1, n_samples=8, graph=True)
             assert again["graph_replays"] == 8
             assert np.array_equal(again["samples"], first["samples"])
             assert np.array_equal(again["choices"], first["choices"])
@@ -90,7 +91,7 @@ def test_graph_with_concurrent_states(qs):
     for _ in range(2):
         states = [qs.State(c.n, hip_stream=s.cuda_stream) for s in streams]
         try:
-            got = qs.qs_run_trajectories([st.h for st in states], c, 48, **kw)
+            got = qs.qs_run_trajectories([st.h for st in states], c, 48, graph=True, **kw)
         finally:
             for st in states:
                 st.close()
