@@ -403,23 +403,41 @@ def sub_batched(qs, W, torch, steps=2):
             "speedup_vs_one_per_call": value / per_call}
 
 
-def sub_served(qs, W, requests=40, max_qubits=24):
+def cap_large_requests(reqs):
+    """Bounded variant for the top of the request range: a request of n >= 28
+    qubits keeps at most 2^(33 - n) of its trajectories (32 q: 2, 30 q: 8,
+    28 q: 32), so a run with 30-32-qubit requests takes minutes, not hours."""
+    for r in reqs:
+        n = r.workload.circuit.n
+        if n >= 28:
+            r.workload.n_traj = max(1, min(r.workload.n_traj, 1 << (33 - n)))
+    return reqs
+
+
+def sub_served(qs, W, requests=40, max_qubits=24, cap_large=False):
     """Poisson arrivals of random grid circuits (n uniform in 10..max_qubits,
     depth 10-40, depolarizing log-uniform in [1e-4, 1e-2], 1-1000
     trajectories, one shot each), admission by 16 * 2^n bytes, ~70% load."""
     from paper_2111_02396_amd import serving
 
-    reqs = W.serving_requests(requests, 1.0, seed=1, n_hi=max_qubits)
+    def make(rate):
+        reqs = W.serving_requests(requests, rate, seed=1, n_hi=max_qubits)
+        return cap_large_requests(reqs) if cap_large else reqs
+
+    reqs = make(1.0)
     work = sum(r.workload.n_traj * 30 * 16.0 * (1 << r.workload.circuit.n) / 6e12 + 2e-4
                for r in reqs)
     rate = 0.7 * len(reqs) / work
-    reqs = W.serving_requests(requests, rate, seed=1, n_hi=max_qubits)
+    reqs = make(rate)
     srv = serving.Server()
     d = srv.run(reqs).as_dict()
     lanes = {}
     for r in reqs:
         lanes[srv.results[r.rid].lane] = lanes.get(srv.results[r.rid].lane, 0) + 1
-    return {"workload": f"{requests} Poisson requests at {rate:.2f}/s, n 10-{max_qubits}",
+    sizes = [r.workload.circuit.n for r in reqs]
+    return {"workload": f"{requests} Poisson requests at {rate:.2f}/s, n 10-{max_qubits}"
+                        + (" (n >= 28: at most 2^(33-n) trajectories)" if cap_large else ""),
+            "largest_request_qubits": max(sizes), "requests_28_or_more_qubits": sum(n >= 28 for n in sizes),
             "value": d["trajectories_per_s"], "unit": "trajectories/s", "p50_s": d["p50_s"],
             "p99_s": d["p99_s"], "requests": d["requests"], "wall_s": d["wall_s"], "lanes": lanes,
             "errors": sum(1 for r in reqs if srv.results[r.rid].error)}
@@ -460,6 +478,9 @@ def main() -> int:
                          "copy: a plain device copy, the reference for calibrating byte counters")
     ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
     ap.add_argument("--max-qubits", type=int, default=26, help="serving: largest request")
+    ap.add_argument("--cap-large", type=int, default=0,
+                    help="serving: 1 = requests of 28 or more qubits keep at most 2^(33-n) "
+                         "trajectories (a bounded run at the top of the range)")
     ap.add_argument("--copy-qubits", type=int, default=24, help="copy: state size")
     args = ap.parse_args()
 
@@ -531,11 +552,14 @@ def main() -> int:
 
     extras = {}
     if args.extras and (args.rows, args.cols) == (4, 6):
-        log("autotune: fixed widths 4/13 for comparison")
-        extras["fixed_widths_4_13"] = {
-            k: v for k, v in run_grid(qs, W, args, torch, n_traj=500, steps=1, warmup=1,
-                                      streams=args.streams, max_fuse=4, tile_bits=13).items()
-            if k in ("value", "unit", "max_fuse", "tile_bits", "gate_sweeps_per_traj")}
+        log("autotune: fixed widths 4/13, 5/13 and 4/14 for comparison")
+        for f, tb in ((4, 13), (5, 13), (4, 14)):
+            r = run_grid(qs, W, args, torch, n_traj=500, steps=1, warmup=1, streams=args.streams,
+                         max_fuse=f, tile_bits=tb)
+            extras[f"fixed_widths_{f}_{tb}"] = {
+                k: v for k, v in r.items()
+                if k in ("value", "unit", "max_fuse", "tile_bits", "gate_sweeps_per_traj")}
+            extras[f"fixed_widths_{f}_{tb}"]["avg_launch_us"] = r["sweep"]["avg_launch_us"]
         extras["depolarizing_strength"] = []
         for p in (1e-4, 1e-2):
             log(f"p = {p:g}")
@@ -694,7 +718,8 @@ def other_workload(args, qs, W, torch) -> int:
                "value": r["value"], "unit": r["unit"], "ms_per_step": 4096e3 / r["value"],
                "config": {"workload": r["workload"]}, **{k: v for k, v in r.items() if k != "value"}}
     elif args.workload == "serving":
-        r = sub_served(qs, W, requests=args.requests, max_qubits=args.max_qubits)
+        r = sub_served(qs, W, requests=args.requests, max_qubits=args.max_qubits,
+                       cap_large=bool(args.cap_large))
         out = {"metric": "served trajectories/s; p50/p99 request latency", **common,
                "value": r["value"], "unit": r["unit"], "ms_per_step": 1e3 * r["wall_s"],
                "config": {"workload": r["workload"]}, **{k: v for k, v in r.items() if k != "value"}}

@@ -1115,13 +1115,19 @@ uint64_t circuit_hash(const qs_circuit *c) {
 struct ModelEntry {
     uint64_t id = 0;
     uint64_t hash = 0;
+    size_t bytes = 0;  // estimate of the host memory held
     int n = 0;
     std::vector<qs_op> ops;
     std::vector<double> pool;
     CircuitModel model;
 };
 
-constexpr size_t kModelCacheEntries = 64;
+// Bounded by count and by an estimate of the host memory an entry holds
+// (a batch of a few hundred distinct circuits must fit, or every call would
+// rebuild every model and miss every plan keyed by it).
+constexpr size_t kModelCacheEntries = 4096;
+constexpr size_t kModelCacheBytes = size_t(512) << 20;
+size_t g_model_bytes = 0;
 std::mutex g_model_mu;
 std::multimap<uint64_t, std::shared_ptr<const ModelEntry>> g_model_cache;
 std::deque<std::shared_ptr<const ModelEntry>> g_model_fifo;
@@ -1165,18 +1171,26 @@ qs_status circuit_model(const qs_circuit *c, std::shared_ptr<const ModelEntry> *
             return QS_OK;
         }
     e->id = g_model_next_id++;
-    if (g_model_fifo.size() >= kModelCacheEntries) {
-        const auto &old = g_model_fifo.front();
+    e->bytes = sizeof(ModelEntry) + sizeof(qs_op) * e->ops.size() + sizeof(double) * e->pool.size() +
+               (sizeof(qs::PlanOp) + 2 * sizeof(int) + sizeof(void *) + sizeof(double)) * e->model.ops.size();
+    for (const ChannelInfo &ci : e->model.channels)
+        e->bytes += sizeof(ChannelInfo) + sizeof(cd) * (ci.unit.size() + ci.excess_sorted.size()) +
+                    (2 * sizeof(double) + 1) * ci.pbar.size();
+    while (!g_model_fifo.empty() && (g_model_fifo.size() >= kModelCacheEntries ||
+                                     g_model_bytes + e->bytes > kModelCacheBytes)) {
+        const auto old = g_model_fifo.front();
         auto r = g_model_cache.equal_range(old->hash);
         for (auto it = r.first; it != r.second; ++it)
             if (it->second == old) {
                 g_model_cache.erase(it);
                 break;
             }
+        g_model_bytes -= old->bytes;
         g_model_fifo.pop_front();
     }
     g_model_cache.emplace(h, e);
     g_model_fifo.push_back(e);
+    g_model_bytes += e->bytes;
     *out = std::move(e);
     return QS_OK;
 }
