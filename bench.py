@@ -518,9 +518,11 @@ def main() -> int:
         "achieved": sw["hbm"]["achieved"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
         "frac": sw["hbm"]["frac"],
         "traffic": (traffic / 1e9) if traffic else None,
-        "traffic_unit": ("GB per launch: rocprofv3 TCC_EA0 read and write request counters x "
-                         "request size, profiles/apply_tile_grid24_counters.md (null unless that "
-                         "summary matches the built kernel source and the run's tile width)"),
+        "traffic_unit": ("GB per launch of apply_tile<13>: rocprofv3 FETCH_SIZE x 2.000 + "
+                         "WRITE_SIZE x 1.000 (factors from a plain 2 GiB copy), "
+                         "profiles/apply_tile_grid24_counters.md, which also gives the raw "
+                         "TCC_EA0 request-counter bytes (null unless that summary matches the "
+                         "built kernel source and the run's tile width)"),
         "counter_summaries": ["profiles/apply_tile_grid24_counters.md",
                               "profiles/apply_tile_grid24_pmc.md",
                               "profiles/apply_tile_grid28_counters.md"],
