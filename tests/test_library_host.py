@@ -216,3 +216,28 @@ def test_batched_planning_without_trajectories(lib):
     with pytest.raises(lib.QsError) as e:
         lib.qs_run_batched(pb, max_fuse=3)
     assert e.value.code == lib.QS_ERR_INVALID_ARGUMENT
+
+
+def test_batched_planning_from_concurrent_threads(lib):
+    """Several host threads plan batches at once (no trajectories, so no
+    device work): the circuit-model cache, the batched plan cache and the
+    planner's worker pool are shared, and every call must still succeed
+    with the same counts."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    circuits = [W.generic_grid_circuit(n, 6, p_dep=0.01, seed=s) for s, n in enumerate(range(10, 16))]
+
+    def plan(seed):
+        rng = np.random.default_rng(seed)
+        picks = rng.permutation(len(circuits))[:4]
+        items = [W.TrajectoryWorkload(f"c{i}", circuits[i], n_traj=0, n_samples=2, circuit_id=int(i))
+                 for i in picks]
+        out = []
+        for _ in range(5):
+            _, stats = lib.qs_run_batched(items, max_fuse=3)
+            out.append(stats["jobs"])
+        return out
+
+    with ThreadPoolExecutor(max_workers=6) as ex:
+        results = list(ex.map(plan, range(12)))
+    assert all(r == [0] * 5 for r in results)
