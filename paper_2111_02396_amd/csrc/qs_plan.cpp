@@ -441,6 +441,102 @@ std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, 
     return out;
 }
 
+std::vector<Sweep> group_sweeps_best(int n_qubits, const std::vector<Block> &blocks, int max_bits,
+                                     int low_bits, int max_blocks, int mat_budget,
+                                     const int *slot_per_k, int restarts, uint64_t seed) {
+    std::vector<Sweep> best = group_sweeps(n_qubits, blocks, max_bits, low_bits, max_blocks,
+                                           mat_budget, slot_per_k, true);
+    if (restarts <= 0 || best.size() <= 1) return best;
+    for (const auto &sw : best)
+        if (int(sw.bits.size()) > max_bits) return best;  // a block that fits no tile: keep as is
+    const int nb = int(blocks.size());
+    std::vector<int> last(n_qubits, -1), npred0(nb, 0);
+    std::vector<std::vector<int>> succ(nb);
+    for (int b = 0; b < nb; ++b)
+        for (int i = 0; i < blocks[b].k; ++i) {
+            const int q = blocks[b].q[i], p = last[q];
+            if (p >= 0 && (succ[p].empty() || succ[p].back() != b)) {
+                succ[p].push_back(b);
+                ++npred0[b];
+            }
+            last[q] = b;
+        }
+    const int low = std::min(low_bits, n_qubits);
+    uint64_t state = seed;
+    auto draw = [&state](size_t m) {  // splitmix64, reduced to [0, m)
+        uint64_t z = (state += 0x9e3779b97f4a7c15ull);
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return size_t((z ^ (z >> 31)) % m);
+    };
+    std::vector<int> npred, ready, cands;
+    std::vector<char> in(n_qubits, 0);
+    for (int r = 0; r < restarts; ++r) {
+        npred = npred0;
+        ready.clear();
+        for (int b = 0; b < nb; ++b)
+            if (npred[b] == 0) ready.push_back(b);
+        std::vector<Sweep> cur;
+        int done = 0;
+        bool ok = true;
+        while (done < nb) {
+            if (cur.size() + 1 >= best.size()) {  // cannot end with fewer sweeps
+                ok = false;
+                break;
+            }
+            std::fill(in.begin(), in.end(), 0);
+            int nbits = 0, mats = 0;
+            for (int q = 0; q < low; ++q) {
+                in[q] = 1;
+                ++nbits;
+            }
+            Sweep sw;
+            for (;;) {
+                if (int(sw.blocks.size()) >= max_blocks) break;
+                // the sweep's first block: any ready block that fits; later
+                // ones: the least qubit growth, ties drawn at random
+                cands.clear();
+                int least = 1 << 30;
+                for (int i = 0; i < int(ready.size()); ++i) {
+                    const Block &B = blocks[ready[i]];
+                    int g = 0;
+                    for (int j = 0; j < B.k; ++j) g += in[B.q[j]] ? 0 : 1;
+                    if (nbits + g > max_bits || mats + slot_per_k[B.k] > mat_budget) continue;
+                    const int key = sw.blocks.empty() ? 0 : g;
+                    if (key < least) {
+                        least = key;
+                        cands.clear();
+                    }
+                    if (key == least) cands.push_back(i);
+                }
+                if (cands.empty()) break;
+                const int pos = cands[draw(cands.size())];
+                const int b = ready[pos];
+                ready.erase(ready.begin() + pos);
+                sw.blocks.push_back(b);
+                ++done;
+                mats += slot_per_k[blocks[b].k];
+                for (int j = 0; j < blocks[b].k; ++j)
+                    if (!in[blocks[b].q[j]]) {
+                        in[blocks[b].q[j]] = 1;
+                        ++nbits;
+                    }
+                for (int s2 : succ[b])
+                    if (--npred[s2] == 0) ready.push_back(s2);
+            }
+            if (sw.blocks.empty()) {
+                ok = false;
+                break;
+            }
+            for (int q = 0; q < n_qubits; ++q)
+                if (in[q]) sw.bits.push_back(q);
+            cur.push_back(std::move(sw));
+        }
+        if (ok && cur.size() < best.size()) best = std::move(cur);
+    }
+    return best;
+}
+
 double block_cost(int k) {
     // relative cost of one block applied to a tile in LDS by width: µs per
     // 2^24 amplitudes, measured on gfx950 with 13-bit tiles (barrier and read

@@ -99,4 +99,14 @@ std::vector<Sweep> group_sweeps(int n_qubits, const std::vector<Block> &blocks, 
                                 int low_bits, int max_blocks, int mat_budget,
                                 const int *slot_per_k, bool search = true);
 
+// The grouping with the fewest sweeps among group_sweeps' and `restarts`
+// randomized fills: each sweep starts from a ready block drawn among those
+// that fit and then adds the ready block of least qubit growth, ties drawn
+// at random (a counter-based generator seeded with `seed`, so the result is
+// reproducible).  A fill is abandoned once it cannot end with fewer sweeps
+// than the best so far.
+std::vector<Sweep> group_sweeps_best(int n_qubits, const std::vector<Block> &blocks, int max_bits,
+                                     int low_bits, int max_blocks, int mat_budget,
+                                     const int *slot_per_k, int restarts, uint64_t seed);
+
 }  // namespace qs

@@ -1195,6 +1195,46 @@ qs_status circuit_model(const qs_circuit *c, std::shared_ptr<const ModelEntry> *
     return QS_OK;
 }
 
+// ---- sweep grouping effort and the per-segment cache
+// A call's default plan is cached, so its grouping is searched the harder the
+// larger the state (every sweep saved is one read and one write of it).  A
+// trajectory whose channels need inner products regroups the blocks of each
+// segment between such channels; those groupings are cached per segment.
+int plan_restarts(int n) { return n >= 24 ? 4096 : n >= 20 ? 512 : n >= 16 ? 64 : 16; }
+int segment_restarts(int n) { return n >= 24 ? 64 : n >= 20 ? 16 : 4; }
+constexpr uint64_t kGroupSeed = 0x243f6a8885a308d3ull;
+
+struct SegKey {
+    uint64_t model;  // model id
+    int mode, f, tb, start, end;
+    bool operator<(const SegKey &o) const {
+        return std::tie(model, mode, f, tb, start, end) < std::tie(o.model, o.mode, o.f, o.tb, o.start, o.end);
+    }
+};
+constexpr size_t kSegmentCacheEntries = 16384;
+std::mutex g_seg_mu;
+std::map<SegKey, std::vector<qs::Sweep>> g_seg_cache;
+std::deque<SegKey> g_seg_fifo;
+
+bool segment_lookup(const SegKey &k, std::vector<qs::Sweep> *out) {
+    std::lock_guard<std::mutex> lock(g_seg_mu);
+    auto it = g_seg_cache.find(k);
+    if (it == g_seg_cache.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void segment_insert(const SegKey &k, const std::vector<qs::Sweep> &sw) {
+    std::lock_guard<std::mutex> lock(g_seg_mu);
+    if (g_seg_cache.count(k)) return;
+    if (g_seg_fifo.size() >= kSegmentCacheEntries) {
+        g_seg_cache.erase(g_seg_fifo.front());
+        g_seg_fifo.pop_front();
+    }
+    g_seg_cache.emplace(k, sw);
+    g_seg_fifo.push_back(k);
+}
+
 struct Runner {
     qs_state s;
     const CircuitModel &m;
@@ -1487,8 +1527,9 @@ struct Runner {
         const int T = p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits;
         sweeps.clear();
         if (T >= 10 && m.n >= qs::kTileMinQubits) {
-            sweeps = qs::group_sweeps(m.n, blocks, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates,
-                                      qs::tile_mat_budget(std::min(T, m.n)), tile_slots());
+            sweeps = qs::group_sweeps_best(m.n, blocks, std::min(T, m.n), qs::kTileLowBits,
+                                           qs::kMaxTileGates, qs::tile_mat_budget(std::min(T, m.n)),
+                                           tile_slots(), plan_restarts(m.n), kGroupSeed);
         } else {
             for (size_t b = 0; b < blocks.size(); ++b) {
                 qs::Sweep sw;
@@ -1579,10 +1620,13 @@ struct Runner {
         }
         const int T = p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits;
         std::vector<qs::Sweep> sw;
-        if (T >= 10 && m.n >= qs::kTileMinQubits) {
-            sw = qs::group_sweeps(m.n, rb, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates,
-                                  qs::tile_mat_budget(std::min(T, m.n)),
-                                  tile_slots(), true);
+        const SegKey skey{chash, p.mode, max_fuse, T, seg_start, seg_end};
+        if (chash && segment_lookup(skey, &sw)) {
+        } else if (T >= 10 && m.n >= qs::kTileMinQubits) {
+            sw = qs::group_sweeps_best(m.n, rb, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates,
+                                       qs::tile_mat_budget(std::min(T, m.n)), tile_slots(),
+                                       segment_restarts(m.n), kGroupSeed);
+            if (chash) segment_insert(skey, sw);
         } else {
             for (size_t b = 0; b < rb.size(); ++b) {
                 qs::Sweep one;
@@ -2573,9 +2617,9 @@ qs_status qs_sweep_plan(const qs_circuit *c, int max_fuse, int tile_bits, int32_
     const int T = tile_bits == 0 ? qs::kDefaultTileBits : tile_bits;
     std::vector<qs::Sweep> sw;
     if (T >= 10 && m.n >= qs::kTileMinQubits) {
-        sw = qs::group_sweeps(m.n, blocks, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates,
-                              qs::tile_mat_budget(std::min(T, m.n)),
-                              tile_slots());
+        sw = qs::group_sweeps_best(m.n, blocks, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates,
+                                   qs::tile_mat_budget(std::min(T, m.n)), tile_slots(),
+                                   plan_restarts(m.n), kGroupSeed);
     } else {
         for (size_t b = 0; b < blocks.size(); ++b) {
             qs::Sweep one;
@@ -2924,7 +2968,8 @@ qs_status plan_batched_circuit(const CircuitModel &m, const std::vector<const cd
         sw.push_back(std::move(one));
     } else {
         static const int no_budget[6] = {0, 0, 0, 0, 0, 0};
-        sw = qs::group_sweeps(n, e.blocks, qs::kBatchTileBits, 6, 1 << 30, 1 << 30, no_budget);
+        sw = qs::group_sweeps_best(n, e.blocks, qs::kBatchTileBits, 6, 1 << 30, 1 << 30, no_budget,
+                                   plan_restarts(n), kGroupSeed);
     }
     e.gate_of_block.assign(e.blocks.size(), -1);
     std::vector<cd> tmp(1024);
