@@ -1196,11 +1196,19 @@ qs_status circuit_model(const qs_circuit *c, std::shared_ptr<const ModelEntry> *
 }
 
 // ---- sweep grouping effort and the per-segment cache
-// A call's default plan is cached, so its grouping is searched the harder the
-// larger the state (every sweep saved is one read and one write of it).  A
-// trajectory whose channels need inner products regroups the blocks of each
-// segment between such channels; those groupings are cached per segment.
-int plan_restarts(int n) { return n >= 24 ? 4096 : n >= 20 ? 512 : n >= 16 ? 64 : 16; }
+// Every sweep saved is one read and one write of the state per trajectory, so
+// the default plan's grouping is searched in proportion to the sweep work of
+// the call that plans it (n_traj states of 2^n amplitudes; about 40 ms for
+// 4096 restarts on a 24-qubit plan), and always hard from 26 qubits on, where
+// one trajectory's sweeps take tens of milliseconds.  The plan is cached, so
+// later calls on the same circuit reuse it.  A trajectory whose channels need
+// inner products regroups the blocks of each segment between such channels;
+// those groupings are cached per segment.
+int plan_restarts(int n, int64_t n_traj) {
+    if (n >= 26) return 4096;
+    const double w = std::ldexp(double(std::max<int64_t>(n_traj, 1)), n - 20);
+    return int(std::min(4096.0, std::max(64.0, w)));
+}
 int segment_restarts(int n) { return n >= 24 ? 64 : n >= 20 ? 16 : 4; }
 constexpr uint64_t kGroupSeed = 0x243f6a8885a308d3ull;
 
@@ -1529,7 +1537,7 @@ struct Runner {
         if (T >= 10 && m.n >= qs::kTileMinQubits) {
             sweeps = qs::group_sweeps_best(m.n, blocks, std::min(T, m.n), qs::kTileLowBits,
                                            qs::kMaxTileGates, qs::tile_mat_budget(std::min(T, m.n)),
-                                           tile_slots(), plan_restarts(m.n), kGroupSeed);
+                                           tile_slots(), plan_restarts(m.n, p.n_traj), kGroupSeed);
         } else {
             for (size_t b = 0; b < blocks.size(); ++b) {
                 qs::Sweep sw;
@@ -2619,7 +2627,7 @@ qs_status qs_sweep_plan(const qs_circuit *c, int max_fuse, int tile_bits, int32_
     if (T >= 10 && m.n >= qs::kTileMinQubits) {
         sw = qs::group_sweeps_best(m.n, blocks, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates,
                                    qs::tile_mat_budget(std::min(T, m.n)), tile_slots(),
-                                   plan_restarts(m.n), kGroupSeed);
+                                   plan_restarts(m.n, 1 << 20), kGroupSeed);
     } else {
         for (size_t b = 0; b < blocks.size(); ++b) {
             qs::Sweep one;
@@ -2958,7 +2966,7 @@ qs_status device_draws(const qs_batch_item *items, int n_items, const std::vecto
 // Fusion, sweep grouping and default block matrices of one circuit for the
 // batched launch (every channel at its most likely pick).
 qs_status plan_batched_circuit(const CircuitModel &m, const std::vector<const cd *> &default_mats,
-                               int f, bool resident, BatchPlanEntry &e) {
+                               int f, bool resident, int64_t n_traj, BatchPlanEntry &e) {
     const int n = m.n;
     e.blocks = qs::fuse_greedy(n, m.ops, f, &e.op_block);
     std::vector<qs::Sweep> sw;
@@ -2969,7 +2977,7 @@ qs_status plan_batched_circuit(const CircuitModel &m, const std::vector<const cd
     } else {
         static const int no_budget[6] = {0, 0, 0, 0, 0, 0};
         sw = qs::group_sweeps_best(n, e.blocks, qs::kBatchTileBits, 6, 1 << 30, 1 << 30, no_budget,
-                                   plan_restarts(n), kGroupSeed);
+                                   plan_restarts(n, n_traj), kGroupSeed);
     }
     e.gate_of_block.assign(e.blocks.size(), -1);
     std::vector<cd> tmp(1024);
@@ -3108,7 +3116,7 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
         batch_plan_lookup(bkey, &hit);
         if (!hit) {
             auto e = std::make_shared<BatchPlanEntry>();
-            const qs_status ps = plan_batched_circuit(*P.m, P.default_mats, f, P.resident, *e);
+            const qs_status ps = plan_batched_circuit(*P.m, P.default_mats, f, P.resident, I.n_traj, *e);
             if (ps != QS_OK) {
                 X.status = ps;
                 X.error = g_last_error;
