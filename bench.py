@@ -468,7 +468,7 @@ def main() -> int:
     ap.add_argument("--cpu-cycles", type=int, default=1,
                     help="cycles of each oracle trajectory timed for the CPU baseline (0 = skip)")
     ap.add_argument("--cpu-workers", type=int, default=16,
-                    help="oracle processes at once for the all-core CPU baseline")
+                    help="oracle trajectories run at once (one host thread each) for the all-core CPU baseline")
     ap.add_argument("--extras", type=int, default=1,
                     help="1: add the bounded sub-records for the other workloads")
     ap.add_argument("--workload", default="grid24",
