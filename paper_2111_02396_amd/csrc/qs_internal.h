@@ -82,6 +82,14 @@ struct TileArgs {
     int n_gates;
     int mat_total;
     int init_zero;  // 1: start from |0...0> written in LDS instead of reading the state
+    // With rdm_out set, the launch also forms the reduced density matrix of
+    // the qubit at tile-local bit rdm_lt on the state it leaves (Section 3.5's
+    // inner products, from the tile in LDS after its gates): one record of
+    // 8 doubles per workgroup, R[j][l] = sum v_j conj(v_l) as re, im in row
+    // order, to be summed over the launch's workgroups.  Not with 5-qubit
+    // blocks.
+    int rdm_lt;
+    double *rdm_out;
     TileGate g[kMaxTileGates];
 };
 
@@ -195,11 +203,17 @@ hipError_t launch_apply_gate(float2 *amp, int n, const GateDesc &g, const float2
                              hipStream_t st);
 
 // Several gates in one sweep: every gate's targets are bits of the tile.
-hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t st);
+// grid_out (optional): the launch's workgroup count (its RDM record count).
+hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t st,
+                             int *grid_out = nullptr);
 // Validates a and sets up its kernel instantiation without enqueueing
 // anything (before a launch under stream capture).
 hipError_t prepare_apply_tile(int n, const TileArgs &a);
-hipError_t launch_apply_tile_impl(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch);
+hipError_t launch_apply_tile_impl(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch,
+                                  int *grid_out = nullptr);
+// Sums `count` records of `width` doubles in index order into out_dev.
+hipError_t launch_reduce_records(const double *partials, int count, int width, double *out_dev,
+                                 hipStream_t st);
 
 // FP64 reductions with a fixed tree.  Each writes `width` doubles to out_dev.
 // norm: width 1 (sum |psi|^2).

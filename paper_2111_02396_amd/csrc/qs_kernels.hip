@@ -13,6 +13,7 @@
 //    work-item per sample with Philox draws.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <mutex>
 
 #include "qs_internal.h"
@@ -555,7 +556,9 @@ __device__ __forceinline__ void tile_gate_mfma5(float2 *__restrict__ sd, const f
 // VGPRs, so launches without one use a leaner instantiation).  5-qubit blocks
 // run on MFMA when every wavefront gets a batch of 16 groups (TB >= 9 +
 // log2(NT / 64)), else on VALU from the plain matrix.
-template <int TB, typename Idx, bool K5, int NT>
+// RK: the launch also accumulates the reduced density matrix of one tile
+// qubit (TileArgs::rdm_out) from every tile after its gates.
+template <int TB, typename Idx, bool K5, int NT, bool RK>
 __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n_tiles,
                                                  TileArgs a) {
     constexpr int NB = ilog2(NT);
@@ -641,6 +644,10 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
     const int tid_l = SwizzledTile::map(int(threadIdx.x) << 1);
     float4 o[R];
     Idx prev_base = 0;
+    // RDM of the qubit at tile bit rdm_lt: R00, R11 and R01 = sum v0 conj(v1)
+    // over every pair of the work-item's amplitudes that differ in that bit,
+    // in a fixed order, summed over the workgroup's tiles.
+    double r00 = 0.0, r11 = 0.0, r01r = 0.0, r01i = 0.0;
     auto run_tile = [&](Idx t, bool has_prev) {
         __syncthreads();  // the previous tile is out of LDS; matrices staged
         const Idx base = tile_base(t);
@@ -698,12 +705,78 @@ __global__ __launch_bounds__(NT) void apply_tile(float2 *__restrict__ amp, Idx n
             const float2 lo = sd[tid_l + (r << (NB + 1))], hi = sd[(tid_l ^ 1) + (r << (NB + 1))];
             o[r] = make_float4(lo.x, lo.y, hi.x, hi.y);
         }
+        if constexpr (RK) {
+            // the work-item's amplitudes are local indices 2 tid + e + 2 NT r,
+            // read again from LDS (a rolled loop keeps the registers of the
+            // common sweep); the partner across the qubit's bit pc sits at
+            // LDS index ^ map(2^pc)
+            const int pc = a.rdm_lt;
+            const int pm = SwizzledTile::map(1 << pc);
+            const int tid_bit = pc >= 1 && pc <= NB ? (int(threadIdx.x) >> (pc - 1)) & 1 : 0;
+#pragma unroll 1
+            for (int i = 0; i < 2 * R; ++i) {
+                const int r = i >> 1, e = i & 1;
+                const int bit = pc == 0 ? e : (pc <= NB ? tid_bit : (r >> (pc - NB - 1)) & 1);
+                const int at = (tid_l ^ e) + (r << (NB + 1));
+                const float2 v = sd[at];
+                const double vr = v.x, vi = v.y;
+                if (bit) {
+                    r11 = fma(vr, vr, fma(vi, vi, r11));
+                } else {
+                    r00 = fma(vr, vr, fma(vi, vi, r00));
+                    const float2 u = sd[at ^ pm];
+                    const double ur = u.x, ui = u.y;
+                    r01r = fma(vr, ur, fma(vi, ui, r01r));
+                    r01i = fma(vi, ur, fma(-vr, ui, r01i));
+                }
+            }
+        }
         prev_base = base;
     };
     run_tile(tile, false);
     for (tile += gridDim.x; tile < n_tiles; tile += gridDim.x) run_tile(tile, true);
 #pragma unroll
     for (int r = 0; r < R; ++r) *reinterpret_cast<float4 *>(amp + prev_base + off_r[r]) = o[r];
+    if constexpr (RK) {
+        // wavefront sums by a fixed shuffle tree, then the wavefronts in order
+        // through LDS (the tile is no longer needed once every wavefront has
+        // read its last tile out)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            r00 += __shfl_xor(r00, off, 64);
+            r11 += __shfl_xor(r11, off, 64);
+            r01r += __shfl_xor(r01r, off, 64);
+            r01i += __shfl_xor(r01i, off, 64);
+        }
+        __syncthreads();
+        double *red = reinterpret_cast<double *>(sd);
+        const int wave = int(threadIdx.x) >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            red[4 * wave] = r00;
+            red[4 * wave + 1] = r11;
+            red[4 * wave + 2] = r01r;
+            red[4 * wave + 3] = r01i;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s00 = 0.0, s11 = 0.0, sr = 0.0, si = 0.0;
+            for (int w = 0; w < NT / 64; ++w) {
+                s00 += red[4 * w];
+                s11 += red[4 * w + 1];
+                sr += red[4 * w + 2];
+                si += red[4 * w + 3];
+            }
+            double *rec = a.rdm_out + size_t(blockIdx.x) * 8;
+            rec[0] = s00;
+            rec[1] = 0.0;
+            rec[2] = sr;
+            rec[3] = si;
+            rec[4] = sr;
+            rec[5] = -si;
+            rec[6] = s11;
+            rec[7] = 0.0;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- branch selection
@@ -1463,10 +1536,10 @@ int device_cus() {
 // Once per instantiation, thread-safely: allow the matrix region, and read
 // how many workgroups per CU registers and waves allow (with no matrices the
 // LDS is not what limits the count); a negative value is an error.
-template <int TB, typename Idx, bool K5, int NT>
+template <int TB, typename Idx, bool K5, int NT, bool RK>
 int tile_reg_limit() {
     static const int reg_limit = [] {
-        const void *fn = reinterpret_cast<const void *>(&apply_tile<TB, Idx, K5, NT>);
+        const void *fn = reinterpret_cast<const void *>(&apply_tile<TB, Idx, K5, NT, RK>);
         if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 int(sizeof(float2) * kTileMatBudget)) != hipSuccess)
             return -1;
@@ -1479,12 +1552,13 @@ int tile_reg_limit() {
 
 // launch = false only sets the instantiation up (no stream work), so that a
 // later launch under stream capture makes no attribute or occupancy calls.
-template <int TB, typename Idx, bool K5, int NT>
-hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch) {
+template <int TB, typename Idx, bool K5, int NT, bool RK>
+hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch,
+                       int *grid_out) {
     // static tile + dynamic matrices
     const size_t dyn = sizeof(float2) * size_t(a.mat_total);
     const size_t lds = sizeof(float2) * (size_t(1) << TB) + dyn;
-    const int reg_limit = tile_reg_limit<TB, Idx, K5, NT>();
+    const int reg_limit = tile_reg_limit<TB, Idx, K5, NT, RK>();
     if (reg_limit < 0) return hipErrorInvalidDeviceFunction;
     const int cus = device_cus();
     if (!launch) return hipSuccess;
@@ -1495,12 +1569,15 @@ hipError_t tile_launch(float2 *amp, int n, const TileArgs &a, hipStream_t st, bo
     if (per_cu > reg_limit) per_cu = reg_limit;
     uint64_t grid = uint64_t(cus) * uint64_t(per_cu);
     if (grid > uint64_t(n_tiles)) grid = uint64_t(n_tiles);
-    apply_tile<TB, Idx, K5, NT><<<unsigned(grid), NT, dyn, st>>>(amp, n_tiles, a);
+    if (RK && grid > uint64_t(kMaxReduceBlocks)) return hipErrorInvalidValue;  // record space
+    if (grid_out) *grid_out = int(grid);
+    apply_tile<TB, Idx, K5, NT, RK><<<unsigned(grid), NT, dyn, st>>>(amp, n_tiles, a);
     return hipGetLastError();
 }
 
 template <int TB, typename Idx>
-hipError_t tile_launch_k(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch) {
+hipError_t tile_launch_k(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch,
+                         int *grid_out) {
     bool k5 = false;
     for (int gi = 0; gi < a.n_gates; ++gi) k5 |= a.g[gi].k == 5;
     // Four wavefronts per SIMD hide the LDS and MFMA latency: a 2^14-amplitude
@@ -1509,18 +1586,23 @@ hipError_t tile_launch_k(float2 *amp, int n, const TileArgs &a, hipStream_t st, 
     // more workgroups and do better with 256 (measured on the 24-qubit noisy
     // grid).
     constexpr int NT = TB >= 14 ? 1024 : (TB >= 13 ? 512 : kBlock);
-    return k5 ? tile_launch<TB, Idx, true, NT>(amp, n, a, st, launch)
-              : tile_launch<TB, Idx, false, NT>(amp, n, a, st, launch);
+    if (a.rdm_out) {
+        if (k5) return hipErrorInvalidValue;
+        return tile_launch<TB, Idx, false, NT, true>(amp, n, a, st, launch, grid_out);
+    }
+    return k5 ? tile_launch<TB, Idx, true, NT, false>(amp, n, a, st, launch, grid_out)
+              : tile_launch<TB, Idx, false, NT, false>(amp, n, a, st, launch, grid_out);
 }
 
 template <typename Idx>
-hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch) {
+hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch,
+                          int *grid_out) {
     switch (a.tb) {
-        case 10: return tile_launch_k<10, Idx>(amp, n, a, st, launch);
-        case 11: return tile_launch_k<11, Idx>(amp, n, a, st, launch);
-        case 12: return tile_launch_k<12, Idx>(amp, n, a, st, launch);
-        case 13: return tile_launch_k<13, Idx>(amp, n, a, st, launch);
-        case 14: return tile_launch_k<14, Idx>(amp, n, a, st, launch);
+        case 10: return tile_launch_k<10, Idx>(amp, n, a, st, launch, grid_out);
+        case 11: return tile_launch_k<11, Idx>(amp, n, a, st, launch, grid_out);
+        case 12: return tile_launch_k<12, Idx>(amp, n, a, st, launch, grid_out);
+        case 13: return tile_launch_k<13, Idx>(amp, n, a, st, launch, grid_out);
+        case 14: return tile_launch_k<14, Idx>(amp, n, a, st, launch, grid_out);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1658,6 +1740,7 @@ bool tile_for_gate(int n, const GateDesc &g, TileArgs &a) {
 hipError_t launch_apply_gate(float2 *amp, int n, const GateDesc &g, const float2 *mat_dev,
                              hipStream_t st) {
     TileArgs a;
+    std::memset(&a, 0, sizeof(a));
     if (tile_for_gate(n, g, a)) {
         a.g[0].mat = mat_dev;
         return launch_apply_tile(amp, n, a, st);
@@ -1666,18 +1749,20 @@ hipError_t launch_apply_gate(float2 *amp, int n, const GateDesc &g, const float2
     return apply_direct_idx<uint64_t>(amp, n, g, mat_dev, st);
 }
 
-hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t st) {
-    return launch_apply_tile_impl(amp, n, a, st, true);
+hipError_t launch_apply_tile(float2 *amp, int n, const TileArgs &a, hipStream_t st, int *grid_out) {
+    return launch_apply_tile_impl(amp, n, a, st, true, grid_out);
 }
 
 hipError_t prepare_apply_tile(int n, const TileArgs &a) {
     return launch_apply_tile_impl(nullptr, n, a, nullptr, false);
 }
 
-hipError_t launch_apply_tile_impl(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch) {
+hipError_t launch_apply_tile_impl(float2 *amp, int n, const TileArgs &a, hipStream_t st, bool launch,
+                                  int *grid_out) {
     if (a.tb < 10 || a.tb > kMaxTileBits || a.tb > n || a.n_gates < 0 ||
         a.n_gates > kMaxTileGates || a.mat_total < 0 || a.mat_total > kTileMatBudget)
         return hipErrorInvalidValue;
+    if (a.rdm_out && (a.rdm_lt < 0 || a.rdm_lt >= a.tb)) return hipErrorInvalidValue;
     // tile bits: ascending global positions below n, the first kTileLowBits
     // of them bits 0.. (the pair loads need local bit 0 = global bit 0)
     for (int b = 0; b < a.tb; ++b)
@@ -1705,8 +1790,16 @@ hipError_t launch_apply_tile_impl(float2 *amp, int n, const TileArgs &a, hipStre
             default: gate_tables<5, SwizzledTile>(g.lt, g.tab); break;
         }
     }
-    if (n <= 31) return apply_tile_idx<uint32_t>(amp, n, b, st, launch);
-    return apply_tile_idx<uint64_t>(amp, n, b, st, launch);
+    if (n <= 31) return apply_tile_idx<uint32_t>(amp, n, b, st, launch, grid_out);
+    return apply_tile_idx<uint64_t>(amp, n, b, st, launch, grid_out);
+}
+
+hipError_t launch_reduce_records(const double *partials, int count, int width, double *out_dev,
+                                 hipStream_t st) {
+    if (count < 1 || count > kMaxReduceBlocks || width < 1 || width > kMaxReduceWidth)
+        return hipErrorInvalidValue;
+    reduce_records<<<1, kBlock, 0, st>>>(partials, count, width, out_dev);
+    return hipGetLastError();
 }
 
 hipError_t launch_norm(const float2 *amp, int n, double *partials, double *out_dev,

@@ -38,6 +38,9 @@ qs_status fail(qs_status st, const std::string &msg) {
 constexpr int kDefaultFuse = 4;
 constexpr size_t kArenaHalf = size_t(1) << 18;  // float2 per half of the staging ring (2 MiB)
 constexpr double kRenormLogThreshold = -46.0;  // ~1e-20 on the norm squared
+// Where a sweep that forms a reduced density matrix writes its workgroup
+// records in the state's reduction buffer (past the norm pass's records).
+constexpr size_t kRdmRecordOffset = size_t(qs::kMaxReduceBlocks);
 
 struct PendingOp {
     int k;
@@ -1269,7 +1272,9 @@ struct Runner {
     struct Unit {
         const TileLayout *L;
         std::vector<const BlockDesc *> items;
+        int rdm_q = -1;  // >= 0: the sweep also forms the reduced density matrix of this qubit
     };
+    int rdm_records = 0;  // workgroup records the last such sweep wrote
     // one sweep of a segment: its layout and (block, op range) members in order
     struct SegSweep {
         const TileLayout *L;
@@ -1642,12 +1647,32 @@ struct Runner {
                 sw.push_back(std::move(one));
             }
         }
-        for (const auto &w : sw) {
-            seg_layouts.push_back(make_layout(w, rb));
+        // the last sweep before a one-qubit channel that needs inner products
+        // holds that qubit, so that it can form the channel's reduced density
+        // matrix on the way (a tile's qubits are its blocks' plus fill)
+        const int rq = rdm_qubit(seg_end);
+        for (size_t u = 0; u < sw.size(); ++u) {
+            const qs::Sweep &w = sw[u];
+            if (u + 1 == sw.size() && rq >= 0 && !w.bits.empty() &&  // a tile sweep
+                std::find(w.bits.begin(), w.bits.end(), rq) == w.bits.end() &&
+                int(w.bits.size()) < qs::kMaxTileBits) {
+                qs::Sweep w2 = w;
+                w2.bits.insert(std::upper_bound(w2.bits.begin(), w2.bits.end(), rq), rq);
+                seg_layouts.push_back(make_layout(w2, rb));
+            } else {
+                seg_layouts.push_back(make_layout(w, rb));
+            }
             SegSweep ss{&seg_layouts.back(), {}};
             for (int b : w.blocks) ss.members.push_back(orig[b]);
             out.push_back(std::move(ss));
         }
+    }
+
+    // The qubit of a one-qubit channel at op index `op` (a segment end), or -1.
+    int rdm_qubit(int op) const {
+        if (op >= int(m.ops.size()) || m.kind[op] != QS_OP_CHANNEL) return -1;
+        const ChannelInfo &ci = m.channels[m.channel_of_op[op]];
+        return ci.k == 1 ? ci.t[0] : -1;
     }
 
     // Launch the deferred reset, if any (before anything reads the state).
@@ -1700,8 +1725,21 @@ struct Runner {
             res.gate_k_launches[d->g.k]++;
         }
         a.mat_total = lofs;
+        if (u.rdm_q >= 0) {
+            a.rdm_lt = L.local[u.rdm_q];
+            a.rdm_out = s->red_partials + kRdmRecordOffset;
+            // a renormalisation this sweep would call for happens before it:
+            // the channel's selection scales the next block by the norm of the
+            // state the matrix is formed on
+            if (!a.init_zero && log_norm_bound + lb < kRenormLogThreshold) {
+                if (timing) QS_CHECK(timer.close(s));
+                QS_CHECK(renormalize_now(s));
+                res.sweeps += 2;
+                log_norm_bound = 0.0;
+            }
+        }
         if (timing) QS_CHECK(timer.open(s));
-        QS_HIP(s, qs::launch_apply_tile(s->amp, s->n, a, s->st));
+        QS_HIP(s, qs::launch_apply_tile(s->amp, s->n, a, s->st, u.rdm_q >= 0 ? &rdm_records : nullptr));
         if (timing) timer.launched();
         res.sweeps++;
         res.gate_sweeps++;
@@ -2168,6 +2206,26 @@ struct Runner {
                 }
                 if (!unit.items.empty()) units.push_back(std::move(unit));
             }
+            // the segment's last sweep forms the next channel's reduced density
+            // matrix when its tile holds the channel's qubit (and it has no
+            // 5-qubit block); otherwise a read pass does, below
+            bool rdm_fused = false;
+            const int rq = seg_end < n_ops ? rdm_qubit(seg_end) : -1;
+            if (rq >= 0 && !units.empty()) {
+                Unit &lu = units.back();
+                bool k5 = false;
+                double lb = 0.0;
+                for (const BlockDesc *d : lu.items) {
+                    k5 |= d->g.k == 5;
+                    lb += d->log_bound;
+                }
+                if (lu.L->tiled && lu.L->tb >= 10 && lu.L->local[rq] >= 0 && !k5 &&
+                    lb >= kRenormLogThreshold) {
+                    QS_CHECK(ensure_reduce(s));
+                    lu.rdm_q = rq;
+                    rdm_fused = true;
+                }
+            }
             QS_CHECK(flush_units(units));
             sel = PendingSelect();
             if (seg_end == n_ops) break;
@@ -2176,10 +2234,15 @@ struct Runner {
             // with the next segment picks the branch and scales its block
             const int c = m.channel_of_op[seg_end];
             const ChannelInfo &ci = m.channels[c];
-            QS_CHECK(settle_reset());
-            QS_CHECK(ensure_reduce(s));
-            QS_HIP(s, qs::launch_rdm(s->amp, s->n, ci.k, ci.ts, s->red_partials, sel_rdm, s->st));
-            res.sweeps++;
+            if (rdm_fused) {
+                QS_HIP(s, qs::launch_reduce_records(s->red_partials + kRdmRecordOffset, rdm_records, 8,
+                                                    sel_rdm, s->st));
+            } else {
+                QS_CHECK(settle_reset());
+                QS_CHECK(ensure_reduce(s));
+                QS_HIP(s, qs::launch_rdm(s->amp, s->n, ci.k, ci.ts, s->red_partials, sel_rdm, s->st));
+                res.sweeps++;
+            }
             sel.active = true;
             sel.op = seg_end;
             sel.channel = c;

@@ -494,3 +494,41 @@ def test_grid24_full_size_delayed_equals_conventional(qs):
         assert rel_l2(a["state"], b["state"]) < 2 * AMP_TOL
         assert np.array_equal(a["samples"], b["samples"])
     assert compared >= 2
+
+
+def test_driver_two_qubit_channel_and_fused_reduced_density_matrix(qs, orc):
+    """Inner products over both kinds of reduced density matrix: one-qubit
+    amplitude damping (its matrix is formed by the last tile sweep before the
+    channel when the tile holds the qubit) and a two-qubit channel that is not
+    a mixture of unitaries (amplitude damping on both qubits at once, four
+    Kraus operators; its 4x4 matrix comes from a read pass).  14 qubits, so
+    tiles are narrower than the state; against the oracle."""
+    rng = np.random.default_rng(21)
+    n = 14
+    ad = W.amplitude_damp(0.2)
+    ad2 = [np.kron(b, a) for b in ad for a in ad]  # matrix bit 0 <-> first qubit
+    ops = []
+    for layer in range(10):
+        for q in range(0, n - 1, 2):
+            a, b = (q, q + 1) if layer % 2 == 0 else ((q + 1) % n, (q + 2) % n)
+            ops.append(W.Op(W.GATE, (a, b), [W.random_unitary(2, rng)], layer, "u2"))
+        for q in rng.choice(n, size=3, replace=False):
+            ops.append(W.Op(W.CHANNEL, (int(q),), ad, layer, "amplitude_damp"))
+        a, b = (int(x) for x in rng.choice(n, size=2, replace=False))
+        ops.append(W.Op(W.CHANNEL, (a, b), ad2, layer, "amplitude_damp2"))
+    c = W.Circuit(n, ops, "ad2")
+    m = orc.Marshalled(c)
+    slow = 0
+    for t in range(3):
+        got = _driver(qs, c, 1, 0, seed=5, traj_offset=t, n_samples=20, return_state=True,
+                      max_fuse=4)
+        ref = orc.run_trajectory(c, t, mode=0, seed=5, n_samples=20, return_state=True,
+                                 marshalled=m)
+        _, tie = compare_choices(got["choices"][0], ref)
+        assert tie == 0
+        assert np.array_equal(got["paths"][0], ref["paths"])
+        slow += int(got["n_slow"][0])
+        assert rel_l2(got["state"], ref["state"]) < AMP_TOL
+        mism = np.nonzero(got["samples"][0] != ref["samples"])[0]
+        assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
+    assert slow >= 6
