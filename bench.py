@@ -298,7 +298,7 @@ def cpu_baseline(cycles: int, workers: int) -> dict:
 
 # ------------------------------------------------------------------ other workloads
 
-def sub_chain12(qs, W, torch, steps=3):
+def sub_chain12(qs, W, torch, steps=20):
     """The 12-qubit chain (depth 20, depolarizing 1e-3 after every gate): 100
     trajectories x 1000 samples in one persistent launch, and as one
     qs_run_trajectories call over the range."""

@@ -107,6 +107,7 @@ struct BatchGate {
     int k;
     int lt[kMaxGateQubits];  // ascending; global bits (resident) or tile-local bits
     int mat;                 // float2 offset of the default matrix in the pool
+    int m0, m1;              // the block's operations in the member table
 };
 
 struct BatchSweep {
@@ -121,68 +122,65 @@ struct BatchCircuit {
     int s0, s1;              // sweep range
     int n_samples;
     int readout;             // offset of 2n doubles (e0[], e1[]) in the readout pool, or -1
+    int g0, n_gates;         // the circuit's blocks (absolute first, count)
+    int ch0, nch;            // the circuit's channels in the channel table
+    int pool0, pool_len;     // float2 range of the circuit's default matrices in the pool
+};
+
+// A channel of a batched circuit (Algorithm 2's fast path for mixtures of
+// unitaries: the pick is decided by r against the running sums of the
+// fixed probabilities).
+struct BatchChannel {
+    int32_t nk;              // Kraus operators
+    int32_t default_pick;    // the pick folded into the default block matrices
+    int32_t pbar;            // offset of the nk probabilities in the pbar pool
+    int32_t gate;            // block holding the channel, relative to the circuit's first
+    int32_t unit;            // double2 offset of K_i / sqrt(pbar_i), i < nk, in the FP64 pool
+    uint32_t identity;       // bit i: K_i is a multiple of I (left out of the fused product)
+};
+
+// One operation of a fused block, in the block's order, for recomputing the
+// block's matrix when a trajectory's picks differ from the defaults.
+struct BatchMember {
+    int k;                   // qubits of the operation
+    int lp[kMaxGateQubits];  // positions of its qubits (its own order) in the block's qubit list
+    int src;                 // >= 0: double2 offset of a gate matrix in the FP64 pool;
+                             // < 0: channel -src - 1 of the circuit
 };
 
 struct BatchJob {
     int circuit;
     uint32_t traj;           // Philox counter word 1
     uint32_t circ_id;        // Philox counter word 2
-    int p0, p1;              // patch range
+    int pad;
     uint64_t seed;           // Philox key
     int64_t out;             // first output sample
+    int64_t choices;         // first recorded pick, or -1
 };
-
-struct BatchPatch {
-    int gate;                // absolute gate index
-    int mat;                 // float2 offset of the trajectory's matrix
-};
-
-// Per-trajectory channel draws of a batched launch on the device (Algorithm
-// 2's fast path for mixtures of unitaries: every pick is decided by r against
-// the running sums of the fixed probabilities).  Picks other than a channel's
-// most likely one are appended to a list as (job, channel, pick) for the host
-// to build the job's patched blocks from.
-struct BatchDrawChannel {
-    int32_t nk;              // Kraus operators
-    int32_t default_pick;    // the pick the default plan folds in
-    int32_t pbar;            // offset of the nk probabilities in the pbar pool
-    int32_t pad;
-};
-
-struct BatchDrawJob {
-    int32_t ch0, nch;        // channel range in the channel table
-    uint32_t traj;           // Philox counter word 1
-    uint32_t circ_id;        // Philox counter word 2
-    uint64_t seed;           // Philox key
-    int64_t choices;         // offset of the job's nch recorded picks, or -1
-};
-
-struct BatchDrawArgs {
-    const BatchDrawChannel *chan;
-    const double *pbar;
-    const BatchDrawJob *jobs;
-    int n_jobs;
-    int over_cap;            // entries the list holds
-    int8_t *choices;         // recorded picks (may be null when no job records)
-    int32_t *count;          // entries appended (may exceed over_cap)
-    int32_t *over;           // 3 x over_cap: job, channel, pick
-};
-
-hipError_t launch_batch_draws(const BatchDrawArgs &a, hipStream_t st);
 
 struct BatchArgs {
     const BatchCircuit *circs;
     const BatchSweep *sweeps;
     const BatchGate *gates;
-    const BatchPatch *patches;
     const BatchJob *jobs;
-    const float2 *mats;
+    const float2 *mats;      // default block matrices
     const double *readout;
+    const BatchChannel *chans;
+    const double *pbar;
+    const BatchMember *members;
+    const double2 *fmats;    // FP64 gate and channel matrices for the members
+    float2 *patched;         // per-workgroup matrices of the blocks a job's picks change
+    int64_t patched_stride;  // float2 entries per workgroup
+    int8_t *choices;         // recorded picks
     float2 *slots;           // per-workgroup state slots (tiled circuits)
     int64_t slot_amps;
     uint64_t *out;
     int n_jobs;
 };
+
+// Blocks per batched circuit: the job's patched-block flags are one bit each
+// in a 2 KiB LDS array.
+constexpr int kBatchMaxBlocks = 16384;
 
 struct ReadoutDesc {
     int enabled;

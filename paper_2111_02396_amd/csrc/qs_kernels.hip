@@ -244,13 +244,15 @@ __device__ __forceinline__ void tile_gate_valu(float2 *__restrict__ sd, const fl
 // Work-item (lane, wave) owns groups lane + 64 wave + NT i; the next group's
 // amplitudes are read before this one's are written (the last iteration
 // re-reads its own group, which is harmless: the reads precede the writes).
-template <int K, class L, int NT = kBlock>
+// MatLds: `gm` is an LDS copy (read as broadcasts) instead of global memory
+// read through the scalar cache.
+template <int K, class L, int NT = kBlock, bool MatLds = false>
 __device__ __forceinline__ void tile_gate_small(float2 *__restrict__ sd, const float2 *gm,
                                                 const int *lt, const int *tab, int tb) {
     constexpr int D = 1 << K;
     float2 u[D * D];
 #pragma unroll
-    for (int i = 0; i < D * D; ++i) u[i] = const_entry(gm, i);
+    for (int i = 0; i < D * D; ++i) u[i] = MatLds ? gm[i] : const_entry(gm, i);
     int off[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) off[j] = L::map(local_offset<K, int>(j, lt));
@@ -842,20 +844,22 @@ __global__ __launch_bounds__(64) void select_branch(SelectArgs a) {
 // ---------------------------------------------------------------- batched
 
 // One fused block on amplitudes held in LDS (a whole resident state, or a
-// tile).  Fragments for the MFMA gates are staged per block; the trailing
-// barrier lets the next block reuse the staging area.
+// tile).  For k <= 4, `m` is the block's matrix already copied to LDS; for
+// k = 5 it is the global copy.  Fragments for the MFMA gates are staged per
+// block.  `then` runs after the block's arithmetic and before the trailing
+// barrier, which lets the next block reuse the staging area.
+template <class Then>
 __device__ __forceinline__ void batched_gate(float2 *__restrict__ sd, float *__restrict__ frag,
-                                             const BatchGate &g, const float2 *__restrict__ m,
-                                             int tb) {
+                                             const BatchGate &g, const float2 *m, int tb, Then then) {
     int lt[kMaxGateQubits], tab[kMaxTileBits];
 #pragma unroll
     for (int b = 0; b < kMaxGateQubits; ++b) lt[b] = g.lt[b];
     if (g.k == 1) {
         gate_tables<1, PlainTile>(lt, tab);
-        tile_gate_small<1, PlainTile>(sd, m, lt, tab, tb);
+        tile_gate_small<1, PlainTile, kBlock, true>(sd, m, lt, tab, tb);
     } else if (g.k == 2) {
         gate_tables<2, PlainTile>(lt, tab);
-        tile_gate_small<2, PlainTile>(sd, m, lt, tab, tb);
+        tile_gate_small<2, PlainTile, kBlock, true>(sd, m, lt, tab, tb);
     } else if (g.k == 3 && tb >= 10) {
         gate_tables<3, PlainTile>(lt, tab);
         stage_frag3(frag, m, tab);
@@ -866,18 +870,224 @@ __device__ __forceinline__ void batched_gate(float2 *__restrict__ sd, float *__r
         stage_frag4(frag, m, tab);
         __syncthreads();
         tile_gate_mfma4<PlainTile>(sd, frag, tab, tb);
+    } else if (g.k == 3) {
+        tile_gate_valu<3, PlainTile>(sd, m, lt, tb);
+    } else if (g.k == 4) {
+        tile_gate_valu<4, PlainTile>(sd, m, lt, tb);
     } else {
-        const int dd = 1 << (2 * g.k);
         float2 *mm = reinterpret_cast<float2 *>(frag);
-        for (int i = threadIdx.x; i < dd; i += kBlock) mm[i] = m[i];
+        for (int i = threadIdx.x; i < 1024; i += kBlock) mm[i] = m[i];
         __syncthreads();
-        switch (g.k) {
-            case 3: tile_gate_valu<3, PlainTile>(sd, mm, lt, tb); break;
-            case 4: tile_gate_valu<4, PlainTile>(sd, mm, lt, tb); break;
-            default: tile_gate_valu<5, PlainTile>(sd, mm, lt, tb); break;
+        tile_gate_valu<5, PlainTile>(sd, mm, lt, tb);
+    }
+    then();
+    __syncthreads();
+}
+
+// Algorithm 2's fast path for a mixture of unitaries: the first i with
+// r < pbar_i after subtracting the earlier pbar_j (FP64, in order); when
+// rounding leaves r above the total, the last operator with weight.
+__device__ __forceinline__ int draw_pick(const double *pb, int nk, double r) {
+    for (int i = 0; i < nk; ++i) {
+        if (r < pb[i]) return i;
+        r -= pb[i];
+    }
+    for (int i = nk - 1; i >= 0; --i)
+        if (pb[i] > 0.0) return i;
+    return nk - 1;
+}
+
+// A block of a job: its descriptor and its matrix (the default one, or the
+// job's recomputed copy when one of the block's channels took another pick).
+struct BatchedRef {
+    BatchGate g;
+    const float2 *m;
+};
+
+__device__ __forceinline__ BatchedRef batched_ref(const BatchArgs &A, const uint32_t *mask,
+                                                  const float2 *mine, const BatchCircuit &C, int gi) {
+    BatchedRef r;
+    r.g = A.gates[gi];
+    const int rel = gi - C.g0;
+    const bool patched = (mask[rel >> 5] >> (rel & 31)) & 1u;
+    r.m = patched ? mine + (r.g.mat - C.pool0) : A.mats + r.g.mat;
+    return r;
+}
+
+// This work-item's entry of a k <= 4 matrix (at most 256 entries, one per
+// work-item).
+__device__ __forceinline__ bool batched_holds(const BatchedRef &r) {
+    return r.g.k <= 4 && int(threadIdx.x) < (1 << (2 * r.g.k));
+}
+
+// Blocks [g0, g1) on the amplitudes in `sd`, software-pipelined so that no
+// global-memory latency sits between two blocks: while block i runs, the
+// matrix of block i + 1 travels into registers (and lands in the other half
+// of the double-buffered LDS copy `raw` after block i's arithmetic) and the
+// descriptor of block i + 2 is loaded.  Workgroup barriers on gfx950 do not
+// wait for outstanding global loads, so both overlap the block's work.
+__device__ __forceinline__ void batched_blocks(const BatchArgs &A, const uint32_t *mask, const float2 *mine,
+                               const BatchCircuit &C, int g0, int g1, float2 *__restrict__ sd,
+                               float *__restrict__ frag, float2 *raw, int tb) {
+    if (g0 >= g1) return;
+    BatchedRef cur = batched_ref(A, mask, mine, C, g0);
+    if (batched_holds(cur)) raw[threadIdx.x] = cur.m[threadIdx.x];
+    BatchedRef nxt = cur;
+    if (g0 + 1 < g1) nxt = batched_ref(A, mask, mine, C, g0 + 1);
+    __syncthreads();
+    int buf = 0;
+    for (int gi = g0; gi < g1; ++gi) {
+        const bool put1 = gi + 1 < g1 && batched_holds(nxt);
+        float2 e1 = make_float2(0.f, 0.f);
+        if (put1) e1 = nxt.m[threadIdx.x];
+        BatchedRef after = nxt;
+        if (gi + 2 < g1) after = batched_ref(A, mask, mine, C, gi + 2);
+        float2 *next_raw = raw + 256 * (buf ^ 1);
+        const float2 *m = cur.g.k <= 4 ? raw + 256 * buf : cur.m;
+        batched_gate(sd, frag, cur.g, m, tb, [&] {
+            if (put1) next_raw[threadIdx.x] = e1;
+        });
+        cur = nxt;
+        nxt = after;
+        buf ^= 1;
+    }
+}
+
+// One operation (k qubits; block position of its bit b in bits 3b..3b+2 of
+// `lpp`) on a column of a fused block's matrix, as the host's fusion does
+// it: for each group, w_j = sum_l U[j][l] v_l in FP64 with the complex
+// products and sums rounded one by one (no contraction into FMAs).
+__device__ __forceinline__ int member_spread(int j, int k, int lpp) {
+    int x = 0;
+    for (int b = 0; b < k; ++b) x |= ((j >> b) & 1) << ((lpp >> (3 * b)) & 7);
+    return x;
+}
+
+__device__ __forceinline__ int member_base(int grp, int opmask) {
+    int base = 0, rest = grp;  // the group's bits, in order, at the positions the operation leaves free
+    for (int p = 0; p < kMaxGateQubits; ++p)
+        if (!((opmask >> p) & 1)) {
+            base |= (rest & 1) << p;
+            rest >>= 1;
+        }
+    return base;
+}
+
+// k <= 3: the group's v in registers, U an LDS copy.
+template <int K>
+__device__ __forceinline__ void fuse_member_small(double2 *col, int D, int lpp, const double2 *U) {
+#pragma clang fp contract(off)
+    constexpr int d = 1 << K;
+    int opmask = 0, off[d];
+#pragma unroll
+    for (int b = 0; b < K; ++b) opmask |= 1 << ((lpp >> (3 * b)) & 7);
+#pragma unroll
+    for (int j = 0; j < d; ++j) off[j] = member_spread(j, K, lpp);
+    for (int grp = 0; grp < (D >> K); ++grp) {
+        const int base = member_base(grp, opmask);
+        double2 v[d];
+#pragma unroll
+        for (int l = 0; l < d; ++l) v[l] = col[base + off[l]];
+#pragma unroll
+        for (int j = 0; j < d; ++j) {
+            double sr = 0.0, si = 0.0;
+#pragma unroll
+            for (int l = 0; l < d; ++l) {
+                const double2 u = U[j * d + l];
+                const double pr = u.x * v[l].x - u.y * v[l].y;
+                const double pi = u.x * v[l].y + u.y * v[l].x;
+                sr = sr + pr;
+                si = si + pi;
+            }
+            col[base + off[j]] = make_double2(sr, si);
         }
     }
-    __syncthreads();
+}
+
+// k = 4, 5 (a wide gate sharing a block with a channel): v from `old`, a
+// copy of the column taken before the operation, U from global memory.
+__device__ __forceinline__ void fuse_member_wide(double2 *col, double2 *old, int D, int k, int lpp,
+                                                 const double2 *U) {
+#pragma clang fp contract(off)
+    const int d = 1 << k;
+    for (int r = 0; r < D; ++r) old[r] = col[r];
+    int opmask = 0;
+    for (int b = 0; b < k; ++b) opmask |= 1 << ((lpp >> (3 * b)) & 7);
+    for (int grp = 0; grp < (D >> k); ++grp) {
+        const int base = member_base(grp, opmask);
+        for (int j = 0; j < d; ++j) {
+            double sr = 0.0, si = 0.0;
+            for (int l = 0; l < d; ++l) {
+                const double2 u = U[j * d + l];
+                const double2 v = old[base + member_spread(l, k, lpp)];
+                const double pr = u.x * v.x - u.y * v.y;
+                const double pi = u.x * v.y + u.y * v.x;
+                sr = sr + pr;
+                si = si + pi;
+            }
+            col[base + member_spread(j, k, lpp)] = make_double2(sr, si);
+        }
+    }
+}
+
+// The matrix of block `rel` of the job's circuit with the job's picks, by
+// one wavefront: each active lane carries one column of the product from
+// the identity through the block's operations in order, in the wavefront's
+// LDS workspace `ws` (1024 complex128: the column and its copy, so 32
+// columns at a time for k <= 4 and 16 for k = 5; operators of up to 3
+// qubits are staged in `ush`, 64 complex128), and writes it as complex64
+// to the job's copy of the block's matrix.  Channel picks are drawn again
+// (the same Philox call as the draw pass).
+__device__ __forceinline__ void fuse_patched(const BatchArgs &A, const BatchJob &J, const BatchCircuit &C,
+                                             int rel, double2 *ws, double2 *ush, float2 *mine) {
+    const BatchGate g = A.gates[C.g0 + rel];
+    const int D = 1 << g.k;
+    const int per_pass = D <= 16 ? D : 16;
+    const int lane = int(threadIdx.x) & 63;
+    double2 *col = ws + lane * D;
+    double2 *old = ws + 512 + lane * D;
+    for (int c0 = 0; c0 < D; c0 += per_pass) {
+        const bool on = lane < per_pass;
+        const int c = c0 + lane;
+        if (on)
+            for (int r = 0; r < D; ++r) col[r] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+        for (int mi = g.m0; mi < g.m1; ++mi) {
+            const BatchMember M = A.members[mi];
+            const double2 *U;
+            if (M.src >= 0) {
+                U = A.fmats + M.src;
+            } else {
+                const int ci = -M.src - 1;
+                const BatchChannel ch = A.chans[C.ch0 + ci];
+                const int pick = draw_pick(A.pbar + ch.pbar, ch.nk,
+                                           philox_uniform(J.seed, uint32_t(ci), J.traj, J.circ_id, kStreamChannel));
+                if ((ch.identity >> pick) & 1u) continue;
+                U = A.fmats + ch.unit + pick * (1 << (2 * M.k));
+            }
+            int lpp = 0;
+#pragma unroll
+            for (int b = 0; b < kMaxGateQubits; ++b) lpp |= (M.lp[b] & 7) << (3 * b);
+            if (M.k <= 3) {
+                // the wavefront's lanes run in lockstep: the previous
+                // operator's reads precede these writes, and these writes
+                // precede the reads below
+                __builtin_amdgcn_wave_barrier();
+                if (lane < (1 << (2 * M.k))) ush[lane] = U[lane];
+                __builtin_amdgcn_wave_barrier();
+                if (on) {
+                    if (M.k == 1) fuse_member_small<1>(col, D, lpp, ush);
+                    else if (M.k == 2) fuse_member_small<2>(col, D, lpp, ush);
+                    else fuse_member_small<3>(col, D, lpp, ush);
+                }
+            } else if (on) {
+                fuse_member_wide(col, old, D, M.k, lpp, U);
+            }
+        }
+        if (on) {
+            float2 *dst = mine + (g.mat - C.pool0);
+            for (int r = 0; r < D; ++r) dst[r * D + c] = make_float2(float(col[r].x), float(col[r].y));
+        }
+    }
 }
 
 // Persistent launch: each workgroup takes jobs blockIdx.x, + gridDim.x, ...
@@ -890,28 +1100,59 @@ __global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
     extern __shared__ float2 smem[];
     float2 *sd = smem;                                                   // 2^13 amplitudes
     float *frag = reinterpret_cast<float *>(smem + (1 << kBatchLdsQubits));  // 2048 floats
+    float2 *raw = smem + (1 << kBatchLdsQubits) + 1024;                  // 2 x 256 entries
     __shared__ double part[kBlock];
     float2 *slot = A.slots ? A.slots + size_t(blockIdx.x) * size_t(A.slot_amps) : nullptr;
+    float2 *mine = A.patched + size_t(blockIdx.x) * size_t(A.patched_stride);
+    uint32_t *mask = reinterpret_cast<uint32_t *>(part);  // blocks the job's picks change
     for (int job = blockIdx.x; job < A.n_jobs; job += gridDim.x) {
         const BatchJob J = A.jobs[job];
         const BatchCircuit C = A.circs[J.circuit];
         const int n = C.n;
         const int dim = 1 << n;
+        // the job's channel draws (one Philox call per channel, Algorithm
+        // 2's fast path), recorded when asked; a pick other than the default
+        // one flags its block
+        const int words = (C.n_gates + 31) >> 5;
+        for (int w = threadIdx.x; w < words; w += kBlock) mask[w] = 0u;
+        __syncthreads();
+        for (int c = threadIdx.x; c < C.nch; c += kBlock) {
+            const BatchChannel ch = A.chans[C.ch0 + c];
+            const int pick = draw_pick(A.pbar + ch.pbar, ch.nk,
+                                       philox_uniform(J.seed, uint32_t(c), J.traj, J.circ_id, kStreamChannel));
+            if (J.choices >= 0) A.choices[J.choices + c] = int8_t(pick);
+            if (pick != ch.default_pick) atomicOr(&mask[ch.gate >> 5], 1u << (ch.gate & 31));
+        }
+        __syncthreads();
+        // the flagged blocks' matrices with the job's picks, one wavefront
+        // per block (workspace: a quarter of the LDS state area each)
+        {
+            const int wave = int(threadIdx.x) >> 6;
+            double2 *ws = reinterpret_cast<double2 *>(sd) + wave * 1024;
+            double2 *ush = reinterpret_cast<double2 *>(raw) + wave * 64;
+            for (int w = wave; w < words; w += kBlock / 64) {
+                uint32_t bits = __builtin_amdgcn_readfirstlane(mask[w]);
+                while (bits) {
+                    const int b = __builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    fuse_patched(A, J, C, 32 * w + b, ws, ush, mine);
+                }
+            }
+            // The workgroup's own global stores (these copies, the state slot)
+            // are read back only by its own wavefronts, which share one CU and
+            // its L1: the barrier's workgroup-scope ordering suffices, and no
+            // device-scope fence (an L2 write-back and invalidate on gfx950)
+            // is needed anywhere in this kernel.
+            __syncthreads();
+        }
         float2 *state = C.resident ? sd : slot;
         for (int i = threadIdx.x; i < dim; i += kBlock)
             state[i] = make_float2(i == 0 ? 1.f : 0.f, 0.f);
-        if (!C.resident) __threadfence();
         __syncthreads();
-        int p = J.p0;
         for (int si = C.s0; si < C.s1; ++si) {
             const BatchSweep &S = A.sweeps[si];
             if (C.resident) {
-                for (int gi = S.g0; gi < S.g1; ++gi) {
-                    const BatchGate g = A.gates[gi];
-                    int mo = g.mat;
-                    if (p < J.p1 && A.patches[p].gate == gi) mo = A.patches[p++].mat;
-                    batched_gate(sd, frag, g, A.mats + mo, n);
-                }
+                batched_blocks(A, mask, mine, C, S.g0, S.g1, sd, frag, raw, n);
                 continue;
             }
             // tiled: one pass over the slot, tile by tile
@@ -921,7 +1162,6 @@ __global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
             for (int b = 0; b < 8; ++b)
                 if ((threadIdx.x >> b) & 1) off_tid |= 1 << S.pos[b];
             const int n_tiles = dim >> tb;
-            const int p_sweep = p;
             for (int t = 0; t < n_tiles; ++t) {
                 int base = t;
                 for (int b = 0; b < tb; ++b) {
@@ -936,13 +1176,7 @@ __global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
                     sd[threadIdx.x + (r << 8)] = slot[base + o];
                 }
                 __syncthreads();
-                p = p_sweep;
-                for (int gi = S.g0; gi < S.g1; ++gi) {
-                    const BatchGate g = A.gates[gi];
-                    int mo = g.mat;
-                    if (p < J.p1 && A.patches[p].gate == gi) mo = A.patches[p++].mat;
-                    batched_gate(sd, frag, g, A.mats + mo, tb);
-                }
+                batched_blocks(A, mask, mine, C, S.g0, S.g1, sd, frag, raw, tb);
                 for (int r = 0; r < R; ++r) {
                     int o = 0;
                     for (int b = 8; b < tb; ++b)
@@ -951,8 +1185,6 @@ __global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
                 }
                 __syncthreads();
             }
-            __threadfence();  // this pass's stores reach L2, stale L1 lines go
-            __syncthreads();
         }
         // sampling: chunk c = amplitudes [c*L, (c+1)*L), L = dim / 256 (>= 1)
         const int L = dim >= kBlock ? dim / kBlock : 1;
@@ -1607,40 +1839,6 @@ hipError_t apply_tile_idx(float2 *amp, int n, const TileArgs &a, hipStream_t st,
     }
 }
 
-// Channel draws of a batched launch: one workgroup per job at a time, its
-// work-items over the job's channels.  Picks follow the same rule and the
-// same FP64 arithmetic as the host planner.
-__global__ void __launch_bounds__(256) batch_draws(BatchDrawArgs a) {
-    for (int j = blockIdx.x; j < a.n_jobs; j += gridDim.x) {
-        const BatchDrawJob J = a.jobs[j];
-        for (int c = threadIdx.x; c < J.nch; c += blockDim.x) {
-            const BatchDrawChannel ch = a.chan[J.ch0 + c];
-            double r = philox_uniform(J.seed, uint32_t(c), J.traj, J.circ_id, kStreamChannel);
-            const double *pb = a.pbar + ch.pbar;
-            int pick = -1;
-            for (int i = 0; i < ch.nk; ++i) {
-                if (r < pb[i]) {
-                    pick = i;
-                    break;
-                }
-                r -= pb[i];
-            }
-            if (pick < 0)  // rounding left r above the total: the last operator with weight
-                for (int i = ch.nk - 1; i >= 0 && pick < 0; --i)
-                    if (pb[i] > 0.0) pick = i;
-            if (J.choices >= 0) a.choices[J.choices + c] = int8_t(pick);
-            if (pick != ch.default_pick) {
-                const int slot = atomicAdd(a.count, 1);
-                if (slot < a.over_cap) {
-                    a.over[3 * slot] = j;
-                    a.over[3 * slot + 1] = c;
-                    a.over[3 * slot + 2] = pick;
-                }
-            }
-        }
-    }
-}
-
 }  // namespace
 
 hipError_t launch_select(const SelectArgs &a, hipStream_t st) {
@@ -1650,26 +1848,19 @@ hipError_t launch_select(const SelectArgs &a, hipStream_t st) {
 }
 
 int batched_grid() {
-    const int per_cu = int((160u * 1024u) / (sizeof(float2) * ((1u << kBatchLdsQubits) + 1024u) +
+    const int per_cu = int((160u * 1024u) / (sizeof(float2) * ((1u << kBatchLdsQubits) + 1536u) +
                                              sizeof(double) * kBlock));
     return device_cus() * (per_cu < 1 ? 1 : per_cu);
 }
 
 hipError_t launch_batched(const BatchArgs &a, int grid, hipStream_t st) {
-    const size_t lds = sizeof(float2) * ((size_t(1) << kBatchLdsQubits) + 1024);
+    const size_t lds = sizeof(float2) * ((size_t(1) << kBatchLdsQubits) + 1536);
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&run_batched),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                                        int(lds));
     if (attr != hipSuccess) return attr;
     if (grid < 1) return hipErrorInvalidValue;
     run_batched<<<unsigned(grid), kBlock, lds, st>>>(a);
-    return hipGetLastError();
-}
-
-hipError_t launch_batch_draws(const BatchDrawArgs &a, hipStream_t st) {
-    if (a.n_jobs < 1) return hipSuccess;
-    const unsigned grid = unsigned(a.n_jobs < 4096 ? a.n_jobs : 4096);
-    batch_draws<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

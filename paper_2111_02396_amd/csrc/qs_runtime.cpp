@@ -2733,12 +2733,13 @@ struct BatchPlanKey {
     bool operator<(const BatchPlanKey &o) const { return std::tie(hash, f) < std::tie(o.hash, o.f); }
 };
 struct BatchPlanEntry {
-    std::vector<qs::Block> blocks;
-    std::vector<int> op_block;
-    std::vector<int> gate_of_block;       // gate index (local) of each block
-    std::vector<qs::BatchSweep> sweeps;   // gate ranges local to the circuit
-    std::vector<qs::BatchGate> gates;     // mat: offset into pool
-    std::vector<float2> pool;             // the default matrices of the blocks
+    std::vector<qs::BatchSweep> sweeps;     // gate ranges local to the circuit
+    std::vector<qs::BatchGate> gates;       // mat: offset into pool; m0, m1: into members
+    std::vector<float2> pool;               // the default matrices of the blocks
+    std::vector<qs::BatchChannel> chans;    // pbar: into pbar; unit: into fmats
+    std::vector<double> pbar;
+    std::vector<qs::BatchMember> members;   // src >= 0: into fmats
+    std::vector<double2> fmats;             // FP64 gate and channel matrices of the members
 };
 constexpr size_t kBatchPlanEntries = 2048;
 std::mutex g_bplan_mu;
@@ -2765,20 +2766,8 @@ void batch_plan_insert(const BatchPlanKey &k, std::shared_ptr<const BatchPlanEnt
 struct BatchPlanCircuit {
     std::shared_ptr<const ModelEntry> me;
     const CircuitModel *m = nullptr;  // me->model
-    std::vector<qs::Block> blocks;
-    std::vector<int> op_block;
-    std::vector<const cd *> default_mats;
-    std::vector<int> gate_of_block;  // absolute gate index of each block
-    int64_t gate_base = 0;           // first absolute gate index
-    int64_t default_mat_base = 0;    // float2 offset of this circuit's default matrices
-    int circuit_index = 0;
+    std::shared_ptr<const BatchPlanEntry> plan;
     bool resident = false;
-};
-
-// Host-side pieces produced per trajectory by the planning threads.
-struct BatchTrajOut {
-    std::vector<qs::BatchPatch> patches;  // gate index, matrix offset in `pool` (local)
-    std::vector<float2> pool;             // patched matrices
 };
 
 // Grow-only device buffers for the batched launch, one set per device; a
@@ -2788,13 +2777,11 @@ struct BatchBuffers {
     char *prog = nullptr;
     size_t prog_cap = 0;
     float2 *slots = nullptr;
-    size_t slots_cap = 0;  // bytes
-    char *host = nullptr;  // pinned staging for the program
+    size_t slots_cap = 0;    // bytes
+    float2 *patched = nullptr;
+    size_t patched_cap = 0;  // bytes
+    char *host = nullptr;    // pinned staging for the program
     size_t host_cap = 0;
-    char *draw_dev = nullptr;   // channel draws: tables in, picks out
-    size_t draw_dev_cap = 0;
-    char *draw_host = nullptr;  // pinned mirror of draw_dev
-    size_t draw_host_cap = 0;
 };
 
 BatchBuffers &batch_buffers() {
@@ -2894,155 +2881,30 @@ class HostPool {
     uint64_t generation_ = 0;
 };
 
-// Batches with at least this many channel draws draw them on the device
-// (below it the round trip costs more than the host's draws); at most
-// kDeviceDrawMax, and with room for kDeviceOverCap picks other than the
-// default ones (beyond that the host draws instead).
-constexpr size_t kDeviceDrawMin = 16384;
-constexpr size_t kDeviceDrawMax = size_t(1) << 30;
-constexpr size_t kDeviceOverCap = size_t(1) << 20;
-constexpr size_t kDeviceOverFirst = 8192;  // entries copied back with the count
-
-// The channel draws of every job on the device.  job_of(j) gives job j's
-// (item, trajectory within the item); on_pick(j, channel, pick) receives
-// the picks other than the channel's default one, in (job, channel) order.
-// Recorded picks are written to the items' kraus_choices.  *done is false
-// (and nothing is reported) when the picks other than the default ones do
-// not fit the list: the caller then draws on the host.
-template <class JobOf, class OnPick>
-qs_status device_draws(const qs_batch_item *items, int n_items, const std::vector<BatchPlanCircuit> &plans,
-                       size_t n_jobs, JobOf job_of, size_t draws, hipStream_t st, BatchBuffers &BB,
-                       OnPick on_pick, bool *done) {
-    *done = false;
-    std::vector<qs::BatchDrawChannel> chan;
-    std::vector<double> pbar;
-    std::vector<int32_t> ch0(n_items);
-    std::vector<int64_t> choice_base(n_items, -1);
-    int64_t n_choices = 0;
-    for (int it = 0; it < n_items; ++it) {
-        const CircuitModel &m = *plans[it].m;
-        ch0[it] = int32_t(chan.size());
-        for (const ChannelInfo &c : m.channels) {
-            chan.push_back({c.nk, c.default_pick, int32_t(pbar.size()), 0});
-            pbar.insert(pbar.end(), c.pbar.begin(), c.pbar.end());
-        }
-        if (items[it].kraus_choices && !m.channels.empty()) {
-            choice_base[it] = n_choices;
-            n_choices += items[it].n_traj * int64_t(m.channels.size());
-        }
-    }
-    std::vector<qs::BatchDrawJob> dj(n_jobs);
-    for (size_t j = 0; j < n_jobs; ++j) {
-        const auto ir = job_of(j);
-        const qs_batch_item &I = items[ir.first];
-        const int nch = int(plans[ir.first].m->channels.size());
-        qs::BatchDrawJob &J = dj[j];
-        J.ch0 = ch0[ir.first];
-        J.nch = nch;
-        J.traj = uint32_t(I.traj_offset + ir.second);
-        J.circ_id = I.circuit_id;
-        J.seed = I.seed;
-        J.choices = choice_base[ir.first] >= 0 ? choice_base[ir.first] + ir.second * nch : -1;
-    }
-    const size_t over_cap = std::min(draws, kDeviceOverCap);
-    auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
-    const size_t o_chan = 0;
-    const size_t o_pbar = o_chan + align(sizeof(qs::BatchDrawChannel) * std::max<size_t>(chan.size(), 1));
-    const size_t o_jobs = o_pbar + align(sizeof(double) * std::max<size_t>(pbar.size(), 1));
-    const size_t o_count = o_jobs + align(sizeof(qs::BatchDrawJob) * n_jobs);
-    const size_t o_over = o_count + 256;
-    const size_t o_choice = o_over + align(sizeof(int32_t) * 3 * over_cap);
-    const size_t total = o_choice + align(size_t(std::max<int64_t>(n_choices, 1)));
-    hipError_t e = hipSuccess;
-    if (total > BB.draw_dev_cap) {
-        if (BB.draw_dev) (void)hipFree(BB.draw_dev);
-        BB.draw_dev = nullptr;
-        BB.draw_dev_cap = 0;
-        if ((e = hipMalloc(&BB.draw_dev, total)) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(QS_ERR_OUT_OF_MEMORY, "allocating the channel-draw buffers failed");
-        }
-        BB.draw_dev_cap = total;
-    }
-    if (total > BB.draw_host_cap) {
-        if (BB.draw_host) (void)hipHostFree(BB.draw_host);
-        BB.draw_host = nullptr;
-        BB.draw_host_cap = 0;
-        if ((e = hipHostMalloc(reinterpret_cast<void **>(&BB.draw_host), total, hipHostMallocDefault)) !=
-            hipSuccess) {
-            (void)hipGetLastError();
-            return fail(QS_ERR_OUT_OF_MEMORY, "allocating pinned draw staging failed");
-        }
-        BB.draw_host_cap = total;
-    }
-    char *h = BB.draw_host, *d = BB.draw_dev;
-    std::memcpy(h + o_chan, chan.data(), sizeof(qs::BatchDrawChannel) * chan.size());
-    std::memcpy(h + o_pbar, pbar.data(), sizeof(double) * pbar.size());
-    std::memcpy(h + o_jobs, dj.data(), sizeof(qs::BatchDrawJob) * n_jobs);
-    std::memset(h + o_count, 0, sizeof(int32_t));
-    qs::BatchDrawArgs A;
-    A.chan = reinterpret_cast<const qs::BatchDrawChannel *>(d + o_chan);
-    A.pbar = reinterpret_cast<const double *>(d + o_pbar);
-    A.jobs = reinterpret_cast<const qs::BatchDrawJob *>(d + o_jobs);
-    A.n_jobs = int(n_jobs);
-    A.over_cap = int(over_cap);
-    A.choices = reinterpret_cast<int8_t *>(d + o_choice);
-    A.count = reinterpret_cast<int32_t *>(d + o_count);
-    A.over = reinterpret_cast<int32_t *>(d + o_over);
-    const size_t first = std::min(over_cap, kDeviceOverFirst);
-    auto dev = [&](hipError_t x) -> qs_status {
-        if (x == hipSuccess) return QS_OK;
-        return fail(QS_ERR_DEVICE, std::string("batched channel draws: ") + hipGetErrorString(x));
-    };
-    QS_CHECK(dev(hipMemcpyAsync(d, h, o_count + sizeof(int32_t), hipMemcpyHostToDevice, st)));
-    QS_CHECK(dev(qs::launch_batch_draws(A, st)));
-    QS_CHECK(dev(hipMemcpyAsync(h + o_count, d + o_count, (o_over - o_count) + sizeof(int32_t) * 3 * first,
-                                hipMemcpyDeviceToHost, st)));
-    if (n_choices > 0)
-        QS_CHECK(dev(hipMemcpyAsync(h + o_choice, d + o_choice, size_t(n_choices), hipMemcpyDeviceToHost, st)));
-    QS_CHECK(dev(hipStreamSynchronize(st)));
-    int32_t count = 0;
-    std::memcpy(&count, h + o_count, sizeof(count));
-    if (count < 0 || size_t(count) > over_cap) return QS_OK;  // the host draws instead
-    if (size_t(count) > first) {
-        QS_CHECK(dev(hipMemcpyAsync(h + o_over + sizeof(int32_t) * 3 * first, d + o_over + sizeof(int32_t) * 3 * first,
-                                    sizeof(int32_t) * 3 * (size_t(count) - first), hipMemcpyDeviceToHost, st)));
-        QS_CHECK(dev(hipStreamSynchronize(st)));
-    }
-    for (int it = 0; it < n_items; ++it)
-        if (choice_base[it] >= 0)
-            std::memcpy(items[it].kraus_choices, h + o_choice + choice_base[it],
-                        size_t(items[it].n_traj) * plans[it].m->channels.size());
-    std::vector<std::array<int32_t, 3>> over(static_cast<size_t>(count));
-    std::memcpy(over.data(), h + o_over, sizeof(int32_t) * 3 * size_t(count));
-    std::sort(over.begin(), over.end());
-    for (const auto &x : over) {
-        if (x[0] < 0 || size_t(x[0]) >= n_jobs || x[1] < 0 || x[1] >= dj[size_t(x[0])].nch ||
-            x[2] < 0 || x[2] >= chan[size_t(dj[size_t(x[0])].ch0 + x[1])].nk)
-            return fail(QS_ERR_DEVICE, "channel draw out of range");
-        on_pick(x[0], x[1], x[2]);
-    }
-    *done = true;
-    return QS_OK;
-}
-
 // Fusion, sweep grouping and default block matrices of one circuit for the
-// batched launch (every channel at its most likely pick).
+// batched launch (every channel at its most likely pick), with what the
+// device needs to redo a block for other picks: the channel table and, for
+// each block holding a channel, its operations with FP64 matrices.
 qs_status plan_batched_circuit(const CircuitModel &m, const std::vector<const cd *> &default_mats,
                                int f, bool resident, int64_t n_traj, BatchPlanEntry &e) {
     const int n = m.n;
-    e.blocks = qs::fuse_greedy(n, m.ops, f, &e.op_block);
+    std::vector<int> op_block;
+    const std::vector<qs::Block> blocks = qs::fuse_greedy(n, m.ops, f, &op_block);
+    if (blocks.size() > size_t(qs::kBatchMaxBlocks))
+        return fail(QS_ERR_NOT_SUPPORTED, "batched circuits fuse into at most 16384 blocks");
     std::vector<qs::Sweep> sw;
     if (resident) {
         qs::Sweep one;
-        for (size_t b = 0; b < e.blocks.size(); ++b) one.blocks.push_back(int(b));
+        for (size_t b = 0; b < blocks.size(); ++b) one.blocks.push_back(int(b));
         sw.push_back(std::move(one));
     } else {
         static const int no_budget[6] = {0, 0, 0, 0, 0, 0};
-        sw = qs::group_sweeps_best(n, e.blocks, qs::kBatchTileBits, 6, 1 << 30, 1 << 30, no_budget,
+        sw = qs::group_sweeps_best(n, blocks, qs::kBatchTileBits, 6, 1 << 30, 1 << 30, no_budget,
                                    plan_restarts(n, n_traj), kGroupSeed);
     }
-    e.gate_of_block.assign(e.blocks.size(), -1);
+    std::vector<char> has_channel(blocks.size(), 0);
+    for (const ChannelInfo &c : m.channels) has_channel[size_t(op_block[size_t(c.op)])] = 1;
+    std::vector<int> gate_of_block(blocks.size(), -1);
     std::vector<cd> tmp(1024);
     for (const auto &w : sw) {
         qs::BatchSweep S;
@@ -3073,7 +2935,7 @@ qs_status plan_batched_circuit(const CircuitModel &m, const std::vector<const cd
         }
         S.g0 = int(e.gates.size());
         for (int b : w.blocks) {
-            const qs::Block &B = e.blocks[b];
+            const qs::Block &B = blocks[b];
             qs::BatchGate G;
             std::memset(&G, 0, sizeof(G));
             G.k = B.k;
@@ -3083,12 +2945,55 @@ qs_status plan_batched_circuit(const CircuitModel &m, const std::vector<const cd
             G.mat = int(e.pool.size());
             e.pool.resize(e.pool.size() + size_t(D) * D + (D * D) % 2);
             to_float2(D, tmp.data(), e.pool.data() + G.mat);
-            e.gate_of_block[b] = int(e.gates.size());
+            G.m0 = G.m1 = int(e.members.size());
+            if (has_channel[size_t(b)]) {
+                for (int o : B.ops) {
+                    const qs::PlanOp &op = m.ops[size_t(o)];
+                    qs::BatchMember M;
+                    std::memset(&M, 0, sizeof(M));
+                    M.k = op.k;
+                    for (int j = 0; j < op.k; ++j) M.lp[j] = int(std::find(B.q, B.q + B.k, op.q[j]) - B.q);
+                    if (m.kind[size_t(o)] == QS_OP_GATE) {
+                        const cd *U = m.gate_mat[size_t(o)];
+                        if (!U) continue;  // left out of the product, as in the default fusion
+                        M.src = int(e.fmats.size());
+                        const int d = 1 << op.k;
+                        for (int x = 0; x < d * d; ++x) e.fmats.push_back(make_double2(U[x].real(), U[x].imag()));
+                    } else {
+                        M.src = -m.channel_of_op[size_t(o)] - 1;
+                    }
+                    e.members.push_back(M);
+                }
+                G.m1 = int(e.members.size());
+            }
+            gate_of_block[size_t(b)] = int(e.gates.size());
             e.gates.push_back(G);
         }
         S.g1 = int(e.gates.size());
         e.sweeps.push_back(S);
     }
+    for (const ChannelInfo &c : m.channels) {
+        if (c.nk > 32) return fail(QS_ERR_NOT_SUPPORTED, "batched channels have at most 32 Kraus operators");
+        const int D = 1 << c.k;
+        qs::BatchChannel ch;
+        ch.nk = c.nk;
+        ch.default_pick = c.default_pick;
+        ch.pbar = int32_t(e.pbar.size());
+        ch.gate = gate_of_block[size_t(op_block[size_t(c.op)])];
+        ch.unit = int32_t(e.fmats.size());
+        ch.identity = 0;
+        for (int i = 0; i < c.nk; ++i) {
+            if (c.identity[size_t(i)]) ch.identity |= 1u << i;
+            for (int x = 0; x < D * D; ++x) {
+                const cd u = c.unit[size_t(i) * D * D + x];
+                e.fmats.push_back(make_double2(u.real(), u.imag()));
+            }
+        }
+        e.pbar.insert(e.pbar.end(), c.pbar.begin(), c.pbar.end());
+        e.chans.push_back(ch);
+    }
+    if (e.pool.size() > size_t(1) << 28 || e.fmats.size() > size_t(1) << 28)
+        return fail(QS_ERR_NOT_SUPPORTED, "batched circuit too large");
     return QS_OK;
 }
 
@@ -3103,13 +3008,11 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
     std::memset(r, 0, sizeof(*r));
     r->max_fuse_used = f;
 
-    // ---- per-circuit plans (threads over circuits), then concatenated
+    // ---- per-circuit plans (threads over circuits, cached per circuit and
+    // width), then concatenated
     std::vector<BatchPlanCircuit> plans(n_items);
     std::vector<qs::BatchCircuit> circs(n_items);
     struct CircPieces {
-        std::vector<qs::BatchSweep> sweeps;
-        std::vector<qs::BatchGate> gates;  // mat: local offset into pool
-        std::vector<float2> pool;
         std::vector<double> readout;
         qs_status status = QS_OK;
         std::string error;
@@ -3132,7 +3035,6 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
         const qs_batch_item &I = items[it];
         BatchPlanCircuit &P = plans[it];
         CircPieces &X = pieces[it];
-        P.circuit_index = it;
         qs_status stt = circuit_model(I.circuit, &P.me);
         if (stt != QS_OK) {
             X.status = stt;
@@ -3155,16 +3057,8 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
         }
         const int n = P.m->n;
         P.resident = n <= qs::kBatchLdsQubits;
-        const int n_ops = int(P.m->ops.size());
-        P.default_mats.assign(n_ops, nullptr);
-        for (int o = 0; o < n_ops; ++o) {
-            if (P.m->kind[o] == QS_OP_GATE) P.default_mats[o] = P.m->gate_mat[o];
-            else {
-                const ChannelInfo &c = P.m->channels[P.m->channel_of_op[o]];
-                P.default_mats[o] = fast_pick_matrix(c, c.default_pick);
-            }
-        }
         qs::BatchCircuit &C = circs[it];
+        std::memset(&C, 0, sizeof(C));
         C.n = n;
         C.resident = P.resident ? 1 : 0;
         C.n_samples = I.n_samples;
@@ -3175,291 +3069,242 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
             for (int q = 0; q < n; ++q) X.readout.push_back(ro.e1[q]);
         }
         const BatchPlanKey bkey{P.me->id, f};
-        std::shared_ptr<const BatchPlanEntry> hit;
-        batch_plan_lookup(bkey, &hit);
-        if (!hit) {
+        batch_plan_lookup(bkey, &P.plan);
+        if (!P.plan) {
+            const int n_ops = int(P.m->ops.size());
+            std::vector<const cd *> default_mats(size_t(n_ops), nullptr);
+            for (int o = 0; o < n_ops; ++o) {
+                if (P.m->kind[size_t(o)] == QS_OP_GATE) default_mats[size_t(o)] = P.m->gate_mat[size_t(o)];
+                else {
+                    const ChannelInfo &c = P.m->channels[size_t(P.m->channel_of_op[size_t(o)])];
+                    default_mats[size_t(o)] = fast_pick_matrix(c, c.default_pick);
+                }
+            }
             auto e = std::make_shared<BatchPlanEntry>();
-            const qs_status ps = plan_batched_circuit(*P.m, P.default_mats, f, P.resident, I.n_traj, *e);
+            const qs_status ps = plan_batched_circuit(*P.m, default_mats, f, P.resident, I.n_traj, *e);
             if (ps != QS_OK) {
                 X.status = ps;
                 X.error = g_last_error;
                 return;
             }
             batch_plan_insert(bkey, e);
-            hit = std::move(e);
+            P.plan = std::move(e);
         }
-        P.blocks = hit->blocks;
-        P.op_block = hit->op_block;
-        P.gate_of_block = hit->gate_of_block;
-        X.sweeps = hit->sweeps;
-        X.gates = hit->gates;
-        X.pool = hit->pool;
     };
-    {
-        HostPool::get().run(size_t(n_items), 1, 16u, [&](size_t lo, size_t hi) {
-            for (size_t it = lo; it < hi; ++it) plan_one(int(it));
-        });
-    }
-    std::vector<qs::BatchSweep> sweeps;
-    std::vector<qs::BatchGate> gates;
-    std::vector<float2> pool;
-    std::vector<double> readout;
+    HostPool::get().run(size_t(n_items), 1, 16u, [&](size_t lo, size_t hi) {
+        for (size_t it = lo; it < hi; ++it) plan_one(int(it));
+    });
+    for (int it = 0; it < n_items; ++it)
+        if (pieces[it].status != QS_OK) return fail(pieces[it].status, pieces[it].error);
+
+    // ---- the launch's tables: each circuit's pieces with shifted offsets
+    size_t n_sweeps = 0, n_gates = 0, n_pool = 0, n_chans = 0, n_pbar = 0, n_members = 0, n_fmats = 0, n_ro = 0;
     int max_tiled_n = 0;
-    int64_t total_jobs = 0, total_samples = 0;
+    int64_t max_pool = 0, total_jobs = 0, total_samples = 0, total_choices = 0;
     for (int it = 0; it < n_items; ++it) {
-        CircPieces &X = pieces[it];
-        if (X.status != QS_OK) return fail(X.status, X.error);
-        BatchPlanCircuit &P = plans[it];
+        const BatchPlanEntry &E = *plans[it].plan;
         qs::BatchCircuit &C = circs[it];
-        const int gshift = int(gates.size());
-        const int pshift = int(pool.size());
-        C.s0 = int(sweeps.size());
-        for (auto S : X.sweeps) {
-            S.g0 += gshift;
-            S.g1 += gshift;
-            sweeps.push_back(S);
-        }
-        C.s1 = int(sweeps.size());
-        for (auto G : X.gates) {
-            G.mat += pshift;
-            gates.push_back(G);
-        }
-        for (auto &g : P.gate_of_block) g += gshift;
-        P.gate_base = gshift;
-        pool.insert(pool.end(), X.pool.begin(), X.pool.end());
-        if (C.readout >= 0) {
-            C.readout = int(readout.size());
-            readout.insert(readout.end(), X.readout.begin(), X.readout.end());
-        }
-        if (!P.resident) max_tiled_n = std::max(max_tiled_n, P.m->n);
+        C.s0 = int(n_sweeps);
+        C.s1 = int(n_sweeps + E.sweeps.size());
+        C.g0 = int(n_gates);
+        C.n_gates = int(E.gates.size());
+        C.ch0 = int(n_chans);
+        C.nch = int(E.chans.size());
+        C.pool0 = int(n_pool);
+        C.pool_len = int(E.pool.size());
+        if (C.readout >= 0) C.readout = int(n_ro);
+        n_sweeps += E.sweeps.size();
+        n_gates += E.gates.size();
+        n_pool += E.pool.size();
+        n_chans += E.chans.size();
+        n_pbar += E.pbar.size();
+        n_members += E.members.size();
+        n_fmats += E.fmats.size();
+        n_ro += pieces[it].readout.size();
+        if (!plans[it].resident) max_tiled_n = std::max(max_tiled_n, C.n);
+        if (!E.chans.empty()) max_pool = std::max<int64_t>(max_pool, int64_t(E.pool.size()));
         total_jobs += items[it].n_traj;
         total_samples += items[it].n_traj * int64_t(items[it].n_samples);
+        if (items[it].kraus_choices) total_choices += items[it].n_traj * int64_t(E.chans.size());
     }
-    if (pool.size() > (size_t(1) << 30)) return fail(QS_ERR_OUT_OF_MEMORY, "matrix pool too large");
+    if (n_pool > (size_t(1) << 30) || n_fmats > (size_t(1) << 30) || n_gates > (size_t(1) << 30))
+        return fail(QS_ERR_OUT_OF_MEMORY, "batched program too large");
 
-    // ---- per-trajectory draws and patched blocks, spread over host threads
-    struct JobRef {
-        int item;
-        int64_t rel;
-        double cost;
-    };
-    std::vector<JobRef> refs;
-    refs.reserve(size_t(total_jobs));
-    for (int it = 0; it < n_items; ++it)
-        for (int64_t t = 0; t < items[it].n_traj; ++t)
-            refs.push_back({it, t, double(int64_t(1) << plans[it].m->n) * double(plans[it].blocks.size())});
-    std::vector<BatchTrajOut> outs(refs.size());
-    size_t draws = 0;  // one Philox call per channel per trajectory
-    for (const auto &R : refs) draws += plans[R.item].m->channels.size();
-    // The patched blocks of job j from its picks other than the default ones.
-    auto patch_job = [&](size_t j, const std::vector<std::pair<int, const cd *>> &over,
-                         std::vector<cd> &t2) {
-        const BatchPlanCircuit &P = plans[refs[j].item];
-        std::vector<const cd *> mats = P.default_mats;
-        std::vector<int> dirty_blocks;
-        for (auto &o : over) {
-            mats[o.first] = o.second;
-            dirty_blocks.push_back(P.op_block[o.first]);
-        }
-        std::sort(dirty_blocks.begin(), dirty_blocks.end());
-        dirty_blocks.erase(std::unique(dirty_blocks.begin(), dirty_blocks.end()), dirty_blocks.end());
-        BatchTrajOut &O = outs[j];
-        for (int b : dirty_blocks) {
-            const qs::Block &B = P.blocks[b];
-            qs::fused_matrix(B.k, B.q, B.ops, P.m->ops, mats, t2.data());
-            const int D = 1 << B.k;
-            qs::BatchPatch pt;
-            pt.gate = P.gate_of_block[b];
-            pt.mat = int(O.pool.size());
-            O.pool.resize(O.pool.size() + size_t(D) * D + (D * D) % 2);
-            to_float2(D, t2.data(), O.pool.data() + pt.mat);
-            O.patches.push_back(pt);
-        }
-        std::sort(O.patches.begin(), O.patches.end(),
-                  [](const qs::BatchPatch &a, const qs::BatchPatch &b) { return a.gate < b.gate; });
-    };
-    BatchBuffers &BB = batch_buffers();
-    std::lock_guard<std::mutex> hold(BB.lock);
-    hipError_t e = hipSuccess;
-    bool drawn = false;
-    if (draws >= kDeviceDrawMin && draws <= kDeviceDrawMax) {
-        // ---- draws on the device; only the picks other than the default
-        // ones come back, and only their jobs are patched on the host
-        std::vector<std::vector<std::pair<int, const cd *>>> over_of(refs.size());
-        std::vector<int> jobs_over;
-        QS_CHECK(device_draws(items, n_items, plans, refs.size(),
-                              [&](size_t j) { return std::make_pair(refs[j].item, refs[j].rel); },
-                              draws, st, BB, [&](int j, int c, int pick) {
-                                  const BatchPlanCircuit &P = plans[refs[j].item];
-                                  const ChannelInfo &ci = P.m->channels[c];
-                                  if (over_of[j].empty()) jobs_over.push_back(j);
-                                  over_of[j].emplace_back(ci.op, fast_pick_matrix(ci, pick));
-                              }, &drawn));
-        HostPool::get().run(jobs_over.size(), 8, 16u, [&](size_t lo, size_t hi) {
-            std::vector<cd> t2(1024);
-            for (size_t x = lo; x < hi; ++x) patch_job(size_t(jobs_over[x]), over_of[jobs_over[x]], t2);
-        });
-    }
-    if (!drawn) {
-        // ---- draws on the host, spread over the worker threads in chunks of
-        // about 2048 draws
-        const unsigned nthreads = unsigned(std::min<size_t>(16, std::max<size_t>(draws / 4096, 1)));
-        const size_t chunk = std::max<size_t>(1, refs.empty() ? 1 : 2048 * refs.size() / std::max<size_t>(draws, 1));
-        HostPool::get().run(refs.size(), chunk, nthreads, [&](size_t lo, size_t hi) {
-            std::vector<cd> t2(1024);
-            std::vector<std::pair<int, const cd *>> over;  // op, matrix
-            for (size_t j = lo; j < hi; ++j) {
-                const qs_batch_item &I = items[refs[j].item];
-                const BatchPlanCircuit &P = plans[refs[j].item];
-                const uint32_t traj = uint32_t(I.traj_offset + refs[j].rel);
-                const int nch = int(P.m->channels.size());
-                int8_t *choices = I.kraus_choices ? I.kraus_choices + refs[j].rel * nch : nullptr;
-                over.clear();
-                for (int c = 0; c < nch; ++c) {
-                    const ChannelInfo &ci = P.m->channels[c];
-                    const double rr = qs::philox_uniform(I.seed, channel_draw_index(uint32_t(c)), traj,
-                                                         I.circuit_id, qs::kStreamChannel);
-                    double resid = 0.0;
-                    const int pk = select_fast(ci, rr, &resid);  // mixtures always resolve here
-                    if (choices) choices[c] = int8_t(pk);
-                    if (pk != ci.default_pick) over.emplace_back(ci.op, fast_pick_matrix(ci, pk));
-                }
-                if (!over.empty()) patch_job(j, over, t2);
-            }
-        });
-    }
     // ---- jobs (largest first, so the persistent workgroups finish together)
-    std::vector<size_t> order(refs.size());
-    for (size_t j = 0; j < order.size(); ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return refs[a].cost > refs[b].cost; });
-    std::vector<qs::BatchJob> jobs(refs.size());
-    std::vector<qs::BatchPatch> patches;
-    std::vector<int64_t> item_out_base(n_items, 0);
+    std::vector<qs::BatchJob> jobs;
+    jobs.reserve(size_t(total_jobs));
+    std::vector<double> cost;
+    cost.reserve(size_t(total_jobs));
+    int64_t blocks_applied = 0, resident_jobs = 0;
     {
-        int64_t acc = 0;
+        int64_t out = 0, ch = 0;
         for (int it = 0; it < n_items; ++it) {
-            item_out_base[it] = acc;
-            acc += items[it].n_traj * int64_t(items[it].n_samples);
+            const qs_batch_item &I = items[it];
+            const BatchPlanEntry &E = *plans[it].plan;
+            const bool rec = I.kraus_choices != nullptr;
+            for (int64_t t = 0; t < I.n_traj; ++t) {
+                qs::BatchJob J;
+                std::memset(&J, 0, sizeof(J));
+                J.circuit = it;
+                J.traj = uint32_t(I.traj_offset + t);
+                J.circ_id = I.circuit_id;
+                J.seed = I.seed;
+                J.out = out + t * I.n_samples;
+                J.choices = rec ? ch + t * int64_t(E.chans.size()) : -1;
+                jobs.push_back(J);
+                cost.push_back(double(int64_t(1) << circs[it].n) * double(E.gates.size()));
+            }
+            out += I.n_traj * int64_t(I.n_samples);
+            if (rec) ch += I.n_traj * int64_t(E.chans.size());
+            blocks_applied += I.n_traj * int64_t(E.gates.size());
+            if (plans[it].resident) resident_jobs += I.n_traj;
         }
     }
-    int64_t blocks_applied = 0, resident_jobs = 0;
-    for (size_t oi = 0; oi < order.size(); ++oi) {
-        const size_t j = order[oi];
-        const JobRef &R = refs[j];
-        const qs_batch_item &I = items[R.item];
-        qs::BatchJob &J = jobs[oi];
-        J.circuit = R.item;
-        J.traj = uint32_t(I.traj_offset + R.rel);
-        J.circ_id = I.circuit_id;
-        J.seed = I.seed;
-        J.out = item_out_base[R.item] + R.rel * I.n_samples;
-        J.p0 = int(patches.size());
-        const int64_t shift = int64_t(pool.size());
-        for (const auto &pt : outs[j].patches) patches.push_back({pt.gate, int(pt.mat + shift)});
-        pool.insert(pool.end(), outs[j].pool.begin(), outs[j].pool.end());
-        J.p1 = int(patches.size());
-        blocks_applied += int64_t(plans[R.item].blocks.size());
-        resident_jobs += plans[R.item].resident ? 1 : 0;
-        if (pool.size() > (size_t(1) << 30)) return fail(QS_ERR_OUT_OF_MEMORY, "matrix pool too large");
+    {
+        std::vector<size_t> order(jobs.size());
+        for (size_t j = 0; j < order.size(); ++j) order[j] = j;
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+        std::vector<qs::BatchJob> sorted(jobs.size());
+        for (size_t j = 0; j < order.size(); ++j) sorted[j] = jobs[order[j]];
+        jobs.swap(sorted);
     }
-    const auto t_plan = std::chrono::steady_clock::now();
-    r->plan_seconds = std::chrono::duration<double>(t_plan - t0).count();
     r->jobs = int64_t(jobs.size());
     r->resident_jobs = resident_jobs;
     r->gate_blocks = blocks_applied;
     if (jobs.empty()) {
-        r->host_seconds = r->plan_seconds;
+        r->plan_seconds = r->host_seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         return QS_OK;
     }
 
-    // ---- device buffers (one allocation, one upload)
+    // ---- device buffers (one program allocation, one upload)
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
     const size_t b_circ = align(sizeof(qs::BatchCircuit) * circs.size());
-    const size_t b_sweep = align(sizeof(qs::BatchSweep) * std::max<size_t>(sweeps.size(), 1));
-    const size_t b_gate = align(sizeof(qs::BatchGate) * std::max<size_t>(gates.size(), 1));
-    const size_t b_patch = align(sizeof(qs::BatchPatch) * std::max<size_t>(patches.size(), 1));
+    const size_t b_sweep = align(sizeof(qs::BatchSweep) * std::max<size_t>(n_sweeps, 1));
+    const size_t b_gate = align(sizeof(qs::BatchGate) * std::max<size_t>(n_gates, 1));
     const size_t b_job = align(sizeof(qs::BatchJob) * jobs.size());
-    const size_t b_pool = align(sizeof(float2) * std::max<size_t>(pool.size(), 1));
-    const size_t b_ro = align(sizeof(double) * std::max<size_t>(readout.size(), 1));
-    const size_t b_out = align(sizeof(uint64_t) * std::max<int64_t>(total_samples, 1));
-    const size_t total = b_circ + b_sweep + b_gate + b_patch + b_job + b_pool + b_ro + b_out;
+    const size_t b_pool = align(sizeof(float2) * std::max<size_t>(n_pool, 1));
+    const size_t b_ro = align(sizeof(double) * std::max<size_t>(n_ro, 1));
+    const size_t b_chan = align(sizeof(qs::BatchChannel) * std::max<size_t>(n_chans, 1));
+    const size_t b_pbar = align(sizeof(double) * std::max<size_t>(n_pbar, 1));
+    const size_t b_mem = align(sizeof(qs::BatchMember) * std::max<size_t>(n_members, 1));
+    const size_t b_fmat = align(sizeof(double2) * std::max<size_t>(n_fmats, 1));
+    const size_t b_out = align(sizeof(uint64_t) * size_t(std::max<int64_t>(total_samples, 1)));
+    const size_t b_choice = align(size_t(std::max<int64_t>(total_choices, 1)));
+    const size_t prog_bytes = b_circ + b_sweep + b_gate + b_job + b_pool + b_ro + b_chan + b_pbar + b_mem + b_fmat;
+    const size_t total = prog_bytes + b_out + b_choice;
     const int grid = qs::batched_grid();
     const size_t slot_amps = max_tiled_n > 0 ? size_t(1) << max_tiled_n : 0;
     const size_t b_slots = sizeof(float2) * slot_amps * size_t(grid);
-    auto grow = [&](size_t need_prog, size_t need_slots) -> qs_status {
+    const size_t patched_stride = (size_t(max_pool) + 63) & ~size_t(63);
+    const size_t b_patched = sizeof(float2) * std::max<size_t>(patched_stride, 64) * size_t(grid);
+    BatchBuffers &BB = batch_buffers();
+    std::lock_guard<std::mutex> hold(BB.lock);
+    hipError_t e = hipSuccess;
+    auto grow_dev = [&](void **ptr, size_t *cap, size_t need, const char *what) -> qs_status {
+        if (need <= *cap) return QS_OK;
+        if (*ptr) (void)hipFree(*ptr);
+        *ptr = nullptr;
+        *cap = 0;
         size_t free_b = 0, total_b = 0;
-        if (need_prog > BB.prog_cap || need_slots > BB.slots_cap || need_prog > BB.host_cap) {
-            if ((e = hipMemGetInfo(&free_b, &total_b)) != hipSuccess)
-                return fail(QS_ERR_DEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+        if ((e = hipMemGetInfo(&free_b, &total_b)) != hipSuccess)
+            return fail(QS_ERR_DEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+        if (free_b < need) return fail(QS_ERR_OUT_OF_MEMORY, std::string("batched ") + what + " do not fit");
+        if (hipMalloc(ptr, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(QS_ERR_OUT_OF_MEMORY, std::string("allocating batched ") + what + " failed");
         }
-        if (need_prog > BB.prog_cap) {
-            if (BB.prog) (void)hipFree(BB.prog);
-            BB.prog = nullptr;
-            BB.prog_cap = 0;
-            if (free_b < need_prog) return fail(QS_ERR_OUT_OF_MEMORY, "batched program does not fit");
-            if (hipMalloc(&BB.prog, need_prog) != hipSuccess) {
-                (void)hipGetLastError();
-                return fail(QS_ERR_OUT_OF_MEMORY, "allocating the batched program failed");
-            }
-            BB.prog_cap = need_prog;
-        }
-        if (need_prog > BB.host_cap) {
-            if (BB.host) (void)hipHostFree(BB.host);
-            BB.host = nullptr;
-            BB.host_cap = 0;
-            if (hipHostMalloc(reinterpret_cast<void **>(&BB.host), need_prog, hipHostMallocDefault) != hipSuccess) {
-                (void)hipGetLastError();
-                return fail(QS_ERR_OUT_OF_MEMORY, "allocating pinned staging failed");
-            }
-            BB.host_cap = need_prog;
-        }
-        if (need_slots > BB.slots_cap) {
-            if (BB.slots) (void)hipFree(BB.slots);
-            BB.slots = nullptr;
-            BB.slots_cap = 0;
-            (void)hipMemGetInfo(&free_b, &total_b);
-            if (free_b < need_slots) return fail(QS_ERR_OUT_OF_MEMORY, "batched state slots do not fit");
-            if (hipMalloc(&BB.slots, need_slots) != hipSuccess) {
-                (void)hipGetLastError();
-                return fail(QS_ERR_OUT_OF_MEMORY, "allocating batched state slots failed");
-            }
-            BB.slots_cap = need_slots;
-        }
+        *cap = need;
         return QS_OK;
     };
-    QS_CHECK(grow(total, b_slots));
+    QS_CHECK(grow_dev(reinterpret_cast<void **>(&BB.prog), &BB.prog_cap, total, "program buffers"));
+    QS_CHECK(grow_dev(reinterpret_cast<void **>(&BB.slots), &BB.slots_cap, b_slots, "state slots"));
+    QS_CHECK(grow_dev(reinterpret_cast<void **>(&BB.patched), &BB.patched_cap, b_patched, "patched matrices"));
+    if (total > BB.host_cap) {
+        if (BB.host) (void)hipHostFree(BB.host);
+        BB.host = nullptr;
+        BB.host_cap = 0;
+        if (hipHostMalloc(reinterpret_cast<void **>(&BB.host), total, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(QS_ERR_OUT_OF_MEMORY, "allocating pinned staging failed");
+        }
+        BB.host_cap = total;
+    }
     char *dbuf = BB.prog;
-    float2 *slots = b_slots ? BB.slots : nullptr;
     char *hostp = BB.host;
-    size_t off = 0;
-    auto put = [&](const void *src, size_t bytes, size_t cap) {
-        if (bytes) std::memcpy(hostp + off, src, bytes);
-        const size_t at = off;
-        off += cap;
-        return at;
-    };
-    const size_t o_circ = put(circs.data(), sizeof(qs::BatchCircuit) * circs.size(), b_circ);
-    const size_t o_sweep = put(sweeps.data(), sizeof(qs::BatchSweep) * sweeps.size(), b_sweep);
-    const size_t o_gate = put(gates.data(), sizeof(qs::BatchGate) * gates.size(), b_gate);
-    const size_t o_patch = put(patches.data(), sizeof(qs::BatchPatch) * patches.size(), b_patch);
-    const size_t o_job = put(jobs.data(), sizeof(qs::BatchJob) * jobs.size(), b_job);
-    const size_t o_pool = put(pool.data(), sizeof(float2) * pool.size(), b_pool);
-    const size_t o_ro = put(readout.data(), sizeof(double) * readout.size(), b_ro);
-    const size_t o_out = off;
+    // the program, written straight into the pinned staging
+    size_t o_circ = 0, o_sweep = o_circ + b_circ, o_gate = o_sweep + b_sweep, o_job = o_gate + b_gate,
+           o_pool = o_job + b_job, o_ro = o_pool + b_pool, o_chan = o_ro + b_ro, o_pbar = o_chan + b_chan,
+           o_mem = o_pbar + b_pbar, o_fmat = o_mem + b_mem, o_out = o_fmat + b_fmat, o_choice = o_out + b_out;
+    std::memcpy(hostp + o_circ, circs.data(), sizeof(qs::BatchCircuit) * circs.size());
+    std::memcpy(hostp + o_job, jobs.data(), sizeof(qs::BatchJob) * jobs.size());
+    {
+        auto *sw = reinterpret_cast<qs::BatchSweep *>(hostp + o_sweep);
+        auto *gt = reinterpret_cast<qs::BatchGate *>(hostp + o_gate);
+        auto *pl = reinterpret_cast<float2 *>(hostp + o_pool);
+        auto *ro = reinterpret_cast<double *>(hostp + o_ro);
+        auto *chn = reinterpret_cast<qs::BatchChannel *>(hostp + o_chan);
+        auto *pb = reinterpret_cast<double *>(hostp + o_pbar);
+        auto *mem = reinterpret_cast<qs::BatchMember *>(hostp + o_mem);
+        auto *fm = reinterpret_cast<double2 *>(hostp + o_fmat);
+        size_t gs = 0, ps = 0, bs = 0, ms = 0, fs = 0;
+        for (int it = 0; it < n_items; ++it) {
+            const BatchPlanEntry &E = *plans[it].plan;
+            const int gshift = int(gs), pshift = int(ps), bshift = int(bs), mshift = int(ms), fshift = int(fs);
+            for (qs::BatchSweep S : E.sweeps) {
+                S.g0 += gshift;
+                S.g1 += gshift;
+                *sw++ = S;
+            }
+            for (qs::BatchGate G : E.gates) {
+                G.mat += pshift;
+                G.m0 += mshift;
+                G.m1 += mshift;
+                *gt++ = G;
+            }
+            for (qs::BatchChannel c : E.chans) {
+                c.pbar += bshift;
+                c.unit += fshift;
+                *chn++ = c;
+            }
+            for (qs::BatchMember M : E.members) {
+                if (M.src >= 0) M.src += fshift;
+                *mem++ = M;
+            }
+            if (!E.pool.empty()) std::memcpy(pl + ps, E.pool.data(), sizeof(float2) * E.pool.size());
+            if (!E.pbar.empty()) std::memcpy(pb + bs, E.pbar.data(), sizeof(double) * E.pbar.size());
+            if (!E.fmats.empty()) std::memcpy(fm + fs, E.fmats.data(), sizeof(double2) * E.fmats.size());
+            if (circs[it].readout >= 0)
+                std::memcpy(ro + circs[it].readout, pieces[it].readout.data(),
+                            sizeof(double) * pieces[it].readout.size());
+            gs += E.gates.size();
+            ps += E.pool.size();
+            bs += E.pbar.size();
+            ms += E.members.size();
+            fs += E.fmats.size();
+        }
+    }
+    const auto t_plan = std::chrono::steady_clock::now();
+    r->plan_seconds = std::chrono::duration<double>(t_plan - t0).count();
     qs_status status = QS_OK;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     do {
-        if ((e = hipMemcpyAsync(dbuf, hostp, o_out, hipMemcpyHostToDevice, st)) != hipSuccess) break;
+        if ((e = hipMemcpyAsync(dbuf, hostp, prog_bytes, hipMemcpyHostToDevice, st)) != hipSuccess) break;
         qs::BatchArgs A;
         A.circs = reinterpret_cast<const qs::BatchCircuit *>(dbuf + o_circ);
         A.sweeps = reinterpret_cast<const qs::BatchSweep *>(dbuf + o_sweep);
         A.gates = reinterpret_cast<const qs::BatchGate *>(dbuf + o_gate);
-        A.patches = reinterpret_cast<const qs::BatchPatch *>(dbuf + o_patch);
         A.jobs = reinterpret_cast<const qs::BatchJob *>(dbuf + o_job);
         A.mats = reinterpret_cast<const float2 *>(dbuf + o_pool);
         A.readout = reinterpret_cast<const double *>(dbuf + o_ro);
-        A.slots = slots;
+        A.chans = reinterpret_cast<const qs::BatchChannel *>(dbuf + o_chan);
+        A.pbar = reinterpret_cast<const double *>(dbuf + o_pbar);
+        A.members = reinterpret_cast<const qs::BatchMember *>(dbuf + o_mem);
+        A.fmats = reinterpret_cast<const double2 *>(dbuf + o_fmat);
+        A.patched = BB.patched;
+        A.patched_stride = int64_t(patched_stride);
+        A.choices = reinterpret_cast<int8_t *>(dbuf + o_choice);
+        A.slots = b_slots ? BB.slots : nullptr;
         A.slot_amps = int64_t(slot_amps);
         A.out = reinterpret_cast<uint64_t *>(dbuf + o_out);
         A.n_jobs = int(jobs.size());
@@ -3471,9 +3316,15 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
         }
         if ((e = qs::launch_batched(A, std::min<int64_t>(grid, int64_t(jobs.size())), st)) != hipSuccess) break;
         if (timing && (e = hipEventRecord(ev1, st)) != hipSuccess) break;
-        // samples come back into the pinned staging (its program part has been sent)
-        if ((e = hipMemcpyAsync(hostp + o_out, dbuf + o_out, sizeof(uint64_t) * size_t(total_samples),
+        // samples and picks come back into the pinned staging (its program
+        // part has been sent)
+        if (total_samples > 0 &&
+            (e = hipMemcpyAsync(hostp + o_out, dbuf + o_out, sizeof(uint64_t) * size_t(total_samples),
                                 hipMemcpyDeviceToHost, st)) != hipSuccess)
+            break;
+        if (total_choices > 0 &&
+            (e = hipMemcpyAsync(hostp + o_choice, dbuf + o_choice, size_t(total_choices), hipMemcpyDeviceToHost,
+                                st)) != hipSuccess)
             break;
         if ((e = hipStreamSynchronize(st)) != hipSuccess) break;
         if (timing) {
@@ -3488,11 +3339,20 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (status != QS_OK) return status;
-    const uint64_t *out = reinterpret_cast<const uint64_t *>(hostp + o_out);
-    for (int it = 0; it < n_items; ++it) {
-        const int64_t cnt = items[it].n_traj * int64_t(items[it].n_samples);
-        if (cnt > 0)
-            std::memcpy(items[it].bitstrings, out + item_out_base[it], sizeof(uint64_t) * size_t(cnt));
+    {
+        const uint64_t *out = reinterpret_cast<const uint64_t *>(hostp + o_out);
+        const int8_t *chs = reinterpret_cast<const int8_t *>(hostp + o_choice);
+        int64_t ob = 0, cb = 0;
+        for (int it = 0; it < n_items; ++it) {
+            const int64_t cnt = items[it].n_traj * int64_t(items[it].n_samples);
+            if (cnt > 0) std::memcpy(items[it].bitstrings, out + ob, sizeof(uint64_t) * size_t(cnt));
+            ob += cnt;
+            if (items[it].kraus_choices) {
+                const int64_t nc = items[it].n_traj * int64_t(plans[it].plan->chans.size());
+                if (nc > 0) std::memcpy(items[it].kraus_choices, chs + cb, size_t(nc));
+                cb += nc;
+            }
+        }
     }
     r->host_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return QS_OK;
