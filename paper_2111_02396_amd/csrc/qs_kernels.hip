@@ -848,37 +848,40 @@ __global__ __launch_bounds__(64) void select_branch(SelectArgs a) {
 // k = 5 it is the global copy.  Fragments for the MFMA gates are staged per
 // block.  `then` runs after the block's arithmetic and before the trailing
 // barrier, which lets the next block reuse the staging area.
-template <class Then>
+template <int NT, class Then>
 __device__ __forceinline__ void batched_gate(float2 *__restrict__ sd, float *__restrict__ frag,
                                              const BatchGate &g, const float2 *m, int tb, Then then) {
     int lt[kMaxGateQubits], tab[kMaxTileBits];
 #pragma unroll
     for (int b = 0; b < kMaxGateQubits; ++b) lt[b] = g.lt[b];
+    // MFMA paths need at least one 16-group batch per wavefront at 512
+    // work-items (k = 3: 10 bits, k = 4: 11); the 256-work-item form keeps
+    // the same rule, so a job's arithmetic does not depend on the form
     if (g.k == 1) {
         gate_tables<1, PlainTile>(lt, tab);
-        tile_gate_small<1, PlainTile, kBlock, true>(sd, m, lt, tab, tb);
+        tile_gate_small<1, PlainTile, NT, true>(sd, m, lt, tab, tb);
     } else if (g.k == 2) {
         gate_tables<2, PlainTile>(lt, tab);
-        tile_gate_small<2, PlainTile, kBlock, true>(sd, m, lt, tab, tb);
+        tile_gate_small<2, PlainTile, NT, true>(sd, m, lt, tab, tb);
     } else if (g.k == 3 && tb >= 10) {
         gate_tables<3, PlainTile>(lt, tab);
-        stage_frag3(frag, m, tab);
+        stage_frag3<NT>(frag, m, tab);
         __syncthreads();
-        tile_gate_mfma3<PlainTile>(sd, frag, tab, tb);
-    } else if (g.k == 4 && tb >= 10) {
+        tile_gate_mfma3<PlainTile, NT>(sd, frag, tab, tb);
+    } else if (g.k == 4 && tb >= 11) {
         gate_tables<4, PlainTile>(lt, tab);
-        stage_frag4(frag, m, tab);
+        stage_frag4<NT>(frag, m, tab);
         __syncthreads();
-        tile_gate_mfma4<PlainTile>(sd, frag, tab, tb);
+        tile_gate_mfma4<PlainTile, NT>(sd, frag, tab, tb);
     } else if (g.k == 3) {
-        tile_gate_valu<3, PlainTile>(sd, m, lt, tb);
+        tile_gate_valu<3, PlainTile, NT>(sd, m, lt, tb);
     } else if (g.k == 4) {
-        tile_gate_valu<4, PlainTile>(sd, m, lt, tb);
+        tile_gate_valu<4, PlainTile, NT>(sd, m, lt, tb);
     } else {
         float2 *mm = reinterpret_cast<float2 *>(frag);
-        for (int i = threadIdx.x; i < 1024; i += kBlock) mm[i] = m[i];
+        for (int i = threadIdx.x; i < 1024; i += NT) mm[i] = m[i];
         __syncthreads();
-        tile_gate_valu<5, PlainTile>(sd, mm, lt, tb);
+        tile_gate_valu<5, PlainTile, NT>(sd, mm, lt, tb);
     }
     then();
     __syncthreads();
@@ -926,6 +929,7 @@ __device__ __forceinline__ bool batched_holds(const BatchedRef &r) {
 // of the double-buffered LDS copy `raw` after block i's arithmetic) and the
 // descriptor of block i + 2 is loaded.  Workgroup barriers on gfx950 do not
 // wait for outstanding global loads, so both overlap the block's work.
+template <int NT>
 __device__ __forceinline__ void batched_blocks(const BatchArgs &A, const uint32_t *mask, const float2 *mine,
                                const BatchCircuit &C, int g0, int g1, float2 *__restrict__ sd,
                                float *__restrict__ frag, float2 *raw, int tb) {
@@ -944,7 +948,7 @@ __device__ __forceinline__ void batched_blocks(const BatchArgs &A, const uint32_
         if (gi + 2 < g1) after = batched_ref(A, mask, mine, C, gi + 2);
         float2 *next_raw = raw + 256 * (buf ^ 1);
         const float2 *m = cur.g.k <= 4 ? raw + 256 * buf : cur.m;
-        batched_gate(sd, frag, cur.g, m, tb, [&] {
+        batched_gate<NT>(sd, frag, cur.g, m, tb, [&] {
             if (put1) next_raw[threadIdx.x] = e1;
         });
         cur = nxt;
@@ -1096,7 +1100,9 @@ __device__ __forceinline__ void fuse_patched(const BatchArgs &A, const BatchJob 
 // the workgroup samples the final state (inverse CDF over 256 contiguous
 // chunks whose FP64 sums are scanned in order; readout flips as in
 // sample_draw).
-__global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
+template <int NT>
+__global__ __launch_bounds__(NT) void run_batched(BatchArgs A) {
+    constexpr int LNT = ilog2(NT);
     extern __shared__ float2 smem[];
     float2 *sd = smem;                                                   // 2^13 amplitudes
     float *frag = reinterpret_cast<float *>(smem + (1 << kBatchLdsQubits));  // 2048 floats
@@ -1114,9 +1120,9 @@ __global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
         // 2's fast path), recorded when asked; a pick other than the default
         // one flags its block
         const int words = (C.n_gates + 31) >> 5;
-        for (int w = threadIdx.x; w < words; w += kBlock) mask[w] = 0u;
+        for (int w = threadIdx.x; w < words; w += NT) mask[w] = 0u;
         __syncthreads();
-        for (int c = threadIdx.x; c < C.nch; c += kBlock) {
+        for (int c = threadIdx.x; c < C.nch; c += NT) {
             const BatchChannel ch = A.chans[C.ch0 + c];
             const int pick = draw_pick(A.pbar + ch.pbar, ch.nk,
                                        philox_uniform(J.seed, uint32_t(c), J.traj, J.circ_id, kStreamChannel));
@@ -1125,12 +1131,13 @@ __global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
         }
         __syncthreads();
         // the flagged blocks' matrices with the job's picks, one wavefront
-        // per block (workspace: a quarter of the LDS state area each)
+        // per block, by the first four wavefronts (workspace: a quarter of
+        // the LDS state area each)
         {
             const int wave = int(threadIdx.x) >> 6;
             double2 *ws = reinterpret_cast<double2 *>(sd) + wave * 1024;
             double2 *ush = reinterpret_cast<double2 *>(raw) + wave * 64;
-            for (int w = wave; w < words; w += kBlock / 64) {
+            for (int w = wave; wave < 4 && w < words; w += 4) {
                 uint32_t bits = __builtin_amdgcn_readfirstlane(mask[w]);
                 while (bits) {
                     const int b = __builtin_ctz(bits);
@@ -1146,20 +1153,20 @@ __global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
             __syncthreads();
         }
         float2 *state = C.resident ? sd : slot;
-        for (int i = threadIdx.x; i < dim; i += kBlock)
+        for (int i = threadIdx.x; i < dim; i += NT)
             state[i] = make_float2(i == 0 ? 1.f : 0.f, 0.f);
         __syncthreads();
         for (int si = C.s0; si < C.s1; ++si) {
             const BatchSweep &S = A.sweeps[si];
             if (C.resident) {
-                batched_blocks(A, mask, mine, C, S.g0, S.g1, sd, frag, raw, n);
+                batched_blocks<NT>(A, mask, mine, C, S.g0, S.g1, sd, frag, raw, n);
                 continue;
             }
             // tiled: one pass over the slot, tile by tile
             const int tb = S.tb;
-            const int R = (1 << tb) / kBlock;
+            const int R = (1 << tb) / NT;
             int off_tid = 0;
-            for (int b = 0; b < 8; ++b)
+            for (int b = 0; b < LNT; ++b)
                 if ((threadIdx.x >> b) & 1) off_tid |= 1 << S.pos[b];
             const int n_tiles = dim >> tb;
             for (int t = 0; t < n_tiles; ++t) {
@@ -1171,22 +1178,23 @@ __global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
                 base += off_tid;
                 for (int r = 0; r < R; ++r) {
                     int o = 0;
-                    for (int b = 8; b < tb; ++b)
-                        if (((r << 8) >> b) & 1) o |= 1 << S.pos[b];
-                    sd[threadIdx.x + (r << 8)] = slot[base + o];
+                    for (int b = LNT; b < tb; ++b)
+                        if (((r << LNT) >> b) & 1) o |= 1 << S.pos[b];
+                    sd[threadIdx.x + (r << LNT)] = slot[base + o];
                 }
                 __syncthreads();
-                batched_blocks(A, mask, mine, C, S.g0, S.g1, sd, frag, raw, tb);
+                batched_blocks<NT>(A, mask, mine, C, S.g0, S.g1, sd, frag, raw, tb);
                 for (int r = 0; r < R; ++r) {
                     int o = 0;
-                    for (int b = 8; b < tb; ++b)
-                        if (((r << 8) >> b) & 1) o |= 1 << S.pos[b];
-                    slot[base + o] = sd[threadIdx.x + (r << 8)];
+                    for (int b = LNT; b < tb; ++b)
+                        if (((r << LNT) >> b) & 1) o |= 1 << S.pos[b];
+                    slot[base + o] = sd[threadIdx.x + (r << LNT)];
                 }
                 __syncthreads();
             }
         }
-        // sampling: chunk c = amplitudes [c*L, (c+1)*L), L = dim / 256 (>= 1)
+        // sampling: chunk c = amplitudes [c*L, (c+1)*L), L = dim / 256 (>= 1),
+        // the same 256 chunks at either group size
         const int L = dim >= kBlock ? dim / kBlock : 1;
         const int chunks = dim >= kBlock ? kBlock : dim;
         double acc = 0.0;
@@ -1196,7 +1204,7 @@ __global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
                 acc = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), acc));
             }
         }
-        part[threadIdx.x] = acc;
+        if (int(threadIdx.x) < kBlock) part[threadIdx.x] = acc;
         __syncthreads();
         if (threadIdx.x == 0) {
             double run = 0.0;
@@ -1207,7 +1215,7 @@ __global__ __launch_bounds__(kBlock) void run_batched(BatchArgs A) {
         }
         __syncthreads();
         const double N = part[chunks - 1];
-        for (int smp = threadIdx.x; smp < C.n_samples; smp += kBlock) {
+        for (int smp = threadIdx.x; smp < C.n_samples; smp += NT) {
             const double target = philox_uniform(J.seed, uint32_t(smp), J.traj, J.circ_id, kStreamMeasure) * N;
             int lo = 0, hi = chunks;
             while (lo < hi) {
@@ -1853,14 +1861,23 @@ int batched_grid() {
     return device_cus() * (per_cu < 1 ? 1 : per_cu);
 }
 
+// Launches with no more jobs than CUs run one 512-work-item group per job
+// (eight wavefronts share each block's work, twice the 256-work-item
+// form's); larger ones run two 256-work-item groups per CU.  The grid never
+// exceeds batched_grid(), which sizes the per-workgroup buffers.
 hipError_t launch_batched(const BatchArgs &a, int grid, hipStream_t st) {
     const size_t lds = sizeof(float2) * ((size_t(1) << kBatchLdsQubits) + 1536);
-    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(&run_batched),
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                       int(lds));
-    if (attr != hipSuccess) return attr;
-    if (grid < 1) return hipErrorInvalidValue;
-    run_batched<<<unsigned(grid), kBlock, lds, st>>>(a);
+    static const hipError_t attr256 = hipFuncSetAttribute(reinterpret_cast<const void *>(&run_batched<256>),
+                                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    static const hipError_t attr512 = hipFuncSetAttribute(reinterpret_cast<const void *>(&run_batched<512>),
+                                                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (attr256 != hipSuccess) return attr256;
+    if (attr512 != hipSuccess) return attr512;
+    if (grid < 1 || a.n_jobs < 1) return hipErrorInvalidValue;
+    if (a.n_jobs <= device_cus() && a.n_jobs <= grid)
+        run_batched<512><<<unsigned(a.n_jobs), 512, lds, st>>>(a);
+    else
+        run_batched<256><<<unsigned(grid), 256, lds, st>>>(a);
     return hipGetLastError();
 }
 
