@@ -844,13 +844,16 @@ __global__ __launch_bounds__(64) void select_branch(SelectArgs a) {
 // ---------------------------------------------------------------- batched
 
 // One fused block on amplitudes held in LDS (a whole resident state, or a
-// tile).  For k <= 4, `m` is the block's matrix already copied to LDS; for
-// k = 5 it is the global copy.  Fragments for the MFMA gates are staged per
+// tile).  For k <= 4, `lm` is the block's matrix already copied to LDS; for
+// k = 5, `gm` is the global copy (two pointers, so that LDS reads compile
+// to LDS instructions rather than flat ones, which would wait for every
+// global load in flight).  Fragments for the MFMA gates are staged per
 // block.  `then` runs after the block's arithmetic and before the trailing
 // barrier, which lets the next block reuse the staging area.
 template <int NT, class Then>
 __device__ __forceinline__ void batched_gate(float2 *__restrict__ sd, float *__restrict__ frag,
-                                             const BatchGate &g, const float2 *m, int tb, Then then) {
+                                             const BatchGate &g, const float2 *lm, const float2 *gm, int tb,
+                                             Then then) {
     int lt[kMaxGateQubits], tab[kMaxTileBits];
 #pragma unroll
     for (int b = 0; b < kMaxGateQubits; ++b) lt[b] = g.lt[b];
@@ -859,27 +862,27 @@ __device__ __forceinline__ void batched_gate(float2 *__restrict__ sd, float *__r
     // the same rule, so a job's arithmetic does not depend on the form
     if (g.k == 1) {
         gate_tables<1, PlainTile>(lt, tab);
-        tile_gate_small<1, PlainTile, NT, true>(sd, m, lt, tab, tb);
+        tile_gate_small<1, PlainTile, NT, true>(sd, lm, lt, tab, tb);
     } else if (g.k == 2) {
         gate_tables<2, PlainTile>(lt, tab);
-        tile_gate_small<2, PlainTile, NT, true>(sd, m, lt, tab, tb);
+        tile_gate_small<2, PlainTile, NT, true>(sd, lm, lt, tab, tb);
     } else if (g.k == 3 && tb >= 10) {
         gate_tables<3, PlainTile>(lt, tab);
-        stage_frag3<NT>(frag, m, tab);
+        stage_frag3<NT>(frag, lm, tab);
         __syncthreads();
         tile_gate_mfma3<PlainTile, NT>(sd, frag, tab, tb);
     } else if (g.k == 4 && tb >= 11) {
         gate_tables<4, PlainTile>(lt, tab);
-        stage_frag4<NT>(frag, m, tab);
+        stage_frag4<NT>(frag, lm, tab);
         __syncthreads();
         tile_gate_mfma4<PlainTile, NT>(sd, frag, tab, tb);
     } else if (g.k == 3) {
-        tile_gate_valu<3, PlainTile, NT>(sd, m, lt, tb);
+        tile_gate_valu<3, PlainTile, NT>(sd, lm, lt, tb);
     } else if (g.k == 4) {
-        tile_gate_valu<4, PlainTile, NT>(sd, m, lt, tb);
+        tile_gate_valu<4, PlainTile, NT>(sd, lm, lt, tb);
     } else {
         float2 *mm = reinterpret_cast<float2 *>(frag);
-        for (int i = threadIdx.x; i < 1024; i += NT) mm[i] = m[i];
+        for (int i = threadIdx.x; i < 1024; i += NT) mm[i] = gm[i];
         __syncthreads();
         tile_gate_valu<5, PlainTile, NT>(sd, mm, lt, tb);
     }
@@ -947,8 +950,7 @@ __device__ __forceinline__ void batched_blocks(const BatchArgs &A, const uint32_
         BatchedRef after = nxt;
         if (gi + 2 < g1) after = batched_ref(A, mask, mine, C, gi + 2);
         float2 *next_raw = raw + 256 * (buf ^ 1);
-        const float2 *m = cur.g.k <= 4 ? raw + 256 * buf : cur.m;
-        batched_gate<NT>(sd, frag, cur.g, m, tb, [&] {
+        batched_gate<NT>(sd, frag, cur.g, raw + 256 * buf, cur.m, tb, [&] {
             if (put1) next_raw[threadIdx.x] = e1;
         });
         cur = nxt;
@@ -1095,11 +1097,11 @@ __device__ __forceinline__ void fuse_patched(const BatchArgs &A, const BatchJob 
 }
 
 // Persistent launch: each workgroup takes jobs blockIdx.x, + gridDim.x, ...
-// A job is one trajectory: the state starts as |0...0>, the circuit's blocks
-// run with this trajectory's patched matrices in place of the defaults, and
-// the workgroup samples the final state (inverse CDF over 256 contiguous
-// chunks whose FP64 sums are scanned in order; readout flips as in
-// sample_draw).
+// A job is one trajectory: its channels are drawn, the blocks its picks
+// change are rebuilt, the state starts as |0...0>, the circuit's blocks run
+// with the job's matrices, and the workgroup samples the final state
+// (inverse CDF over 256 contiguous chunks whose FP64 sums are scanned in a
+// fixed order; readout flips as in sample_draw).
 template <int NT>
 __global__ __launch_bounds__(NT) void run_batched(BatchArgs A) {
     constexpr int LNT = ilog2(NT);
@@ -1152,9 +1154,14 @@ __global__ __launch_bounds__(NT) void run_batched(BatchArgs A) {
             // is needed anywhere in this kernel.
             __syncthreads();
         }
-        float2 *state = C.resident ? sd : slot;
-        for (int i = threadIdx.x; i < dim; i += NT)
-            state[i] = make_float2(i == 0 ? 1.f : 0.f, 0.f);
+        // the state: LDS (resident) or the workgroup's slot, each accessed
+        // through its own pointer so that LDS accesses stay LDS instructions
+        const bool res = C.resident != 0;
+        for (int i = threadIdx.x; i < dim; i += NT) {
+            const float2 z = make_float2(i == 0 ? 1.f : 0.f, 0.f);
+            if (res) sd[i] = z;
+            else slot[i] = z;
+        }
         __syncthreads();
         for (int si = C.s0; si < C.s1; ++si) {
             const BatchSweep &S = A.sweeps[si];
@@ -1197,21 +1204,57 @@ __global__ __launch_bounds__(NT) void run_batched(BatchArgs A) {
         // the same 256 chunks at either group size
         const int L = dim >= kBlock ? dim / kBlock : 1;
         const int chunks = dim >= kBlock ? kBlock : dim;
-        double acc = 0.0;
-        if (int(threadIdx.x) < chunks) {
+        auto chunk_sum = [&](const float2 *p) {
+            double acc = 0.0;
             for (int i = 0; i < L; ++i) {
-                const float2 v = state[threadIdx.x * L + i];
+                const float2 v = p[threadIdx.x * L + i];
                 acc = fma(double(v.x), double(v.x), fma(double(v.y), double(v.y), acc));
             }
-        }
+            return acc;
+        };
+        double acc = 0.0;
+        if (int(threadIdx.x) < chunks) acc = res ? chunk_sum(sd) : chunk_sum(slot);
         if (int(threadIdx.x) < kBlock) part[threadIdx.x] = acc;
         __syncthreads();
-        if (threadIdx.x == 0) {
+        // inclusive prefix of the chunk sums by one wavefront: lane l sums
+        // chunks 4l..4l+3 in order, the lanes' totals are scanned across
+        // the wavefront, and chunk c's prefix is the lane's offset plus its
+        // own running sum (a fixed order, so every launch rounds alike),
+        // then made exactly non-decreasing by a running maximum (the two
+        // summation orders can differ by an ulp where lanes meet)
+        if (threadIdx.x < 64) {
+            const int l = int(threadIdx.x);
+            double p[4];
             double run = 0.0;
-            for (int c = 0; c < chunks; ++c) {
-                run += part[c];
-                part[c] = run;  // inclusive prefix
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                run += 4 * l + i < chunks ? part[4 * l + i] : 0.0;
+                p[i] = run;
             }
+            double t = run;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const double u = __shfl_up(t, o);
+                if (l >= o) t += u;
+            }
+            double off = __shfl_up(t, 1);
+            if (l == 0) off = 0.0;
+            double hi = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                p[i] = fmax(hi, off + p[i]);
+                hi = p[i];
+            }
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const double u = __shfl_up(hi, o);
+                if (l >= o) hi = fmax(hi, u);
+            }
+            double below = __shfl_up(hi, 1);
+            if (l == 0) below = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (4 * l + i < chunks) part[4 * l + i] = fmax(below, p[i]);
         }
         __syncthreads();
         const double N = part[chunks - 1];
@@ -1226,14 +1269,16 @@ __global__ __launch_bounds__(NT) void run_batched(BatchArgs A) {
             if (lo >= chunks) {
                 x = uint32_t(dim - 1);
             } else {
-                double run = lo > 0 ? part[lo - 1] : 0.0;
-                int pick = L - 1;
-                for (int i = 0; i < L; ++i) {
-                    const float2 v = state[lo * L + i];
-                    run += fma(double(v.x), double(v.x), double(v.y) * double(v.y));
-                    if (target < run) { pick = i; break; }
-                }
-                x = uint32_t(lo * L + pick);
+                auto within = [&](const float2 *p) {
+                    double run = lo > 0 ? part[lo - 1] : 0.0;
+                    for (int i = 0; i < L; ++i) {
+                        const float2 v = p[lo * L + i];
+                        run += fma(double(v.x), double(v.x), double(v.y) * double(v.y));
+                        if (target < run) return i;
+                    }
+                    return L - 1;
+                };
+                x = uint32_t(lo * L + (res ? within(sd) : within(slot)));
             }
             if (C.readout >= 0) {
                 const double *e0 = A.readout + C.readout;
