@@ -727,7 +727,7 @@ def other_workload(args, qs, W, torch) -> int:
                "config": {"workload": r["workload"]}, **{k: v for k, v in r.items() if k != "value"}}
     else:  # phase damping
         rows = []
-        for (r_, c_, n_traj, n_naive) in ((4, 5, 40, 4), (3, 9, 6, 1)):
+        for (r_, c_, n_traj, n_naive) in ((4, 5, 200, 4), (3, 9, 6, 1)):
             for lam in (1e-4, 1e-3, 1e-2, 1e-1):
                 circ = phase_damped_circuit(r_, c_, lam)
                 wl = W.TrajectoryWorkload(circ.name, circ, n_traj=n_traj, n_samples=1)

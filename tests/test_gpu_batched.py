@@ -150,3 +150,44 @@ def test_batched_without_recorded_choices(qs):
     for x, y in zip(a, b):
         assert "choices" not in y
         assert np.array_equal(x["samples"], y["samples"])
+
+
+def _wide_noisy(n, seed, p):
+    """Random gates on 1..5 unsorted targets, each followed by 1-qubit
+    depolarizing on its targets and, for 2-qubit gates, 2-qubit
+    depolarizing (16 Kraus operators) on the pair."""
+    from workloads.circuits import CHANNEL, Op, depolarize2
+    c = W.random_noisy_circuit(n, 24, seed, p_dep=p, gamma=0.0, max_k=5)
+    ops = []
+    for o in c.ops:
+        ops.append(o)
+        if o.kind != CHANNEL and o.k == 2:
+            ops.append(Op(CHANNEL, o.qubits, depolarize2(p), o.moment, "depolarize2"))
+    c.ops = ops
+    return c
+
+
+@pytest.mark.parametrize("f", [4, 5])
+def test_batched_patched_blocks_with_wide_gates_match_oracle(qs, orc, f):
+    """Blocks that hold a channel next to a 3- to 5-qubit gate with unsorted
+    targets (the generic re-fusion path for operations on 4 or 5 qubits)
+    and 2-qubit channels with 16 Kraus operators, on a resident and a tiled
+    circuit, against the oracle."""
+    items = []
+    for i, n in enumerate((11, 14)):
+        c = _wide_noisy(n, 40 + i, 0.25)
+        assert max(o.k for o in c.ops) >= 4
+        e0, e1 = W.readout_arrays(n, 0.01, 0.02)
+        items.append(TrajectoryWorkload(f"w{i}", c, n_traj=3, seed=11, circuit_id=i,
+                                        n_samples=16, e0=e0, e1=e1, max_fuse=f))
+    res, _ = qs.qs_run_batched(items, max_fuse=f)
+    for w, r in zip(items, res):
+        assert np.count_nonzero(r["choices"]) > 0
+        m = orc.Marshalled(w.circuit)
+        for t in range(w.n_traj):
+            ref = orc.run_trajectory(w.circuit, t, seed=w.seed, circ=w.circuit_id,
+                                     n_samples=w.n_samples, e0=w.e0, e1=w.e1, marshalled=m)
+            _, tie = compare_choices(r["choices"][t], ref)
+            assert tie == 0
+            mism = np.nonzero(r["samples"][t] != ref["samples"])[0]
+            assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE), (w.name, f, t, mism)
