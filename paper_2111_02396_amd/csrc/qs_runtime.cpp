@@ -2346,9 +2346,11 @@ namespace {
 // to trying values.  Here the driver tries them: for every candidate pair it
 // plans the circuit's default plan (each channel at its most likely pick) and
 // times one pass of it from |0...0> on the state's own stream, keeping the
-// fastest.  The choice is cached per (circuit, size, mode) for the life of
-// the process, so later calls, and the chunks of a concurrent call, run
-// the same plan.
+// fastest; where the channels' bounds predict two or more inner-product
+// channels per trajectory, it times the call's first trajectories instead,
+// host planning included.  The choice is cached per (circuit, size, mode)
+// for the life of the process, so later calls, and the chunks of a
+// concurrent call, run the same plan.
 struct TuneKey {
     uint64_t hash;
     int n, mode, f_req, tb_req;
@@ -2357,6 +2359,28 @@ struct TuneKey {
     }
 };
 constexpr double kTuneMargin = 0.03;  // a candidate must beat the default widths by 3 %
+// From this many expected inner-product channels per trajectory on, the
+// trials are whole trajectories timed on the host clock (the host's
+// per-split planning then weighs as much as the sweeps), with a wider margin
+// for their noisier timings.
+constexpr double kTuneSlowPaths = 2.0;
+constexpr double kTuneTrajMargin = 0.05;
+constexpr int64_t kTuneTrajectories = 4;
+
+// Expected channels per trajectory that need inner products: for each
+// channel that is not a mixture of unitaries, the chance that the draw lands
+// past the sum of its bounds (Algorithm 2 resolves every other draw from the
+// bounds alone).
+double expected_slow_paths(const CircuitModel &m) {
+    double e = 0.0;
+    for (const ChannelInfo &c : m.channels) {
+        if (c.mixture) continue;
+        double sum = 0.0;
+        for (double x : c.pbar) sum += x;
+        e += std::max(0.0, 1.0 - sum);
+    }
+    return e;
+}
 std::mutex g_tune_mu;  // one tuning at a time: concurrent trials would disturb each other's timings
 std::map<TuneKey, std::pair<int, int>> g_tune_cache;
 
@@ -2395,6 +2419,12 @@ qs_status resolve_widths(qs_state s, const CircuitModel &m, uint64_t chash, cons
         }
     } guard{ev};
     const int reps = m.n >= 29 ? 1 : 2;  // the first of two also warms caches
+    // circuits whose trajectories often need inner products are timed over
+    // the call's first few trajectories (the same draws for every
+    // candidate), after one untimed trajectory that loads each candidate's
+    // plan and kernels
+    const bool by_traj = expected_slow_paths(m) >= kTuneSlowPaths;
+    const int64_t nt = std::min<int64_t>(kTuneTrajectories, p.n_traj);
     double best = 1e300, t_default = -1.0;
     for (int f : fs) {
         for (int tb : tbs) {
@@ -2403,21 +2433,37 @@ qs_status resolve_widths(qs_state s, const CircuitModel &m, uint64_t chash, cons
             q.tile_bits = tb;
             q.flags = 0;
             q.n_samples = 0;
+            q.p0to1 = q.p1to0 = nullptr;
             qs_traj_result dummy;
             std::memset(&dummy, 0, sizeof(dummy));
-            Runner trial(s, m, q, dummy);
-            trial.chash = chash;
-            trial.tuning = true;
-            QS_CHECK(trial.plan_delayed());
             double t = 1e300;
-            for (int r = 0; r < reps; ++r) {
-                QS_HIP(s, hipEventRecord(ev[0], s->st));
-                QS_CHECK(trial.run_default_plan());
-                QS_HIP(s, hipEventRecord(ev[1], s->st));
-                QS_HIP(s, hipEventSynchronize(ev[1]));
-                float ms = 0.f;
-                QS_HIP(s, hipEventElapsedTime(&ms, ev[0], ev[1]));
-                t = std::min(t, double(ms));
+            if (by_traj) {
+                q.n_traj = 1;
+                q.traj_offset = p.traj_offset + nt < (int64_t(1) << 32) ? p.traj_offset + nt : p.traj_offset;
+                Runner warm(s, m, q, dummy);
+                warm.chash = chash;
+                QS_CHECK(warm.run());
+                q.n_traj = nt;
+                q.traj_offset = p.traj_offset;
+                Runner trial(s, m, q, dummy);
+                trial.chash = chash;
+                const auto ta = std::chrono::steady_clock::now();
+                QS_CHECK(trial.run());  // ends with a stream synchronisation
+                t = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now() - ta).count();
+            } else {
+                Runner trial(s, m, q, dummy);
+                trial.chash = chash;
+                trial.tuning = true;
+                QS_CHECK(trial.plan_delayed());
+                for (int r = 0; r < reps; ++r) {
+                    QS_HIP(s, hipEventRecord(ev[0], s->st));
+                    QS_CHECK(trial.run_default_plan());
+                    QS_HIP(s, hipEventRecord(ev[1], s->st));
+                    QS_HIP(s, hipEventSynchronize(ev[1]));
+                    float ms = 0.f;
+                    QS_HIP(s, hipEventElapsedTime(&ms, ev[0], ev[1]));
+                    t = std::min(t, double(ms));
+                }
             }
             if (f == kDefaultFuse && tb == (p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits))
                 t_default = t;
@@ -2430,7 +2476,8 @@ qs_status resolve_widths(qs_state s, const CircuitModel &m, uint64_t chash, cons
     }
     // the default widths stay unless another pair is clearly faster: trial
     // times of one pass differ by a percent or two from run to run
-    if (t_default > 0.0 && best > (1.0 - kTuneMargin) * t_default) {
+    const double margin = by_traj ? kTuneTrajMargin : kTuneMargin;
+    if (t_default > 0.0 && best > (1.0 - margin) * t_default) {
         *f_out = kDefaultFuse;
         *tb_out = p.tile_bits == 0 ? qs::kDefaultTileBits : p.tile_bits;
     }

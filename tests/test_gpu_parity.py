@@ -532,3 +532,33 @@ def test_driver_two_qubit_channel_and_fused_reduced_density_matrix(qs, orc):
         mism = np.nonzero(got["samples"][0] != ref["samples"])[0]
         assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
     assert slow >= 6
+
+
+def test_autotuner_times_trajectories_when_inner_products_are_frequent(qs, orc):
+    """Amplitude damping at gamma = 0.2 on a 16-qubit grid predicts about 19
+    inner-product channels per trajectory, so the autotuner times whole
+    trajectories (host planning included) instead of one default pass.  The
+    tuned call equals a call with the chosen widths fixed, and matches the
+    oracle."""
+    c = W.grid_circuit(4, 4, 6, p_dep=0.02, gamma=0.2, seed=9)
+    e0, e1 = W.readout_arrays(16, 0.01, 0.02)
+    kw = dict(seed=4, mode=0, n_samples=20, p0to1=e0, p1to0=e1, traj_offset=7)
+    with qs.State(16) as st:
+        tuned = qs.qs_run_trajectories(st.h, c, 6, max_fuse=0, tile_bits=0, **kw)
+        assert tuned["tune_ms"] > 0.0
+        assert tuned["n_slow"].mean() > 5
+        f, tb = tuned["max_fuse_used"], tuned["tile_bits_used"]
+        fixed = qs.qs_run_trajectories(st.h, c, 6, max_fuse=f, tile_bits=tb, **kw)
+    assert np.array_equal(tuned["choices"], fixed["choices"])
+    assert np.array_equal(tuned["samples"], fixed["samples"])
+    m = orc.Marshalled(c)
+    ties = 0
+    for t in range(3):
+        ref = orc.run_trajectory(c, 7 + t, seed=4, n_samples=20, e0=e0, e1=e1, marshalled=m)
+        _, tie = compare_choices(tuned["choices"][t], ref)
+        ties += tie
+        if tie:
+            continue
+        mism = np.nonzero(tuned["samples"][t] != ref["samples"])[0]
+        assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE)
+    assert ties <= 1
