@@ -538,6 +538,12 @@ def main() -> int:
         "compute": sw["compute"],
         "binding_floor": sw["bound"],
     }
+    copy_ref = copy_reference(qs, torch)
+    roofline["copy_reference"] = copy_ref
+    roofline["frac_of_copy"] = sw["hbm"]["achieved"] / copy_ref["24q" if n <= 24 else "28q"]["GB_per_s"]
+    roofline["copy_basis"] = ("achieved / the GB/s of qs_copy_state on a state of the same size "
+                              "class (24q: cache-resident 128 MiB buffers; 28q: HBM-resident 2 GiB)")
+    log(f"copy reference: {json.dumps(copy_ref)}")
 
     w = W.grid24_workload(p_dep=args.p_dep, rows=args.rows, cols=args.cols)
     single = one_state_rate(qs, W, torch, w, min(args.traj, 500), qs.QS_KRAUS_DELAYED,
@@ -577,6 +583,8 @@ def main() -> int:
             log(f"noisy grid at {nq} qubits")
             r = run_grid(qs, W, args, torch, n_traj=nt, steps=1, warmup=1, streams=args.streams,
                          workload=W.noisy_grid_workload(nq, n_traj=nt))
+            if nq >= 28:
+                r["sweep"]["hbm"]["frac_of_copy"] = r["sweep"]["hbm"]["achieved"] / copy_ref["28q"]["GB_per_s"]
             extras["larger_states"].append(
                 {"qubits": nq, "workload": r["workload"], "value": r["value"], "unit": r["unit"],
                  "max_fuse": r["max_fuse"], "tile_bits": r["tile_bits"], "sweep": r["sweep"]})
@@ -597,6 +605,8 @@ def main() -> int:
         extras["grid20"] = small
         log("grid28 (noiseless, f <= 4)")
         extras["grid28"] = sub_grid28(qs, W, torch)
+        g28 = extras["grid28"]["sweep"]["hbm"]
+        g28["frac_of_copy"] = g28["achieved"] / copy_ref["28q"]["GB_per_s"]
         extras["grid28_autotuned"] = {k: v for k, v in sub_grid28(qs, W, torch, max_fuse=0).items()
                                       if k in ("value", "unit", "ms_per_state", "max_fuse",
                                                "tile_bits", "tune_ms", "sweeps_per_state")}
@@ -656,6 +666,40 @@ def main() -> int:
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def copy_reference(qs, torch, qubit_sizes=(24, 28)):
+    """Achievable bandwidth of a plain state copy (qs_copy_state: one read and
+    one write of the state, like a sweep, with 16-byte accesses): at 24
+    qubits the two 128 MiB states sit in the Infinity Cache, at 28 qubits (2
+    GiB each) they do not.  torch's own device copy is timed beside it.
+    Events on the default stream, outside the timed region."""
+    out = {}
+    for q in qubit_sizes:
+        reps = 20 if q <= 24 else 5
+        nbytes = 2 * (8 << q)
+
+        def timed(fn):
+            for _ in range(3):
+                fn()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            e1.synchronize()
+            return nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+        with qs.State(q) as a, qs.State(q) as b:
+            gbps = timed(lambda: qs.qs_copy_state(b.h, a.h))
+        x = torch.zeros(1 << q, dtype=torch.complex64, device="cuda")
+        y = torch.empty_like(x)
+        tgbps = timed(lambda: y.copy_(x))
+        del x, y
+        torch.cuda.empty_cache()
+        out[f"{q}q"] = {"bytes_per_copy": nbytes, "GB_per_s": gbps, "torch_copy_GB_per_s": tgbps}
+    return out
 
 
 # ------------------------------------------------------------------ standalone lines

@@ -188,6 +188,15 @@ qs_status qs_copy_state_to_host(qs_state s, void *host_out, size_t bytes);
 /* Replace the amplitudes with host complex64 data (8*2^n bytes; drops pending ops). */
 qs_status qs_load_state_from_host(qs_state s, const void *host_in, size_t bytes);
 
+/* Copy the amplitudes of `src` into `dst` on the device (one read and one
+ * write of 8*2^n bytes, 16-byte accesses).  src's pending operations are
+ * applied first; dst's are dropped.  The copy runs on dst's stream after the
+ * work already enqueued on src's stream, and later work on src's stream waits
+ * for it.  Both handles keep their own buffers (dst == src is a no-op).
+ * Errors: INVALID_ARGUMENT (null handle, different qubit counts),
+ * NOT_SUPPORTED (states on different devices), DEVICE. */
+qs_status qs_copy_state(qs_state dst, qs_state src);
+
 /* ---- the hot path ------------------------------------------------------- */
 
 /* Apply one (already fused) k-qubit matrix to the state: Section 3.1,

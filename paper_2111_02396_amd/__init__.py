@@ -119,6 +119,7 @@ def load():
         "qs_flush": [vp],
         "qs_copy_state_to_host": [vp, vp, ctypes.c_size_t],
         "qs_load_state_from_host": [vp, vp, ctypes.c_size_t],
+        "qs_copy_state": [vp, vp],
         "qs_apply_fused_gate": [vp, i32, vp, vp],
         "qs_apply_channel": [vp, i32, vp, i32, vp, u64, u32, u32, i32, vp, vp],
         "qs_norm": [vp, vp],
@@ -203,6 +204,10 @@ def qs_copy_state_to_host(s) -> np.ndarray:
 def qs_load_state_from_host(s, amps) -> None:
     a = np.ascontiguousarray(np.asarray(amps, dtype=np.complex64))
     _check(load().qs_load_state_from_host(s, _p(a), a.nbytes))
+
+
+def qs_copy_state(dst, src) -> None:
+    _check(load().qs_copy_state(dst, src))
 
 
 def qs_apply_fused_gate(s, targets, matrix) -> None:

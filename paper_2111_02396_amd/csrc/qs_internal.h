@@ -194,6 +194,9 @@ hipError_t launch_set_basis(float2 *amp, int n, uint64_t index, hipStream_t st);
 
 hipError_t launch_scale(float2 *amp, int n, float s, hipStream_t st);
 
+// dst[i] = src[i] for the 2^n amplitudes (16-byte accesses, grid-stride).
+hipError_t launch_copy_state(float2 *dst, const float2 *src, int n, hipStream_t st);
+
 // Algorithm 1 for one fused gate.  mat_dev: device copy of g.m
 // ((2^k)^2 complex64, ascending-target order).  Gates with a target below 6
 // go through the tiled path, the others through the direct path.

@@ -1305,6 +1305,15 @@ __global__ __launch_bounds__(kBlock) void set_basis(float2 *__restrict__ amp, Id
         amp[i] = make_float2(i == index ? 1.f : 0.f, 0.f);
 }
 
+// A state copy: pairs of amplitudes as 16-byte loads and stores, over a
+// grid of four 256-work-item groups per CU (the shape that copied a 2 GiB
+// state fastest in a sweep of grids and unrolling).
+__global__ __launch_bounds__(kBlock) void copy_pairs(float4 *__restrict__ dst, const float4 *__restrict__ src,
+                                                     int64_t pairs) {
+    const int64_t stride = int64_t(gridDim.x) * kBlock;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < pairs; i += stride) dst[i] = src[i];
+}
+
 template <typename Idx>
 __global__ __launch_bounds__(kBlock) void scale_state(float2 *__restrict__ amp, Idx dim, float s) {
     const Idx stride = Idx(gridDim.x) * Idx(kBlock);
@@ -1942,6 +1951,17 @@ hipError_t launch_set_basis(float2 *amp, int n, uint64_t index, hipStream_t st) 
         set_basis<uint32_t><<<grid, kBlock, 0, st>>>(amp, uint32_t(dim), uint32_t(index));
     else
         set_basis<uint64_t><<<grid, kBlock, 0, st>>>(amp, dim, index);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_state(float2 *dst, const float2 *src, int n, hipStream_t st) {
+    if (n < 1 || n > kMaxQubits || !dst || !src) return hipErrorInvalidValue;
+    const int64_t pairs = int64_t(1) << (n - 1);
+    const int64_t want = (pairs + kBlock - 1) / kBlock;
+    const int64_t cap = int64_t(device_cus()) * 4;
+    const unsigned grid = unsigned(want < cap ? want : cap);
+    copy_pairs<<<grid, kBlock, 0, st>>>(reinterpret_cast<float4 *>(dst), reinterpret_cast<const float4 *>(src),
+                                        pairs);
     return hipGetLastError();
 }
 

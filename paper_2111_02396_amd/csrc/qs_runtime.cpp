@@ -492,7 +492,7 @@ qs_status naive_channel(qs_state s, const ChannelInfo &c, double r, int *pick_ou
 
 qs_status restore_home(qs_state s) {
     if (s->amp == s->home) return QS_OK;
-    QS_HIP(s, hipMemcpyAsync(s->home, s->amp, sizeof(float2) << s->n, hipMemcpyDeviceToDevice, s->st));
+    QS_HIP(s, qs::launch_copy_state(s->home, s->amp, s->n, s->st));
     s->scratch = s->amp;
     s->amp = s->home;
     return QS_OK;
@@ -655,6 +655,38 @@ qs_status qs_load_state_from_host(qs_state s, const void *host_in, size_t bytes)
     QS_CHECK(restore_home(s));
     QS_HIP(s, hipStreamSynchronize(s->st));
     QS_HIP(s, hipMemcpy(s->amp, host_in, need, hipMemcpyHostToDevice));
+    return QS_OK;
+}
+
+qs_status qs_copy_state(qs_state dst, qs_state src) {
+    QS_CHECK(check_handle(dst));
+    QS_CHECK(check_handle(src));
+    if (dst == src) return QS_OK;
+    if (dst->n != src->n) return fail(QS_ERR_INVALID_ARGUMENT, "states differ in qubit count");
+    if (dst->device != src->device) return fail(QS_ERR_NOT_SUPPORTED, "states on different devices");
+    QS_CHECK(flush_pending(src));
+    dst->pending.clear();
+    QS_CHECK(restore_home(dst));
+    hipEvent_t ready = nullptr, done = nullptr;
+    struct EvGuard {
+        hipEvent_t *a, *b;
+        ~EvGuard() {
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
+        }
+    } guard{&ready, &done};
+    const bool two = src->st != dst->st;
+    if (two) {
+        QS_HIP(dst, hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        QS_HIP(dst, hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        QS_HIP(src, hipEventRecord(ready, src->st));
+        QS_HIP(dst, hipStreamWaitEvent(dst->st, ready, 0));
+    }
+    QS_HIP(dst, qs::launch_copy_state(dst->amp, src->amp, dst->n, dst->st));
+    if (two) {
+        QS_HIP(dst, hipEventRecord(done, dst->st));
+        QS_HIP(src, hipStreamWaitEvent(src->st, done, 0));
+    }
     return QS_OK;
 }
 

@@ -108,3 +108,28 @@ def test_state_after_run_is_last_trajectory(qs, mode):
         # and with no trajectories the state is left as it was
         r0 = qs.qs_run_trajectories(st.h, c, 0, seed=4, mode=mode)
         assert np.array_equal(qs.qs_copy_state_to_host(st.h), after)
+
+
+@pytest.mark.parametrize("n", [1, 9, 20])
+def test_copy_state_between_streams(qs, n):
+    """qs_copy_state copies every amplitude bit for bit, from a state on one
+    stream to a state on another, after the source's pending gate, and drops
+    the destination's pending work; mismatched sizes are refused."""
+    rng = np.random.default_rng(n)
+    amps = (rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)).astype(np.complex64)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with qs.State(n, hip_stream=s1.cuda_stream) as a, qs.State(n, hip_stream=s2.cuda_stream) as b:
+        qs.qs_load_state_from_host(a.h, amps)
+        h = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2)
+        qs.qs_apply_fused_gate(a.h, [0], h)
+        qs.qs_apply_fused_gate(b.h, [0], h)
+        qs.qs_copy_state(b.h, a.h)
+        got = qs.qs_copy_state_to_host(b.h)
+        want = qs.qs_copy_state_to_host(a.h)
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+        qs.qs_copy_state(a.h, a.h)
+        assert np.array_equal(qs.qs_copy_state_to_host(a.h).view(np.uint64), want.view(np.uint64))
+    with qs.State(n) as a, qs.State(n + 1) as b:
+        with pytest.raises(qs.QsError) as e:
+            qs.qs_copy_state(b.h, a.h)
+        assert e.value.code == qs.QS_ERR_INVALID_ARGUMENT

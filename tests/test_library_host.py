@@ -57,6 +57,9 @@ def test_validation_before_device_work(lib):
     with pytest.raises(lib.QsError):
         lib.qs_destroy_state(None)
     assert "null" in lib.qs_last_error_message()
+    with pytest.raises(lib.QsError) as e:
+        lib.qs_copy_state(None, None)
+    assert e.value.code == lib.QS_ERR_INVALID_ARGUMENT
 
 
 def test_philox_matches_oracle(lib, orc):
