@@ -226,6 +226,31 @@ def one_state_rate(qs, W, torch, w, n_traj, mode, max_fuse=0, tile_bits=0, warm=
             "tile_bits": r["tile_bits_used"], "graph_replays": r["graph_replays"]}
 
 
+def states_rate(qs, torch, w, n_traj, n_states, mode, max_fuse=0, tile_bits=0):
+    """Trajectories/s of n_states states on their own streams, the range split
+    over them (qs_run_trajectories_concurrent); one untimed warm-up call."""
+    c = w.circuit
+    mc = qs.MarshalledCircuit(c)
+    streams = [torch.cuda.Stream() for _ in range(n_states)]
+    states = [qs.State(c.n, hip_stream=st.cuda_stream) for st in streams]
+    try:
+        hs = [st.h for st in states]
+        kw = dict(seed=w.seed, mode=mode, max_fuse=max_fuse, tile_bits=tile_bits,
+                  n_samples=w.n_samples, p0to1=w.e0, p1to0=w.e1, record_choices=False, marshalled=mc)
+        qs.qs_run_trajectories(hs, c, 2 * n_states, traj_offset=50_000_000, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = qs.qs_run_trajectories(hs, c, n_traj, traj_offset=60_000_000, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        for st in states:
+            st.close()
+    return {"value": n_traj / dt, "unit": "trajectories/s", "trajectories": n_traj, "states": n_states,
+            "sweeps_per_traj": r["sweeps"] / n_traj, "max_fuse": r["max_fuse_used"],
+            "tile_bits": r["tile_bits_used"]}
+
+
 def cpu_info():
     model = None
     try:
@@ -777,8 +802,10 @@ def other_workload(args, qs, W, torch) -> int:
                 wl = W.TrajectoryWorkload(circ.name, circ, n_traj=n_traj, n_samples=1)
                 d = one_state_rate(qs, W, torch, wl, n_traj, qs.QS_KRAUS_DELAYED, 0, 0)
                 nv = one_state_rate(qs, W, torch, wl, n_naive, qs.QS_KRAUS_NAIVE, 4, 0, warm=0)
+                d4 = states_rate(qs, torch, wl, 2 * n_traj, 4, qs.QS_KRAUS_DELAYED)
                 row = {"qubits": r_ * c_, "lambda": lam, "delayed_traj_per_s": d["value"],
                        "naive_traj_per_s": nv["value"], "speedup": d["value"] / nv["value"],
+                       "delayed_4_states_traj_per_s": d4["value"],
                        "max_fuse": d["max_fuse"], "tile_bits": d["tile_bits"]}
                 log(json.dumps(row))
                 rows.append(row)

@@ -1244,7 +1244,15 @@ int plan_restarts(int n, int64_t n_traj) {
     const double w = std::ldexp(double(std::max<int64_t>(n_traj, 1)), n - 20);
     return int(std::min(4096.0, std::max(64.0, w)));
 }
-int segment_restarts(int n) { return n >= 24 ? 64 : n >= 20 ? 16 : 4; }
+// Below 24 qubits a sweep costs a few microseconds, about as much as a
+// dozen restarts on a segment's blocks, and a segment with fewer than 16
+// blocks (noisy circuits split into many) seldom groups better than the
+// searched greedy grouping: it gets no restarts.
+int segment_restarts(int n, size_t blocks) {
+    if (n >= 24) return 64;
+    if (blocks < 16) return 0;
+    return n >= 20 ? 16 : 4;
+}
 constexpr uint64_t kGroupSeed = 0x243f6a8885a308d3ull;
 
 struct SegKey {
@@ -1670,7 +1678,7 @@ struct Runner {
         } else if (T >= 10 && m.n >= qs::kTileMinQubits) {
             sw = qs::group_sweeps_best(m.n, rb, std::min(T, m.n), qs::kTileLowBits, qs::kMaxTileGates,
                                        qs::tile_mat_budget(std::min(T, m.n)), tile_slots(),
-                                       segment_restarts(m.n), kGroupSeed);
+                                       segment_restarts(m.n, rb.size()), kGroupSeed);
             if (chash) segment_insert(skey, sw);
         } else {
             for (size_t b = 0; b < rb.size(); ++b) {
