@@ -333,7 +333,7 @@ def sub_chain12(qs, W, torch, steps=20):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        _, stats = qs.qs_run_batched(prepared, time_kernels=True)
+        _, stats = qs.qs_run_batched(prepared, time_kernels=True, copy=False)
     dt = time.perf_counter() - t0
     mc = qs.MarshalledCircuit(w.circuit)
     with qs.State(w.circuit.n) as st:
@@ -398,14 +398,14 @@ def sub_batched(qs, W, torch, steps=2):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        _, stats = qs.qs_run_batched(prepared, time_kernels=True)
+        _, stats = qs.qs_run_batched(prepared, time_kernels=True, copy=False)
     dt = time.perf_counter() - t0
     value = steps * n_traj / dt
     fixed = {}
     for f in (3,):
         qs.qs_run_batched(prepared, max_fuse=f)
         t1 = time.perf_counter()
-        _, st3 = qs.qs_run_batched(prepared, max_fuse=f, time_kernels=True)
+        _, st3 = qs.qs_run_batched(prepared, max_fuse=f, time_kernels=True, copy=False)
         fixed[f"max_fuse_{f}"] = {"value": n_traj / (time.perf_counter() - t1),
                                   "kernel_ms": st3["kernel_ms"]}
     sample = items[::16]

@@ -342,7 +342,9 @@ typedef struct {
     int32_t n_samples;         /* per trajectory, 0..4096 */
     const double *p0to1;       /* per-qubit readout P(1|0), host, or NULL */
     const double *p1to0;       /* per-qubit readout P(0|1), host, or NULL */
-    uint64_t *bitstrings;      /* host out [n_traj * n_samples] */
+    uint64_t *bitstrings;      /* host out [n_traj * n_samples]; pinned host memory
+                                  (hipHostMalloc) receives 16384 or more samples with one
+                                  transfer and no staging copy */
     int8_t *kraus_choices;     /* host out [n_traj * n_channels], or NULL */
 } qs_batch_item;
 

@@ -11,7 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Dict, Optional
+from typing import Dict, Optional, Tuple
 
 import numpy as np
 
@@ -380,10 +380,27 @@ def qs_run_trajectories(s, circuit, n_traj: int, seed: int = 0, traj_offset: int
     return out
 
 
+def _sample_buffer(n: int) -> Tuple[np.ndarray, object]:
+    """A uint64 host array for n samples: pinned (page-locked) memory when a
+    GPU is present, so that the library can transfer large sample sets into
+    it directly, else ordinary memory.  Returns the array and its owner."""
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            t = torch.empty(max(n, 1), dtype=torch.int64, pin_memory=True)
+            return t.numpy().view(np.uint64), t
+    except (ImportError, RuntimeError):
+        pass
+    a = np.zeros(max(n, 1), dtype=np.uint64)
+    return a, a
+
+
 class PreparedBatch:
     """Workloads marshalled once for repeated qs_run_batched calls.  Each
     workload carries circuit, n_traj, seed, circuit_id, n_samples, e0, e1 and
-    optionally traj_offset."""
+    optionally traj_offset.  Sample buffers are pinned host memory when a GPU
+    is present."""
 
     def __init__(self, workloads, record_choices: bool = True):
         self.keep = []
@@ -394,7 +411,8 @@ class PreparedBatch:
             mc = MarshalledCircuit(w.circuit)
             e0 = None if w.e0 is None else np.ascontiguousarray(w.e0, dtype=np.float64)
             e1 = None if w.e1 is None else np.ascontiguousarray(w.e1, dtype=np.float64)
-            bits = np.zeros(max(w.n_traj * w.n_samples, 1), dtype=np.uint64)
+            bits, owner = _sample_buffer(w.n_traj * w.n_samples)
+            self.keep.append(owner)
             ch = np.zeros(max(w.n_traj * mc.n_channels, 1), dtype=np.int8) if record_choices else None
             self.keep += [mc, e0, e1, bits, ch]
             it = self.items[i]
@@ -411,19 +429,22 @@ class PreparedBatch:
 
 
 def qs_run_batched(workloads, max_fuse: int = 0, hip_stream: Optional[int] = None,
-                   time_kernels: bool = False, record_choices: bool = True):
+                   time_kernels: bool = False, record_choices: bool = True, copy: bool = True):
     """Run workloads (or a PreparedBatch) in one persistent launch; returns
-    per-workload {"samples", "choices"} and launch statistics."""
+    per-workload {"samples", "choices"} and launch statistics.  With
+    copy=False the arrays are views of a PreparedBatch's own buffers, valid
+    until its next call."""
     pb = workloads if isinstance(workloads, PreparedBatch) else PreparedBatch(workloads,
                                                                               record_choices)
     params = QsBatchParams(max_fuse, QS_TRAJ_TIME_KERNELS if time_kernels else 0, hip_stream)
     res = QsBatchResult()
     _check(load().qs_run_batched(pb.items, pb.n, ctypes.byref(params), ctypes.byref(res)))
     results = []
+    own = (lambda a: a.copy()) if copy else (lambda a: a)
     for bits, ch, nch, n_traj, n_samples in pb.outs:
-        d = {"samples": bits[:n_traj * n_samples].reshape(n_traj, n_samples).copy()}
+        d = {"samples": own(bits[:n_traj * n_samples].reshape(n_traj, n_samples))}
         if ch is not None:
-            d["choices"] = ch[:n_traj * nch].reshape(n_traj, nch).copy()
+            d["choices"] = own(ch[:n_traj * nch].reshape(n_traj, nch))
         results.append(d)
     stats = {"jobs": res.jobs, "resident_jobs": res.resident_jobs, "gate_blocks": res.gate_blocks,
              "host_seconds": res.host_seconds, "plan_seconds": res.plan_seconds,

@@ -3088,6 +3088,24 @@ qs_status plan_batched_circuit(const CircuitModel &m, const std::vector<const cd
 
 namespace {
 
+// Items with at least this many samples take them straight into the caller's
+// buffer when it is pinned host memory (smaller ones are not worth a
+// transfer of their own).
+constexpr int64_t kDirectSamples = int64_t(1) << 14;
+
+// Whether a host pointer lies in pinned (page-locked, device-visible) host
+// memory.  Pageable memory makes the query fail; its error is cleared.
+bool pinned_host(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    std::memset(&a, 0, sizeof(a));
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
+}
+
 qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_batch_params *bp,
                            int f, qs_batch_result *r) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -3373,6 +3391,10 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
     }
     const auto t_plan = std::chrono::steady_clock::now();
     r->plan_seconds = std::chrono::duration<double>(t_plan - t0).count();
+    std::vector<char> direct(size_t(n_items), 0);
+    for (int it = 0; it < n_items; ++it)
+        direct[size_t(it)] = items[it].n_traj * int64_t(items[it].n_samples) >= kDirectSamples &&
+                             pinned_host(items[it].bitstrings);
     qs_status status = QS_OK;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     do {
@@ -3403,9 +3425,25 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
         }
         if ((e = qs::launch_batched(A, std::min<int64_t>(grid, int64_t(jobs.size())), st)) != hipSuccess) break;
         if (timing && (e = hipEventRecord(ev1, st)) != hipSuccess) break;
-        // samples and picks come back into the pinned staging (its program
-        // part has been sent)
-        if (total_samples > 0 &&
+        // samples come straight into a caller's buffer that is pinned host
+        // memory (one transfer, no staging copy) when the item has many;
+        // the rest, and the picks, into the pinned staging (its program part
+        // has been sent)
+        bool staged = false;
+        {
+            int64_t ob = 0;
+            for (int it = 0; it < n_items && e == hipSuccess; ++it) {
+                const int64_t cnt = items[it].n_traj * int64_t(items[it].n_samples);
+                if (cnt > 0 && direct[size_t(it)])
+                    e = hipMemcpyAsync(items[it].bitstrings, dbuf + o_out + sizeof(uint64_t) * size_t(ob),
+                                       sizeof(uint64_t) * size_t(cnt), hipMemcpyDeviceToHost, st);
+                else if (cnt > 0)
+                    staged = true;
+                ob += cnt;
+            }
+            if (e != hipSuccess) break;
+        }
+        if (staged &&
             (e = hipMemcpyAsync(hostp + o_out, dbuf + o_out, sizeof(uint64_t) * size_t(total_samples),
                                 hipMemcpyDeviceToHost, st)) != hipSuccess)
             break;
@@ -3432,7 +3470,8 @@ qs_status run_batched_impl(const qs_batch_item *items, int n_items, const qs_bat
         int64_t ob = 0, cb = 0;
         for (int it = 0; it < n_items; ++it) {
             const int64_t cnt = items[it].n_traj * int64_t(items[it].n_samples);
-            if (cnt > 0) std::memcpy(items[it].bitstrings, out + ob, sizeof(uint64_t) * size_t(cnt));
+            if (cnt > 0 && !direct[size_t(it)])
+                std::memcpy(items[it].bitstrings, out + ob, sizeof(uint64_t) * size_t(cnt));
             ob += cnt;
             if (items[it].kraus_choices) {
                 const int64_t nc = items[it].n_traj * int64_t(plans[it].plan->chans.size());

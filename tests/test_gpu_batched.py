@@ -191,3 +191,22 @@ def test_batched_patched_blocks_with_wide_gates_match_oracle(qs, orc, f):
             assert tie == 0
             mism = np.nonzero(r["samples"][t] != ref["samples"])[0]
             assert np.all(ref["sample_margins"][mism] < SAMPLE_TIE), (w.name, f, t, mism)
+
+
+def test_batched_samples_into_pinned_and_pageable_buffers(qs, monkeypatch):
+    """An item with 16384 or more samples lands straight in a pinned caller
+    buffer; pageable buffers go through the library's staging.  Both give
+    the same samples, and views of a prepared batch's buffers hold the
+    latest call's results."""
+    items = _items([(12, 8, 0.02, 40, 1000), (11, 6, 0.02, 3, 20)])
+    pinned = qs.PreparedBatch(items)
+    a, _ = qs.qs_run_batched(pinned)
+    v, _ = qs.qs_run_batched(pinned, copy=False)
+    monkeypatch.setattr(qs, "_sample_buffer",
+                        lambda n: (lambda x: (x, x))(np.zeros(max(n, 1), dtype=np.uint64)))
+    pageable = qs.PreparedBatch(items)
+    b, _ = qs.qs_run_batched(pageable)
+    for x, y, z in zip(a, b, v):
+        assert np.array_equal(x["samples"], y["samples"])
+        assert np.array_equal(x["samples"], z["samples"])
+        assert np.array_equal(x["choices"], y["choices"])
