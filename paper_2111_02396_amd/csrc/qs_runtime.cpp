@@ -1324,6 +1324,7 @@ struct Runner {
     // naive mode: gate blocks per inter-channel segment
     std::vector<std::vector<BlockDesc>> naive_segments;
     std::vector<cd> tmp;
+    std::vector<int> rest_ops;  // a slow block's operations after its channel
     std::deque<std::vector<cd>> slow_mats;
     qs::ReadoutDesc ro;
     double log_norm_bound = 0.0;
@@ -2191,15 +2192,42 @@ struct Runner {
                         const float2 *dc = nullptr;
                         QS_CHECK(arena_stage(s, cand_f2, &hc, &dc));
                         double *hcd = reinterpret_cast<double *>(hc);
+                        // candidate i = (the block's later operations, fused
+                        // once) x K_i on the channel's qubits: the block begins
+                        // with the channel, so each candidate costs 2 Db^2 Dc
+                        // multiply-adds instead of a fusion of its own
                         tmp.resize(size_t(Db) * Db);  // fused_matrix writes Db x Db entries
+                        rest_ops.assign(sub.begin() + 1, sub.end());
+                        qs::fused_matrix(kb, q, rest_ops, m.ops, mats, tmp.data());
+                        int cpos[2] = {0, 0};
+                        int cmask = 0;
+                        for (int j = 0; j < ci.k; ++j) {
+                            cpos[j] = int(std::find(q, q + kb, ci.t[j]) - q);
+                            cmask |= 1 << cpos[j];
+                        }
+                        auto spread = [&](int jx) {
+                            int x = 0;
+                            for (int j = 0; j < ci.k; ++j)
+                                if ((jx >> j) & 1) x |= 1 << cpos[j];
+                            return x;
+                        };
                         for (int i = 0; i < ci.nk; ++i) {
-                            mats[sel.op] = ci.kraus + size_t(i) * Dc * Dc;
-                            qs::fused_matrix(kb, q, sub, m.ops, mats, tmp.data());
-                            for (int e2 = 0; e2 < Db * Db; ++e2) {
-                                hcd[2 * (size_t(i) * Db * Db + e2)] = tmp[e2].real();
-                                hcd[2 * (size_t(i) * Db * Db + e2) + 1] = tmp[e2].imag();
+                            const cd *K = ci.kraus + size_t(i) * Dc * Dc;
+                            double *out = hcd + 2 * size_t(i) * Db * Db;
+                            for (int c = 0; c < Db; ++c) {
+                                int jc = 0;
+                                for (int j = 0; j < ci.k; ++j) jc |= ((c >> cpos[j]) & 1) << j;
+                                const int base = c & ~cmask;
+                                for (int r = 0; r < Db; ++r) {
+                                    cd acc = 0.0;
+                                    for (int jx = 0; jx < Dc; ++jx)
+                                        acc += tmp[size_t(r) * Db + (base | spread(jx))] * K[jx * Dc + jc];
+                                    out[2 * (size_t(r) * Db + c)] = acc.real();
+                                    out[2 * (size_t(r) * Db + c) + 1] = acc.imag();
+                                }
                             }
                         }
+                        mats[sel.op] = ci.kraus + size_t(ci.nk - 1) * Dc * Dc;
                         bd.g.k = kb;
                         for (int b2 = 0; b2 < 5; ++b2) bd.g.t[b2] = b2 < kb ? q[b2] : 0;
                         bd.identity = false;
